@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU library.
+
+This module holds data only -- geometry planes, material constants, run
+configuration values and seeded primary generators.  It contains none of the
+transport arithmetic, so both sides of every parity test can take their
+inputs from here without sharing any of the method.
+
+The calorimeter is the paper's validation set-up (section 2.2, "Physics
+integration and validation": 50 layers, each an absorber slab of 2.3 mm and a
+liquid-argon slab of 5.7 mm), with lead as the absorber instead of lead
+tungstate, 40 x 40 cm transverse.  Primaries use numpy's Philox bit generator
+so every workload is reproducible from its seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Species codes (gamma, electron, positron), shared by both C interfaces.
+GAMMA, ELECTRON, POSITRON = 0, 1, 2
+
+# Process-mask bits (same meaning on both sides).
+P_COMPTON, P_PHOT, P_CONV, P_EIONI, P_EBREM, P_ANNIH, P_CONT = (1 << i for i in range(7))
+P_ALL = 0x7F
+
+# Materials: (Z, A [g/mol], density [g/cm3], mean excitation energy I [eV]).
+# Z and density of lead and liquid argon as in the workload definition;
+# A and I are the PDG values.
+LEAD = (82.0, 207.2, 11.35, 823.0)
+LIQUID_ARGON = (18.0, 39.948, 1.396, 188.0)
+
+# One primary record: 64 bytes, the layout both C interfaces declare.
+PRIMARY_DTYPE = np.dtype(
+    [("event", "<u4"), ("species", "<u4"), ("ekin", "<f8"), ("pos", "<f8", (3,)), ("dir", "<f8", (3,))],
+    align=True,
+)
+assert PRIMARY_DTYPE.itemsize == 64
+
+
+@dataclasses.dataclass
+class Geometry:
+    z_mm: np.ndarray          # n_slabs + 1 planes
+    material: np.ndarray      # n_slabs indices (uint32)
+    materials: list           # list of (Z, A, rho, I)
+    half_xy_mm: float
+
+    @property
+    def n_slabs(self) -> int:
+        return int(self.material.shape[0])
+
+
+def calorimeter(n_layers: int = 50, absorber_mm: float = 2.3, gap_mm: float = 5.7,
+                half_xy_mm: float = 200.0, absorber=LEAD, gap=LIQUID_ARGON) -> Geometry:
+    """Layered sampling calorimeter: slab 2l is absorber, slab 2l+1 is gap."""
+    widths = np.tile(np.array([absorber_mm, gap_mm]), n_layers)
+    z = np.concatenate([[0.0], np.cumsum(widths)])
+    mat = np.tile(np.array([0, 1], dtype=np.uint32), n_layers)
+    return Geometry(z_mm=z.astype(np.float64), material=mat, materials=[absorber, gap],
+                    half_xy_mm=float(half_xy_mm))
+
+
+def single_slab(thickness_mm: float, material=LEAD, half_xy_mm: float = 200.0) -> Geometry:
+    return Geometry(z_mm=np.array([0.0, thickness_mm]), material=np.zeros(1, np.uint32),
+                    materials=[material], half_xy_mm=float(half_xy_mm))
+
+
+@dataclasses.dataclass
+class RunConfig:
+    """Physics and stepping configuration (values only)."""
+    bz_tesla: float = 0.0
+    gamma_cut_MeV: float = 0.1
+    electron_cut_MeV: float = 0.2
+    n_bins: int = 200
+    emin_MeV: float = 1e-3
+    emax_MeV: float = 1e8
+    dr_over_range: float = 0.2
+    final_range_mm: float = 1.0
+    lin_loss_limit: float = 0.01
+    process_mask: int = P_ALL
+    max_steps_per_track: int = 100000
+    seed: int = 1
+
+
+def primaries(n: int) -> np.ndarray:
+    return np.zeros(n, dtype=PRIMARY_DTYPE)
+
+
+def beam(n_events: int, species: int, ekin_MeV: float, smear_rad: float = 0.0,
+         seed: int = 0) -> np.ndarray:
+    """One primary per event at the origin along +z, optional Gaussian
+    angular smear of the x and y slopes (independent, sigma = smear_rad)."""
+    p = primaries(n_events)
+    p["event"] = np.arange(n_events, dtype=np.uint32)
+    p["species"] = species
+    p["ekin"] = ekin_MeV
+    d = np.zeros((n_events, 3))
+    d[:, 2] = 1.0
+    if smear_rad > 0.0:
+        rng = np.random.Generator(np.random.Philox(seed))
+        tx = rng.normal(0.0, smear_rad, n_events)
+        ty = rng.normal(0.0, smear_rad, n_events)
+        d[:, 0] = np.tan(tx)
+        d[:, 1] = np.tan(ty)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+    p["dir"] = d
+    return p
+
+
+def mixed_species(n_events: int, e_lo_MeV: float = 1e3, e_hi_MeV: float = 1e5,
+                  seed: int = 3) -> np.ndarray:
+    """Species (e-, e+, gamma) by event index mod 3; energy log-uniform."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    p = primaries(n_events)
+    p["event"] = np.arange(n_events, dtype=np.uint32)
+    order = np.array([ELECTRON, POSITRON, GAMMA], dtype=np.uint32)
+    p["species"] = order[np.arange(n_events) % 3]
+    p["ekin"] = np.exp(rng.uniform(math.log(e_lo_MeV), math.log(e_hi_MeV), n_events))
+    p["dir"] = np.array([0.0, 0.0, 1.0])
+    return p
+
+
+def workload(name: str):
+    """(geometry, config, primaries) of a named workload."""
+    geo = calorimeter()
+    if name == "cal_1GeV_e-_x32":
+        return geo, RunConfig(seed=1), beam(32, ELECTRON, 1000.0)
+    if name == "cal_10GeV_e-_x10k":
+        return geo, RunConfig(seed=2), beam(10_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=2)
+    if name == "cal_mixed_1-100GeV_bz3.8_x10k":
+        return geo, RunConfig(seed=3, bz_tesla=3.8), mixed_species(10_000, seed=3)
+    if name == "cal_10GeV_e-_x100k":
+        return geo, RunConfig(seed=4), beam(100_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=4)
+    raise KeyError(name)
+
+
+def random_tracks(n: int, n_events: int, geo: Geometry, e_lo: float, e_hi: float,
+                  seed: int, species=None) -> np.ndarray:
+    """Isotropic tracks at random points inside the stack (for edge cases)."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    p = primaries(n)
+    p["event"] = rng.integers(0, n_events, n).astype(np.uint32)
+    p["species"] = rng.integers(0, 3, n) if species is None else species
+    p["ekin"] = np.exp(rng.uniform(math.log(e_lo), math.log(e_hi), n))
+    pos = np.empty((n, 3))
+    pos[:, 0] = rng.uniform(-0.9, 0.9, n) * geo.half_xy_mm
+    pos[:, 1] = rng.uniform(-0.9, 0.9, n) * geo.half_xy_mm
+    pos[:, 2] = rng.uniform(geo.z_mm[0], geo.z_mm[-1], n)
+    p["pos"] = pos
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    p["dir"] = d
+    return p

@@ -1,0 +1,325 @@
+"""Pins of the oracle's cross sections, stopping powers and tables.
+
+Each model is tied to something other than its own formula: a textbook
+differential cross section integrated numerically, a closed-form limit
+(Thomson, complete screening, radiation length, Rutherford, ultra-relativistic
+Bhabha), an integral identity (restricted versus unrestricted loss), scaling
+laws, or tabulated PDG values.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import ems_inputs as I
+
+ME = 0.51099895
+RE = 2.8179403262e-12
+ALPHA = 1 / 137.035999084
+NA = 6.02214076e23
+SIGMA_T = 8 * math.pi / 3 * RE ** 2
+PB, LAR = I.LEAD, I.LIQUID_ARGON
+
+
+def n_atoms(m):
+    return m[2] * NA / m[1] * 1e-3  # per mm^3
+
+
+def quad(f, a, b, n=400, log=False):
+    """adaptive quadrature on many sub-intervals (resolves kinks)"""
+    if log:
+        xs = np.geomspace(a, b, n + 1)
+    else:
+        xs = np.linspace(a, b, n + 1)
+    return sum(integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-12, limit=200)[0] for lo, hi in zip(xs[:-1], xs[1:]))
+
+
+# ---------------------------------------------------------------- Compton
+@pytest.mark.parametrize("E", [1e-3, 1e-2, 0.1, 1.0, 10.0, 1e3, 1e6])
+def test_klein_nishina_total_equals_integral_of_dsigma_domega(oracle_mod, E):
+    # textbook Klein-Nishina differential cross section per solid angle
+    k = E / ME
+
+    def dsdo(c):
+        P = 1.0 / (1.0 + k * (1.0 - c))
+        return 0.5 * RE ** 2 * P * P * (P + 1.0 / P - (1.0 - c * c)) * 2 * math.pi
+
+    ref = quad(dsdo, -1.0, 1.0, n=50)
+    assert oracle_mod.formula("SIGMA_KN", PB, 0, E) == pytest.approx(ref, rel=1e-11)
+
+
+def test_klein_nishina_limits(oracle_mod):
+    # Thomson limit with the first-order recoil correction
+    for E in (1e-3, 2e-3):
+        k = E / ME
+        assert oracle_mod.formula("SIGMA_KN", PB, 0, E) / SIGMA_T == pytest.approx(1 - 2 * k, abs=6 * k * k)
+    # extreme relativistic limit pi r_e^2 / k (ln 2k + 1/2)
+    E = 1e8
+    k = E / ME
+    assert oracle_mod.formula("SIGMA_KN", PB, 0, E) == pytest.approx(
+        math.pi * RE ** 2 / k * (math.log(2 * k) + 0.5), rel=1e-6)
+
+
+@pytest.mark.parametrize("E", [0.01, 0.5, 5.0, 500.0])
+def test_compton_dsigma_deps_integrates_to_total(oracle_mod, E):
+    eps0 = 1.0 / (1.0 + 2.0 * E / ME)
+    f = lambda e: oracle_mod.formula("DSDE_COMPTON", PB, 0, E, e)
+    assert quad(f, eps0, 1.0, n=50, log=True) == pytest.approx(oracle_mod.formula("SIGMA_KN", PB, 0, E), rel=1e-10)
+
+
+# ---------------------------------------------------------------- photo-effect
+def test_photoelectric_scaling(oracle_mod):
+    s1 = oracle_mod.formula("SIGMA_PE", PB, 0, 0.1)
+    assert oracle_mod.formula("SIGMA_PE", PB, 0, 0.2) / s1 == pytest.approx(2 ** -3.5, rel=1e-13)
+    assert s1 / oracle_mod.formula("SIGMA_PE", LAR, 0, 0.1) == pytest.approx((82 / 18) ** 5, rel=1e-13)
+    # K-shell Born value sqrt(32) alpha^4 Z^5 sigma_T at E = m, times 5/4
+    assert oracle_mod.formula("SIGMA_PE", PB, 0, ME) == pytest.approx(
+        1.25 * math.sqrt(32) * ALPHA ** 4 * 82 ** 5 * SIGMA_T, rel=1e-13)
+
+
+# ---------------------------------------------------------------- pair
+def test_pair_threshold(oracle_mod):
+    for E in (0.5, 2 * ME):
+        assert oracle_mod.formula("SIGMA_PAIR", PB, 0, E) == 0.0
+    assert oracle_mod.formula("SIGMA_PAIR", PB, 0, 10.0) > 0.0
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+def test_pair_complete_screening_limit(oracle_mod, mat):
+    # Tsai's complete-screening pair cross section, with the same Coulomb
+    # correction: 4 a r_e^2 Z(Z+1) [7/9 (ln(184 Z^-1/3) - f_c) - 1/54]
+    Z = mat[0]
+    a2 = (ALPHA * Z) ** 2
+    fc = a2 * (1 / (1 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 ** 2 - 0.002 * a2 ** 3)
+    tsai = 4 * ALPHA * RE ** 2 * Z * (Z + 1) * (7 / 9 * (math.log(184 * Z ** (-1 / 3)) - fc) - 1 / 54)
+    assert oracle_mod.formula("SIGMA_PAIR", mat, 0, 1e8) == pytest.approx(tsai, rel=2e-3)
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+@pytest.mark.parametrize("E", [1.2, 3.0, 30.0, 3e3, 3e6])
+def test_pair_total_equals_integral_of_differential(oracle_mod, mat, E):
+    eps0 = ME / E
+    f = lambda e: oracle_mod.formula("DSDE_PAIR", mat, 0, E, e)
+    ref = quad(f, eps0, 1 - eps0, n=800, log=False) if E < 10 else 2 * quad(f, eps0, 0.5, n=400, log=True)
+    got = oracle_mod.formula("SIGMA_PAIR", mat, 0, E)
+    if ref == 0.0:
+        assert got == 0.0
+    else:
+        assert got == pytest.approx(ref, rel=1e-10)
+
+
+# ---------------------------------------------------------------- bremsstrahlung
+@pytest.mark.parametrize("mat,x0_pdg_mm", [(PB, 5.612), (LAR, 140.0)])
+def test_brems_radiation_length(oracle_mod, mat, x0_pdg_mm):
+    """Unrestricted radiative loss / E at 100 TeV -> 1/X0 of the complete
+    screening model (Butcher-Messel constants at delta = 0), and within 3%
+    of the PDG radiation length."""
+    Z = mat[0]
+    T = 1e8
+    et = T + ME
+    nat = n_atoms(mat)
+    f = lambda k: oracle_mod.formula("DSDK_BREM", mat, 0.1, T, k) * k
+    # integrate in y = k/E_t on a log grid up to the kinematic end
+    loss = nat * quad(f, 1e-9 * T, T, n=400, log=True) + nat * quad(f, 0.0, 1e-9 * T, n=4)
+    a2 = (ALPHA * Z) ** 2
+    fc = a2 * (1 / (1 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 ** 2 - 0.002 * a2 ** 3)
+    g1 = 20.867 / 4 - math.log(Z) / 3 - fc
+    g2 = 20.209 / 4 - math.log(Z) / 3 - fc
+    inv_x0 = 4 * ALPHA * RE ** 2 * nat * Z * (Z + 1) * (4 / 3 * g1 - 1 / 3 * g2)
+    assert loss / et == pytest.approx(inv_x0, rel=2e-3)
+    assert 1 / inv_x0 == pytest.approx(x0_pdg_mm, rel=0.03)
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+@pytest.mark.parametrize("T", [0.15, 1.0, 30.0, 3e3, 3e6])
+def test_brems_sigma_and_restricted_loss_quadrature(oracle_mod, mat, T):
+    kc = 0.1
+    f = lambda k: oracle_mod.formula("DSDK_BREM", mat, kc, T, k)
+    ref = quad(f, kc, T, n=600, log=True)
+    assert oracle_mod.formula("SIGMA_BREM", mat, kc, T) == pytest.approx(ref, rel=1e-10)
+    g = lambda k: f(k) * k
+    km = min(kc, T)
+    ref_s = n_atoms(mat) * quad(g, 0.0, km, n=200)
+    assert oracle_mod.formula("SBREM", mat, kc, T) == pytest.approx(ref_s, rel=1e-10)
+
+
+# ---------------------------------------------------------------- Moller / Bhabha
+@pytest.mark.parametrize("T", [0.41, 1.0, 10.0, 1e3, 1e6])
+def test_moller_total_equals_integral(oracle_mod, T):
+    cut = 0.2
+    f = lambda e: oracle_mod.formula("DSDE_MOLLER", PB, 0, T, e)
+    ref = quad(f, cut / T, 0.5, n=200, log=True)
+    assert oracle_mod.formula("SIGMA_MOLLER", PB, cut, T) == pytest.approx(ref, rel=1e-10)
+
+
+@pytest.mark.parametrize("T", [0.21, 1.0, 10.0, 1e3, 1e6])
+def test_bhabha_total_equals_integral(oracle_mod, T):
+    cut = 0.2
+    f = lambda e: oracle_mod.formula("DSDE_BHABHA", PB, 0, T, e)
+    ref = quad(f, cut / T, 1.0, n=200, log=True)
+    assert oracle_mod.formula("SIGMA_BHABHA", PB, cut, T) == pytest.approx(ref, rel=1e-10)
+
+
+def test_ionisation_cut_edges(oracle_mod):
+    assert oracle_mod.formula("SIGMA_MOLLER", PB, 0.2, 0.4) == 0.0
+    assert oracle_mod.formula("SIGMA_BHABHA", PB, 0.2, 0.2) == 0.0
+
+
+@pytest.mark.parametrize("T", [0.5, 5.0, 500.0])
+def test_rutherford_limit(oracle_mod, T):
+    g = T / ME + 1
+    b2 = 1 - 1 / g ** 2
+    ruth = 2 * math.pi * RE ** 2 * ME / (b2 * T)
+    for which in ("DSDE_MOLLER", "DSDE_BHABHA"):
+        eps = 1e-7
+        assert oracle_mod.formula(which, PB, 0, T, eps) * eps ** 2 == pytest.approx(ruth, rel=1e-5)
+
+
+def test_bhabha_ultrarelativistic_limit(oracle_mod):
+    T = 1e8
+    pref = 2 * math.pi * RE ** 2 * ME / T
+    for eps in (0.01, 0.3, 0.7, 0.99):
+        assert oracle_mod.formula("DSDE_BHABHA", PB, 0, T, eps) / pref == pytest.approx(
+            (1 / eps - 1 + eps) ** 2, rel=1e-6)
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+@pytest.mark.parametrize("T", [1.0, 10.0, 1e3])
+def test_restricted_loss_invariant(oracle_mod, mat, T):
+    """S(cut = T_max) - S(cut) equals n_el * int_cut^T_max W dsigma/dW."""
+    cut = 0.2
+    nel = mat[0] * n_atoms(mat)
+    for which, dsde, emax in (("SION_E", "DSDE_MOLLER", 0.5), ("SION_P", "DSDE_BHABHA", 1.0)):
+        full = oracle_mod.formula(which, mat, emax * T, T)
+        restr = oracle_mod.formula(which, mat, cut, T)
+        f = lambda e: e * T * oracle_mod.formula(dsde, mat, 0, T, e)
+        ref = nel * quad(f, cut / T, emax, n=100, log=True)
+        assert full - restr == pytest.approx(ref, rel=1e-8)
+
+
+def test_ionisation_minimum_sanity(oracle_mod):
+    # unrestricted collision loss near minimum ionisation in lead is close to
+    # the PDG value 1.122 MeV cm2/g (11.35 g/cm3 -> 1.27 MeV/mm)
+    T = 1.5
+    s = oracle_mod.formula("SION_E", PB, T / 2, T)
+    assert 1.0 < s < 1.4
+
+
+# ---------------------------------------------------------------- annihilation
+@pytest.mark.parametrize("T", [1e-3, 0.1, 1.0, 100.0, 1e5])
+def test_heitler_total_equals_integral_of_differential(oracle_mod, T):
+    # Heitler's two-photon spectrum in the photon energy fraction; it counts
+    # photons, so it integrates to twice the annihilation cross section
+    g = T / ME + 1
+    s = math.sqrt(g * g - 1)
+    emin = 1 / (g + 1 + s)
+
+    def S(e):
+        return -(g + 1) ** 2 + (g * g + 4 * g + 1) / e - 1 / e ** 2
+
+    f = lambda e: math.pi * RE ** 2 / ((g + 1) * (g * g - 1)) * (S(e) + S(1 - e))
+    ref = quad(f, emin, 1 - emin, n=100)
+    assert 2 * oracle_mod.formula("SIGMA_ANNIH", PB, 0, T) == pytest.approx(ref, rel=1e-8)
+
+
+# ---------------------------------------------------------------- sampler bounds
+def test_pair_rejection_bound(oracle_mod):
+    for mat in (PB, LAR):
+        for E in np.geomspace(1.03, 1e8, 60):
+            fmax = oracle_mod.formula("PAIR_FMAX", mat, 0, E)
+            eps0 = ME / E
+            for e in np.linspace(eps0, 0.5, 200):
+                assert oracle_mod.formula("PAIR_F", mat, 0, E, e) <= fmax * (1 + 1e-12)
+
+
+def test_brems_rejection_bound(oracle_mod):
+    for mat in (PB, LAR):
+        for T in np.geomspace(0.1001, 1e8, 60):
+            b = oracle_mod.formula("BREM_BOUND", mat, 0.1, T)
+            for k in np.geomspace(0.1, T, 200):
+                assert oracle_mod.formula("BREM_F", mat, 0.1, T, k) <= b * (1 + 1e-12)
+
+
+def test_ionisation_rejection_bounds():
+    # eps^2 * bracket <= bound on a dense grid (Bhabha bound 1/beta^2,
+    # Moller bound 2 + ((g-1)/g)^2/4)
+    for T in np.geomspace(0.2001, 1e8, 80):
+        g = T / ME + 1
+        b2 = 1 - 1 / g ** 2
+        y = 1 / (g + 1)
+        w = 1 - 2 * y
+        B1, B2, B4 = 2 - y * y, w * (3 + y * y), w ** 3
+        B3 = B4 + w * w
+        e = np.linspace(1e-6, 1, 5000)
+        f = 1 / b2 - B1 * e + B2 * e ** 2 - B3 * e ** 3 + B4 * e ** 4
+        assert np.all(f <= 1 / b2 * (1 + 1e-12))
+        c = ((g - 1) / g) ** 2
+        d = (2 * g - 1) / g ** 2
+        e = np.linspace(1e-6, 0.5, 5000)
+        fm = c * e * e + 1 + e * e / (1 - e) ** 2 - d * e / (1 - e)
+        assert np.all(fm <= (2 + c / 4) * (1 + 1e-12))
+
+
+# ---------------------------------------------------------------- tables
+def test_tables_at_nodes_equal_formulas(cal_oracle, oracle_mod):
+    tab = cal_oracle.tables()
+    cfg = cal_oracle.cfg
+    nodes = np.exp(np.log(cfg.emin_MeV) + np.arange(cfg.n_bins + 1) * (np.log(cfg.emax_MeV) - np.log(cfg.emin_MeV)) / cfg.n_bins)
+    for m, mat in enumerate(cal_oracle.geo.materials):
+        nat = n_atoms(mat)
+        nel = mat[0] * nat
+        for j in range(0, cfg.n_bins + 1, 7):
+            E = nodes[j]
+            f = oracle_mod.formula
+            assert tab[m, 0, j] == pytest.approx(nel * f("SIGMA_KN", mat, 0, E), rel=1e-12)
+            assert tab[m, 1, j] == pytest.approx(nat * f("SIGMA_PE", mat, 0, E), rel=1e-12)
+            assert tab[m, 2, j] == pytest.approx(nat * f("SIGMA_PAIR", mat, 0, E), rel=1e-12, abs=1e-300)
+            assert tab[m, 5, j] == pytest.approx(nel * f("SIGMA_MOLLER", mat, 0.2, E), rel=1e-12, abs=1e-300)
+            assert tab[m, 6, j] == pytest.approx(nat * f("SIGMA_BREM", mat, 0.1, E), rel=1e-12, abs=1e-300)
+            assert tab[m, 9, j] == pytest.approx(nel * f("SIGMA_BHABHA", mat, 0.2, E), rel=1e-12, abs=1e-300)
+            assert tab[m, 10, j] == pytest.approx(nel * f("SIGMA_ANNIH", mat, 0, E), rel=1e-12)
+            sb = f("SBREM", mat, 0.1, E)
+            assert tab[m, 3, j] == pytest.approx(f("SION_E", mat, 0.2, E) + sb, rel=1e-12)
+            assert tab[m, 7, j] == pytest.approx(f("SION_P", mat, 0.2, E) + sb, rel=1e-12)
+
+
+def test_interpolation_is_linear_in_log_energy(cal_oracle):
+    cfg = cal_oracle.cfg
+    d = (math.log(cfg.emax_MeV) - math.log(cfg.emin_MeV)) / cfg.n_bins
+    tab = cal_oracle.tables()
+    for j in (3, 57, 120):
+        E = math.exp(math.log(cfg.emin_MeV) + (j + 0.25) * d)
+        v = cal_oracle.lookup(0, "S_e-", E)
+        assert v == pytest.approx(0.75 * tab[0, 3, j] + 0.25 * tab[0, 3, j + 1], rel=1e-12)
+
+
+@pytest.mark.parametrize("sp,S,R", [(1, 3, 4), (2, 7, 8)])
+def test_range_table_is_integral_of_inverse_stopping_power(cal_oracle, sp, S, R):
+    tab = cal_oracle.tables()
+    cfg = cal_oracle.cfg
+    lo = math.log(cfg.emin_MeV)
+    d = (math.log(cfg.emax_MeV) - lo) / cfg.n_bins
+    for m in range(2):
+        # R_0 = E_0 / (2 S_0); each bin adds the integral of dE / S_interp
+        assert tab[m, R, 0] == pytest.approx(cfg.emin_MeV / (2 * tab[m, S, 0]), rel=1e-12)
+        for j in (1, 40, 90, 160, 200):
+            f = lambda E: 1.0 / cal_oracle.lookup(m, S, E)
+            e0, e1 = math.exp(lo + (j - 1) * d), math.exp(lo + j * d)
+            inc = integrate.quad(f, e0, e1, epsabs=0, epsrel=1e-13)[0]
+            assert tab[m, R, j] - tab[m, R, j - 1] == pytest.approx(inc, rel=1e-11)
+        # the inverse range inverts the range interpolant
+        for E in np.geomspace(1.5e-3, 1e7, 25):
+            r = cal_oracle.lookup(m, R, E)
+            assert cal_oracle.inverse_range(m, sp, r) == pytest.approx(E, rel=1e-12)
+
+
+def test_process_thresholds_in_tables(cal_oracle):
+    tab = cal_oracle.tables()
+    cfg = cal_oracle.cfg
+    nodes = np.exp(np.log(cfg.emin_MeV) + np.arange(cfg.n_bins + 1) * (np.log(cfg.emax_MeV) - np.log(cfg.emin_MeV)) / cfg.n_bins)
+    for m in range(2):
+        assert np.all(tab[m, 2][nodes <= 2 * ME] == 0) and np.all(tab[m, 2][nodes > 2.5] > 0)
+        assert np.all(tab[m, 5][nodes <= 0.4] == 0) and np.all(tab[m, 5][nodes > 0.4] > 0)
+        assert np.all(tab[m, 9][nodes <= 0.2] == 0) and np.all(tab[m, 9][nodes > 0.2] > 0)
+        assert np.all(tab[m, 6][nodes <= 0.1] == 0) and np.all(tab[m, 6][nodes > 0.1] > 0)
