@@ -1,0 +1,229 @@
+/*
+ * ems.h -- C ABI of the MI355X (gfx950) electromagnetic-shower transport
+ * library.
+ *
+ * The library implements the per-step, track-parallel transport loop of
+ * "Offloading electromagnetic shower transport to GPUs" (AdePT, ACAT 2021):
+ * one step is taken for the whole population of e-, e+ and gamma tracks at a
+ * time, secondaries are appended in parallel to per-species "next" arrays that
+ * are swapped with the "current" arrays after every step, and the species of a
+ * track is implied by the array it is in (section 3, "Stepping workflow").
+ * Physics follows section 2.2 (run-time functions taking scalar arguments plus
+ * an abstracted counter-based RNG), the charged propagation follows section
+ * 2.3 (constant field; here an exact helix), and per-event hit arrays are
+ * returned to the host as in section 4 ("Geant4 integration").
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns ems_status: 0 on success, a negative code on error;
+ *    nothing throws or aborts.  ems_last_error() gives a thread-local text.
+ *  - "host" pointers are ordinary CPU memory read or written before the call
+ *    returns; "device" pointers are HIP device memory owned by the caller.
+ *  - Units: MeV, mm, tesla.  Species codes: EMS_GAMMA, EMS_ELECTRON,
+ *    EMS_POSITRON.
+ *  - A context is single-threaded: calls on one ems_ctx must not overlap.
+ *  - After a HIP error the context is failed: every later call except
+ *    ems_destroy returns EMS_E_STATE.
+ */
+#ifndef EMS_H
+#define EMS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMS_ABI_VERSION 1u
+
+typedef int32_t ems_status;
+enum {
+  EMS_OK = 0,
+  EMS_E_INVALID = -1,   /* bad argument; nothing was changed               */
+  EMS_E_CAPACITY = -2,  /* workspace or queue capacity exceeded            */
+  EMS_E_DEVICE = -3,    /* a HIP runtime call failed                        */
+  EMS_E_STATE = -4,     /* context failed earlier, or call out of order     */
+  EMS_E_BUSY = -5,
+  EMS_E_TIMEOUT = -6,
+  EMS_E_VERSION = -7    /* abi_version does not match EMS_ABI_VERSION       */
+};
+enum { EMS_GAMMA = 0, EMS_ELECTRON = 1, EMS_POSITRON = 2 };
+enum { EMS_FP64 = 0, EMS_MIXED = 1 };
+
+/* process_mask bits */
+enum {
+  EMS_P_COMPTON = 1u << 0, EMS_P_PHOT = 1u << 1, EMS_P_CONV = 1u << 2,
+  EMS_P_EIONI = 1u << 3,   /* Moller / Bhabha delta rays above the cut     */
+  EMS_P_EBREM = 1u << 4,   /* bremsstrahlung photons above the cut         */
+  EMS_P_ANNIH = 1u << 5,   /* positron annihilation in flight               */
+  EMS_P_CONT = 1u << 6,    /* continuous restricted energy loss             */
+  EMS_P_ALL = 0x7fu
+};
+/* flags bits */
+enum {
+  EMS_F_STEPLOG = 1u << 0,     /* record every step (tests; slow)           */
+  EMS_F_FULL_LEDGER = 1u << 1, /* per-event step/secondary/null counts and
+                                  charged path length (one more atomic per
+                                  step); energy terms are always kept       */
+  EMS_F_PROFILE = 1u << 2      /* live tracks per species per iteration     */
+};
+
+typedef struct {
+  double Z, A_g_mol, density_g_cm3, I_eV;
+} ems_material;
+
+/* Slab stack along z (the paper's 50-layer sampling calorimeter, section
+ * 2.2): slab k spans [z_mm[k], z_mm[k+1]) and is made of material[k]. */
+typedef struct {
+  uint32_t n_slabs;              /* 1 .. 4096                               */
+  const double* z_mm;            /* host, n_slabs + 1 strictly increasing   */
+  const uint32_t* material;      /* host, n_slabs indices < n_materials     */
+  uint32_t n_materials;          /* 1 .. 4                                  */
+  const ems_material* materials; /* host                                    */
+  double half_xy_mm;             /* transverse extent [-H, H]^2, H > 0      */
+} ems_geometry;
+
+typedef struct {
+  uint32_t abi_version;          /* EMS_ABI_VERSION                          */
+  uint32_t precision;            /* EMS_FP64 (EMS_MIXED: not yet built)      */
+  double bz_tesla;               /* uniform field along +z                   */
+  double gamma_cut_MeV;          /* bremsstrahlung production threshold      */
+  double electron_cut_MeV;       /* delta-ray production threshold           */
+  uint32_t n_bins;               /* log-energy bins (nodes = n_bins + 1)     */
+  double emin_MeV, emax_MeV;     /* table range; emin is the tracking cut    */
+  double dr_over_range;          /* step-function alpha                      */
+  double final_range_mm;         /* step-function rho                        */
+  double lin_loss_limit;         /* linear-loss limit (fraction of range)    */
+  uint32_t process_mask;         /* EMS_P_* bits                             */
+  uint32_t flags;                /* EMS_F_* bits                             */
+  uint32_t max_steps_per_track;  /* watchdog (>= 1)                          */
+  uint32_t seed;                 /* Philox key word 0                        */
+  uint32_t max_events;           /* tally rows (>= 1)                        */
+  uint64_t track_capacity;       /* tracks per species per queue buffer      */
+  uint32_t steps_per_launch;     /* iterations enqueued between status reads */
+  uint32_t launch_blocks;        /* step-kernel grid (0 = library default)   */
+  uint64_t steplog_capacity;     /* records kept when EMS_F_STEPLOG is set   */
+  uint32_t profile_capacity;     /* iterations kept when EMS_F_PROFILE       */
+  uint32_t reserved;
+} ems_config;
+
+/* One primary track (64 bytes). event is the tally row (< max_events); the
+ * track id is the running index of the primary within its row. */
+typedef struct {
+  uint32_t event, species;
+  double ekin_MeV;               /* kinetic energy; photon: total energy     */
+  double pos_mm[3];              /* inside the stack (on a plane: the slab
+                                    the direction enters)                    */
+  double dir[3];                 /* non-zero; normalised by the library      */
+} ems_primary;
+
+/* Per-event energy ledger.  Exactly (to rounding):
+ *   sum of primary kinetic energies = edep + sum(escaped) + killed
+ *                                     + 2 m_e (n_pair - n_annih)            */
+typedef struct {
+  double edep;                   /* sum of the row's slab deposits          */
+  double escaped[3];             /* kinetic energy leaving the stack        */
+  double killed;                 /* kinetic energy removed by the watchdog  */
+  double charged_len;            /* e-/e+ path length (EMS_F_FULL_LEDGER)   */
+  uint64_t n_steps;              /* (EMS_F_FULL_LEDGER)                     */
+  uint64_t n_created[3];         /* pushed secondaries (EMS_F_FULL_LEDGER)  */
+  uint64_t n_null;               /* null collisions (EMS_F_FULL_LEDGER)     */
+  uint32_t n_pair, n_annih;
+} ems_ledger;
+
+/* One step of one track (EMS_F_STEPLOG), 88 bytes. */
+typedef struct {
+  uint32_t event, species;
+  uint64_t id;
+  uint32_t step;                 /* step index before the increment         */
+  int32_t slab_after;            /* -1 once the track has ended             */
+  uint32_t limiter, process;
+  double e_before, e_after;
+  double pos_after[3];
+  double step_len;
+  double edep;                   /* deposited during this step              */
+} ems_step_record;
+
+typedef struct {
+  uint64_t iterations;           /* breadth-first steps of the population   */
+  uint64_t steps[3];             /* track steps per species                 */
+  uint64_t created[3];           /* secondaries pushed per species          */
+  uint64_t deferred;             /* track-steps postponed for capacity      */
+  uint64_t launches;             /* step-kernel launches                    */
+  uint32_t peak_live[3];         /* largest queue per species               */
+  uint32_t steplog_overflow;     /* records dropped beyond the capacity     */
+  double run_ms;                 /* host wall time of the last ems_run      */
+  double step_kernel_ms;         /* device time of the step launches, from
+                                    HIP events around each chain of launches
+                                    on the bound stream (gaps included)     */
+} ems_run_stats;
+
+typedef struct ems_ctx ems_ctx;
+
+/* Device workspace needed for (cfg, geo), in bytes (host outputs). */
+ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo,
+                               uint64_t* bytes);
+
+/* Builds the tables on the host, uploads tables and geometry into the
+ * caller's device workspace (d_workspace, >= ems_workspace_bytes, 256-byte
+ * aligned) and binds the caller's HIP stream (hipStream_t; NULL = the null
+ * stream).  Workspace and stream must outlive the context.  Tallies start at
+ * zero and event key of row r is r. */
+ems_status ems_create(const ems_config* cfg, const ems_geometry* geo,
+                      void* d_workspace, uint64_t bytes, void* hip_stream,
+                      ems_ctx** out);
+
+/* Sets the RNG event key of tally rows [first_row, first_row + n). Results of
+ * a row depend only on (seed, key, its primaries), never on the row. */
+ems_status ems_set_event_keys(ems_ctx* ctx, uint32_t first_row, uint32_t n,
+                              const uint32_t* host_keys);
+
+/* Validates and copies n primaries (host) into the current queues.  All or
+ * nothing: EMS_E_INVALID (NaN or <= 0 energy, zero direction, position
+ * outside the stack, bad species, event >= max_events) or EMS_E_CAPACITY
+ * leaves the context unchanged.  Asynchronous on the bound stream. */
+ems_status ems_enqueue(ems_ctx* ctx, const ems_primary* host, uint64_t n);
+
+/* Steps the whole population until no track is left.  Returns after the
+ * bound stream has drained.  EMS_E_CAPACITY if the queues cannot make
+ * progress; EMS_E_DEVICE on a HIP error. */
+ems_status ems_run(ems_ctx* ctx);
+
+/* Copies deposits of rows [first, first+n) to host_out[n][n_slabs]. */
+ems_status ems_read_edep(ems_ctx* ctx, uint32_t first, uint32_t n, double* host_out);
+/* Copies ledgers of rows [first, first+n) to host_out[n]. */
+ems_status ems_read_ledger(ems_ctx* ctx, uint32_t first, uint32_t n, ems_ledger* host_out);
+/* Zeroes deposits, ledgers, the step log, the profile and per-row track-id
+ * counters (asynchronous on the bound stream). */
+ems_status ems_reset_tallies(ems_ctx* ctx);
+/* Copies up to cap step records (host_out) and returns the number taken in
+ * *n (may exceed cap; records beyond the configured capacity are dropped). */
+ems_status ems_read_steplog(ems_ctx* ctx, ems_step_record* host_out, uint64_t cap,
+                            uint64_t* n);
+/* Live tracks per species per iteration of the last run: host_out[cap][3]. */
+ems_status ems_read_profile(ems_ctx* ctx, uint32_t* host_out, uint32_t cap, uint32_t* n);
+ems_status ems_stats(ems_ctx* ctx, ems_run_stats* out);
+ems_status ems_destroy(ems_ctx* ctx);
+const char* ems_last_error(void);
+uint32_t ems_abi_version(void);
+
+/* Host-only table export (no device needed), layout
+ * [n_materials][11][n_bins+1] with tables in the order: Compton, photo, pair
+ * (1/mm), S e- (MeV/mm), R e- (mm), Moller, brems, S e+, R e+, Bhabha,
+ * annihilation.  Used to compare the library's tables with an independent
+ * implementation. */
+ems_status ems_host_tables(const ems_config* cfg, const ems_geometry* geo, double* host_out,
+                           uint64_t n_doubles);
+
+/* Test hook, never used by ems_run: runs the library's per-track step code
+ * on the host, breadth-first over a queue, for CPU-side checking before any
+ * GPU is used.  Arguments as for a run: primaries (host), n_events rows,
+ * optional keys (NULL: key = row), edep [n_events][n_slabs] and ledger
+ * [n_events] are overwritten, optional step log. */
+ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* geo,
+                                   const ems_primary* prim, uint64_t n, uint32_t n_events,
+                                   const uint32_t* keys, double* edep, ems_ledger* ledger,
+                                   ems_step_record* log, uint64_t log_cap, uint64_t* log_n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

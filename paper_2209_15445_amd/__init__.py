@@ -1,0 +1,278 @@
+"""Python binding of the MI355X EM-shower transport library (libems.so).
+
+Argument marshalling only: every step of the transport runs in the HIP
+kernels of ``csrc/``.  PyTorch supplies the device workspace (a uint8 tensor)
+and the HIP stream.  If the compiled library is missing this module raises
+on import -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libems.so")
+
+ABI_VERSION = 1
+OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, MIXED = 0, 1
+F_STEPLOG, F_FULL_LEDGER, F_PROFILE = 1, 2, 4
+
+
+class EmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ems error {code}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("Z", C.c_double), ("A_g_mol", C.c_double), ("density_g_cm3", C.c_double), ("I_eV", C.c_double)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_slabs", C.c_uint32), ("z_mm", C.POINTER(C.c_double)), ("material", C.POINTER(C.c_uint32)),
+                ("n_materials", C.c_uint32), ("materials", C.POINTER(Material)), ("half_xy_mm", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("precision", C.c_uint32), ("bz_tesla", C.c_double),
+                ("gamma_cut_MeV", C.c_double), ("electron_cut_MeV", C.c_double), ("n_bins", C.c_uint32),
+                ("emin_MeV", C.c_double), ("emax_MeV", C.c_double), ("dr_over_range", C.c_double),
+                ("final_range_mm", C.c_double), ("lin_loss_limit", C.c_double), ("process_mask", C.c_uint32),
+                ("flags", C.c_uint32), ("max_steps_per_track", C.c_uint32), ("seed", C.c_uint32),
+                ("max_events", C.c_uint32), ("track_capacity", C.c_uint64), ("steps_per_launch", C.c_uint32),
+                ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class RunStats(C.Structure):
+    _fields_ = [("iterations", C.c_uint64), ("steps", C.c_uint64 * 3), ("created", C.c_uint64 * 3),
+                ("deferred", C.c_uint64), ("launches", C.c_uint64), ("peak_live", C.c_uint32 * 3),
+                ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double)]
+
+
+LEDGER_DTYPE = np.dtype([("edep", "<f8"), ("escaped", "<f8", (3,)), ("killed", "<f8"), ("charged_len", "<f8"),
+                         ("n_steps", "<u8"), ("n_created", "<u8", (3,)), ("n_null", "<u8"), ("n_pair", "<u4"),
+                         ("n_annih", "<u4")], align=True)
+STEP_DTYPE = np.dtype([("event", "<u4"), ("species", "<u4"), ("id", "<u8"), ("step", "<u4"), ("slab_after", "<i4"),
+                       ("limiter", "<u4"), ("process", "<u4"), ("e_before", "<f8"), ("e_after", "<f8"),
+                       ("pos_after", "<f8", (3,)), ("step_len", "<f8"), ("edep", "<f8")], align=True)
+PRIMARY_DTYPE = np.dtype([("event", "<u4"), ("species", "<u4"), ("ekin", "<f8"), ("pos", "<f8", (3,)),
+                          ("dir", "<f8", (3,))], align=True)
+
+_lib = None
+
+
+def lib():
+    """Loads libems.so (after torch, so both use the same HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        try:
+            import torch  # noqa: F401  (loads the HIP runtime torch uses)
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+        sig = {
+            "ems_workspace_bytes": [C.POINTER(Config), C.POINTER(Geometry), C.POINTER(u64)],
+            "ems_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, C.POINTER(vp)],
+            "ems_set_event_keys": [vp, u32, u32, vp],
+            "ems_enqueue": [vp, vp, u64],
+            "ems_run": [vp],
+            "ems_read_edep": [vp, u32, u32, vp],
+            "ems_read_ledger": [vp, u32, u32, vp],
+            "ems_reset_tallies": [vp],
+            "ems_read_steplog": [vp, vp, u64, C.POINTER(u64)],
+            "ems_read_profile": [vp, vp, u32, C.POINTER(u32)],
+            "ems_stats": [vp, C.POINTER(RunStats)],
+            "ems_destroy": [vp],
+            "ems_host_tables": [C.POINTER(Config), C.POINTER(Geometry), vp, u64],
+            "ems_debug_host_transport": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, u32, vp, vp, vp, vp, u64,
+                                         C.POINTER(u64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.ems_last_error.argtypes = []
+        L.ems_last_error.restype = C.c_char_p
+        L.ems_abi_version.argtypes = []
+        L.ems_abi_version.restype = C.c_uint32
+        if L.ems_abi_version() != ABI_VERSION:
+            raise ImportError("libems.so ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise EmsError(rc, lib().ems_last_error().decode())
+    return rc
+
+
+class _GeoHolder:
+    """Keeps the arrays a Geometry struct points to alive."""
+
+    def __init__(self, geometry):
+        self.z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
+        self.mat = np.ascontiguousarray(geometry.material, dtype=np.uint32)
+        self.mats = (Material * len(geometry.materials))(*[Material(*m) for m in geometry.materials])
+        g = Geometry()
+        g.n_slabs = len(self.mat)
+        g.z_mm = self.z.ctypes.data_as(C.POINTER(C.c_double))
+        g.material = self.mat.ctypes.data_as(C.POINTER(C.c_uint32))
+        g.n_materials = len(geometry.materials)
+        g.materials = self.mats
+        g.half_xy_mm = float(geometry.half_xy_mm)
+        self.g = g
+        self.n_slabs = len(self.mat)
+
+
+def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0):
+    """Config struct from a run description (any object with the physics
+    fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
+    c = Config()
+    c.abi_version = ABI_VERSION
+    c.precision = precision
+    for f in ("bz_tesla", "gamma_cut_MeV", "electron_cut_MeV", "n_bins", "emin_MeV", "emax_MeV", "dr_over_range",
+              "final_range_mm", "lin_loss_limit", "process_mask", "max_steps_per_track", "seed"):
+        setattr(c, f, getattr(run, f))
+    c.flags = flags
+    c.max_events = max_events
+    c.track_capacity = track_capacity
+    c.steps_per_launch = steps_per_launch
+    c.launch_blocks = launch_blocks
+    c.steplog_capacity = steplog_capacity
+    c.profile_capacity = profile_capacity
+    return c
+
+
+def workspace_bytes(config, geometry) -> int:
+    gh = _GeoHolder(geometry)
+    n = C.c_uint64()
+    _check(lib().ems_workspace_bytes(C.byref(config), C.byref(gh.g), C.byref(n)))
+    return n.value
+
+
+def host_tables(config, geometry) -> np.ndarray:
+    gh = _GeoHolder(geometry)
+    nodes = config.n_bins + 1
+    out = np.empty(len(geometry.materials) * 11 * nodes)
+    _check(lib().ems_host_tables(C.byref(config), C.byref(gh.g), out.ctypes.data_as(C.c_void_p), out.size))
+    return out.reshape(len(geometry.materials), 11, nodes)
+
+
+def _prim(prim):
+    p = np.ascontiguousarray(prim)
+    if p.dtype.itemsize != 64:
+        raise ValueError("primaries must be 64-byte records")
+    return p
+
+
+def debug_host_transport(config, geometry, prim, n_events, keys=None, log_cap=0):
+    """Runs the library's step code on the host (test hook)."""
+    gh = _GeoHolder(geometry)
+    p = _prim(prim)
+    edep = np.zeros((n_events, gh.n_slabs))
+    led = np.zeros(n_events, dtype=LEDGER_DTYPE)
+    log = np.zeros(log_cap, dtype=STEP_DTYPE) if log_cap else None
+    n = C.c_uint64()
+    k = None if keys is None else np.ascontiguousarray(keys, dtype=np.uint32)
+    _check(lib().ems_debug_host_transport(
+        C.byref(config), C.byref(gh.g), p.ctypes.data_as(C.c_void_p), len(p), n_events,
+        None if k is None else k.ctypes.data_as(C.c_void_p), edep.ctypes.data_as(C.c_void_p),
+        led.ctypes.data_as(C.c_void_p), None if log is None else log.ctypes.data_as(C.c_void_p), log_cap,
+        C.byref(n)))
+    out = dict(edep=edep, ledger=led, n_log=n.value)
+    if log is not None:
+        out["log"] = log[: min(log_cap, n.value)]
+    return out
+
+
+class Transport:
+    """One transport context on the current HIP device.
+
+    The workspace is a torch uint8 tensor on the device; the stream is the
+    given torch stream (default: the current stream)."""
+
+    def __init__(self, config, geometry, stream=None, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the transport runs only on the GPU")
+        self.config = config
+        self._gh = _GeoHolder(geometry)
+        self.n_slabs = self._gh.n_slabs
+        nbytes = workspace_bytes(config, geometry)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().ems_create(C.byref(config), C.byref(self._gh.g), C.c_void_p(self._ws_ptr), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ems_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_event_keys(self, keys, first_row=0):
+        k = np.ascontiguousarray(keys, dtype=np.uint32)
+        _check(lib().ems_set_event_keys(self._h, first_row, len(k), k.ctypes.data_as(C.c_void_p)))
+
+    def enqueue(self, prim):
+        p = _prim(prim)
+        _check(lib().ems_enqueue(self._h, p.ctypes.data_as(C.c_void_p), len(p)))
+
+    def run(self):
+        _check(lib().ems_run(self._h))
+
+    def edep(self, first=0, n=None):
+        n = self.config.max_events - first if n is None else n
+        out = np.empty((n, self.n_slabs))
+        _check(lib().ems_read_edep(self._h, first, n, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def ledger(self, first=0, n=None):
+        n = self.config.max_events - first if n is None else n
+        out = np.zeros(n, dtype=LEDGER_DTYPE)
+        _check(lib().ems_read_ledger(self._h, first, n, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def reset(self):
+        _check(lib().ems_reset_tallies(self._h))
+
+    def steplog(self):
+        n = C.c_uint64()
+        _check(lib().ems_read_steplog(self._h, None, 0, C.byref(n)))
+        cap = min(n.value, self.config.steplog_capacity)
+        out = np.zeros(cap, dtype=STEP_DTYPE)
+        _check(lib().ems_read_steplog(self._h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return out, n.value
+
+    def profile(self):
+        n = C.c_uint32()
+        _check(lib().ems_read_profile(self._h, None, 0, C.byref(n)))
+        cap = min(n.value, self.config.profile_capacity)
+        out = np.zeros((cap, 3), dtype=np.uint32)
+        _check(lib().ems_read_profile(self._h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return out, n.value
+
+    def stats(self):
+        s = RunStats()
+        _check(lib().ems_stats(self._h, C.byref(s)))
+        return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
+                    launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
+                    run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms)

@@ -1,0 +1,601 @@
+// ems_api.cpp -- host runtime and C ABI of the transport library.
+//
+// Host side of the paper's stepping workflow (section 3) and of its
+// hybrid-integration contract (section 4): tracks come in, the population is
+// stepped on the GPU until it is empty, per-event deposits go back out.  The
+// device memory and the stream are the caller's (PyTorch provides them); the
+// library only carves the workspace and enqueues work on that stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/ems.h"
+#include "ems_device.hpp"
+
+namespace ems {
+hipError_t launch_step(const KArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
+hipError_t launch_plan(const KArgs& a, hipStream_t s);
+hipError_t set_step_lds(uint32_t bytes);
+}  // namespace ems
+
+using namespace ems;
+
+static_assert(sizeof(ems_primary) == 64, "primary record is 64 bytes");
+static_assert(sizeof(LedgerDev) == sizeof(ems_ledger), "ledger layouts agree");
+static_assert(sizeof(StepRec) == sizeof(ems_step_record), "step record layouts agree");
+
+namespace {
+
+thread_local std::string g_err;
+
+ems_status fail(ems_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kInjectChunk = 1u << 18;
+
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  uint64_t ctl, tab, zp, smat, mat, keys, edep, ledger, profile, log, inj, queues, total;
+  uint64_t cap;
+};
+
+ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
+  if (!c || !g) return fail(EMS_E_INVALID, "null config or geometry");
+  if (c->abi_version != EMS_ABI_VERSION) return fail(EMS_E_VERSION, "abi_version mismatch");
+  if (c->precision != EMS_FP64) return fail(EMS_E_INVALID, "only EMS_FP64 is available");
+  if (g->n_slabs < 1 || g->n_slabs > 4096 || !g->z_mm || !g->material)
+    return fail(EMS_E_INVALID, "geometry needs 1..4096 slabs with planes and materials");
+  if (g->n_materials < 1 || g->n_materials > 4 || !g->materials)
+    return fail(EMS_E_INVALID, "geometry needs 1..4 materials");
+  if (!(g->half_xy_mm > 0.0) || !isfinite(g->half_xy_mm)) return fail(EMS_E_INVALID, "half_xy_mm must be > 0");
+  for (uint32_t i = 0; i < g->n_slabs; ++i) {
+    if (!(g->z_mm[i + 1] > g->z_mm[i]) || !isfinite(g->z_mm[i + 1]) || !isfinite(g->z_mm[i]))
+      return fail(EMS_E_INVALID, "z planes must be finite and strictly increasing");
+    if (g->material[i] >= g->n_materials) return fail(EMS_E_INVALID, "slab material index out of range");
+  }
+  for (uint32_t i = 0; i < g->n_materials; ++i) {
+    const ems_material& m = g->materials[i];
+    if (!(m.Z >= 1.0) || !(m.A_g_mol > 0.0) || !(m.density_g_cm3 > 0.0) || !(m.I_eV > 0.0))
+      return fail(EMS_E_INVALID, "material constants must be positive");
+  }
+  if (c->n_bins < 2 || c->n_bins > 2000 || !(c->emin_MeV > 0.0) || !(c->emax_MeV > c->emin_MeV))
+    return fail(EMS_E_INVALID, "bad energy grid");
+  if (!(c->gamma_cut_MeV > c->emin_MeV) || !(c->electron_cut_MeV > c->emin_MeV))
+    return fail(EMS_E_INVALID, "production cuts must exceed emin");
+  if (!(c->dr_over_range > 0.0 && c->dr_over_range <= 1.0) || !(c->final_range_mm > 0.0) ||
+      !(c->lin_loss_limit > 0.0 && c->lin_loss_limit < 1.0))
+    return fail(EMS_E_INVALID, "bad step-function parameters");
+  if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
+  if (c->max_steps_per_track < 1 || c->max_events < 1) return fail(EMS_E_INVALID, "max_steps and max_events >= 1");
+  if (c->track_capacity < 64 || c->track_capacity > (1ull << 31))
+    return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^31]");
+  return EMS_OK;
+}
+
+Layout plan(const ems_config* c, const ems_geometry* g) {
+  Layout L{};
+  const uint64_t nodes = c->n_bins + 1;
+  L.cap = (c->track_capacity + 63) / 64 * 64;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.tab = take(g->n_materials * kNumTables * nodes * 8);
+  L.zp = take((g->n_slabs + 1) * 8ull);
+  L.smat = take(g->n_slabs * 4ull);
+  L.mat = take(g->n_materials * sizeof(MatRT));
+  L.keys = take(c->max_events * 4ull);
+  L.edep = take((uint64_t)c->max_events * g->n_slabs * 8);
+  L.ledger = take((uint64_t)c->max_events * sizeof(LedgerDev));
+  L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
+  L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
+  L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
+  L.queues = take(6 * L.cap * kTrackBytes);
+  L.total = o;
+  return L;
+}
+
+TableSet tables_for(const ems_config* c, const ems_geometry* g) {
+  TableParams p;
+  p.n_bins = c->n_bins;
+  p.emin = c->emin_MeV;
+  p.emax = c->emax_MeV;
+  p.gamma_cut = c->gamma_cut_MeV;
+  p.electron_cut = c->electron_cut_MeV;
+  p.process_mask = c->process_mask;
+  std::vector<MaterialIn> mats;
+  for (uint32_t i = 0; i < g->n_materials; ++i) {
+    const ems_material& m = g->materials[i];
+    mats.push_back(MaterialIn{m.Z, m.A_g_mol, m.density_g_cm3, m.I_eV});
+  }
+  return build_tables(p, mats);
+}
+
+StepEnv env_for(const ems_config* c, const ems_geometry* g, const TableSet& ts) {
+  StepEnv e{};
+  e.nodes = ts.nodes;
+  e.n_slabs = g->n_slabs;
+  e.lnemin = ts.lnemin;
+  e.dlog = ts.dlog;
+  e.inv_dlog = 1.0 / ts.dlog;
+  e.half_xy = g->half_xy_mm;
+  e.bz = c->bz_tesla;
+  e.ecut = c->emin_MeV;
+  e.tcut = c->electron_cut_MeV;
+  e.kcut = c->gamma_cut_MeV;
+  e.alpha = c->dr_over_range;
+  e.rho = c->final_range_mm;
+  e.lin = c->lin_loss_limit;
+  e.mask = c->process_mask;
+  e.seed = c->seed;
+  e.max_steps = c->max_steps_per_track;
+  return e;
+}
+
+// slab of a point; a point on a plane belongs to the slab it moves into
+int32_t locate(const double* z, uint32_t n, double zz, double uz) {
+  uint32_t lo = 0, hi = n;  // z[lo] <= zz < z[hi]
+  if (zz >= z[n]) return (int32_t)n - 1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (z[mid] <= zz) lo = mid;
+    else hi = mid;
+  }
+  if (lo > 0 && zz == z[lo] && uz < 0.0) lo -= 1;
+  return (int32_t)lo;
+}
+
+// validate and convert primaries; ids are running indices per row
+ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary* p, uint64_t n,
+                   std::vector<uint64_t>& row_count, std::vector<InjRec>& out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    const ems_primary& q = p[i];
+    const double d2 = q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2];
+    const bool ok = q.event < max_events && q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && isfinite(q.ekin_MeV) &&
+                    d2 > 0.0 && isfinite(d2) && q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] &&
+                    fabs(q.pos_mm[0]) <= g.half_xy_mm && fabs(q.pos_mm[1]) <= g.half_xy_mm;
+    if (!ok) return fail(EMS_E_INVALID, "invalid primary #" + std::to_string(i));
+  }
+  out.resize(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    const ems_primary& q = p[i];
+    const double nrm = sqrt(q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2]);
+    InjRec& r = out[i];
+    r.x = q.pos_mm[0];
+    r.y = q.pos_mm[1];
+    r.z = q.pos_mm[2];
+    r.ux = q.dir[0] / nrm;
+    r.uy = q.dir[1] / nrm;
+    r.uz = q.dir[2] / nrm;
+    r.E = q.ekin_MeV;
+    r.ev = q.event;
+    r.sp = q.species;
+    r.slab = locate(g.z_mm, g.n_slabs, r.z, r.uz);
+    r.id = row_count[q.event]++;
+    r.pad = 0;
+  }
+  return EMS_OK;
+}
+
+}  // namespace
+
+struct ems_ctx {
+  ems_config cfg;
+  std::vector<double> z;
+  std::vector<uint32_t> smat;
+  std::vector<ems_material> mats;
+  ems_geometry geo;
+  TableSet ts;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  KArgs args{};
+  uint32_t blocks = 0;
+  std::vector<uint64_t> row_count;
+  uint64_t pending[3] = {0, 0, 0};
+  InjRec* pin_inj = nullptr;
+  Ctl* pin_ctl = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool failed = false;
+  ems_run_stats stats{};
+};
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (ctx)->failed = true;                                                                    \
+      return fail(EMS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    }                                                                                          \
+  } while (0)
+
+extern "C" {
+
+uint32_t ems_abi_version(void) { return EMS_ABI_VERSION; }
+
+const char* ems_last_error(void) { return g_err.c_str(); }
+
+ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo, uint64_t* bytes) {
+  ems_status st = check_inputs(cfg, geo);
+  if (st) return st;
+  if (!bytes) return fail(EMS_E_INVALID, "null output");
+  *bytes = plan(cfg, geo).total;
+  return EMS_OK;
+}
+
+ems_status ems_host_tables(const ems_config* cfg, const ems_geometry* geo, double* out, uint64_t n) {
+  ems_status st = check_inputs(cfg, geo);
+  if (st) return st;
+  const uint64_t nodes = cfg->n_bins + 1;
+  const uint64_t need = (uint64_t)geo->n_materials * kNumExport * nodes;
+  if (!out || n < need) return fail(EMS_E_INVALID, "output buffer too small");
+  TableSet ts = tables_for(cfg, geo);
+  for (uint32_t m = 0; m < geo->n_materials; ++m)
+    for (int t = 0; t < kNumExport; ++t)
+      for (uint64_t j = 0; j < nodes; ++j) out[((uint64_t)m * kNumExport + t) * nodes + j] = ts.at(m, t, (uint32_t)j);
+  return EMS_OK;
+}
+
+ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws, uint64_t bytes, void* stream,
+                      ems_ctx** out) {
+  ems_status st = check_inputs(cfg, geo);
+  if (st) return st;
+  if (!out || !d_ws) return fail(EMS_E_INVALID, "null workspace or output");
+  if (((uintptr_t)d_ws) % kAlign) return fail(EMS_E_INVALID, "workspace must be 256-byte aligned");
+  Layout L = plan(cfg, geo);
+  if (bytes < L.total) return fail(EMS_E_CAPACITY, "workspace smaller than ems_workspace_bytes");
+  ems_ctx* c = new ems_ctx();
+  c->cfg = *cfg;
+  c->z.assign(geo->z_mm, geo->z_mm + geo->n_slabs + 1);
+  c->smat.assign(geo->material, geo->material + geo->n_slabs);
+  c->mats.assign(geo->materials, geo->materials + geo->n_materials);
+  c->geo = *geo;
+  c->geo.z_mm = c->z.data();
+  c->geo.material = c->smat.data();
+  c->geo.materials = c->mats.data();
+  c->ts = tables_for(cfg, geo);
+  c->L = L;
+  c->ws = static_cast<char*>(d_ws);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->row_count.assign(cfg->max_events, 0);
+  auto bad = [&](ems_status s) {
+    delete c;
+    return s;
+  };
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return bad(fail(EMS_E_DEVICE, "no HIP device"));
+  const uint32_t lds = (uint32_t)(geo->n_materials * kNumTables * (cfg->n_bins + 1) * 8 + (geo->n_slabs + 1) * 8 +
+                                  geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
+  if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) return bad(fail(EMS_E_INVALID, "tables exceed LDS"));
+  if (set_step_lds(lds) != hipSuccess) return bad(fail(EMS_E_DEVICE, "cannot reserve LDS for the step kernel"));
+  // blocks resident per CU are bounded by LDS; keep the grid one wave of them
+  const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160u * 1024u) / lds));
+  c->blocks = cfg->launch_blocks ? cfg->launch_blocks : (uint32_t)prop.multiProcessorCount * per_cu;
+
+  KArgs& a = c->args;
+  a.qbase = c->ws + L.queues;
+  a.ctl = reinterpret_cast<Ctl*>(c->ws + L.ctl);
+  a.edep = reinterpret_cast<double*>(c->ws + L.edep);
+  a.ledger = reinterpret_cast<LedgerDev*>(c->ws + L.ledger);
+  a.keys = reinterpret_cast<const uint32_t*>(c->ws + L.keys);
+  a.tab = reinterpret_cast<const double*>(c->ws + L.tab);
+  a.zplane = reinterpret_cast<const double*>(c->ws + L.zp);
+  a.slab_mat = reinterpret_cast<const uint32_t*>(c->ws + L.smat);
+  a.mat = reinterpret_cast<const MatRT*>(c->ws + L.mat);
+  a.log = reinterpret_cast<StepRec*>(c->ws + L.log);
+  a.profile = reinterpret_cast<uint32_t*>(c->ws + L.profile);
+  a.cap = L.cap;
+  a.log_cap = (cfg->flags & EMS_F_STEPLOG) ? cfg->steplog_capacity : 0;
+  a.profile_cap = (cfg->flags & EMS_F_PROFILE) ? cfg->profile_capacity : 0;
+  a.flags = cfg->flags;
+  a.n_mat = geo->n_materials;
+  a.lds_bytes = lds;
+  a.env = env_for(cfg, geo, c->ts);
+
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_inj), kInjectChunk * sizeof(InjRec)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return bad(fail(EMS_E_DEVICE, "pinned host allocation or event creation failed"));
+  std::vector<uint32_t> keys(cfg->max_events);
+  for (uint32_t i = 0; i < cfg->max_events; ++i) keys[i] = i;
+  hipStream_t s = c->stream;
+  bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.tab, c->ts.v.data(), c->ts.v.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.mat, c->ts.rt.data(), c->ts.rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
+                hipSuccess &&
+            hipMemcpyAsync(c->ws + L.keys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemsetAsync(c->ws + L.edep, 0, (L.ledger - L.edep) + (uint64_t)cfg->max_events * sizeof(LedgerDev), s) ==
+                hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    (void)hipHostFree(c->pin_inj);
+    (void)hipHostFree(c->pin_ctl);
+    return bad(fail(EMS_E_DEVICE, "workspace initialisation failed"));
+  }
+  *out = c;
+  return EMS_OK;
+}
+
+ems_status ems_destroy(ems_ctx* c) {
+  if (!c) return EMS_OK;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->pin_inj) (void)hipHostFree(c->pin_inj);
+  if (c->pin_ctl) (void)hipHostFree(c->pin_ctl);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+  return EMS_OK;
+}
+
+ems_status ems_set_event_keys(ems_ctx* c, uint32_t first, uint32_t n, const uint32_t* keys) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!keys || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.keys + first * 4ull, keys, n * 4ull, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EMS_OK;
+}
+
+ems_status ems_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (n == 0) return EMS_OK;
+  if (!p) return fail(EMS_E_INVALID, "null primaries");
+  uint64_t add[3] = {0, 0, 0};
+  for (uint64_t i = 0; i < n; ++i)
+    if (p[i].species <= EMS_POSITRON) add[p[i].species] += 1;
+  for (int s = 0; s < 3; ++s)
+    if (c->pending[s] + add[s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
+  std::vector<uint64_t> rows = c->row_count;
+  std::vector<InjRec> recs;
+  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, recs);
+  if (st) return st;
+  for (uint64_t done = 0; done < n; done += kInjectChunk) {
+    const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // pinned staging is free again
+    memcpy(c->pin_inj, recs.data() + done, k * sizeof(InjRec));
+    InjRec* d = reinterpret_cast<InjRec*>(c->ws + c->L.inj);
+    HIPCHK(c, hipMemcpyAsync(d, c->pin_inj, k * sizeof(InjRec), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_inject(c->args, d, k, c->stream));
+  }
+  c->row_count.swap(rows);
+  for (int s = 0; s < 3; ++s) c->pending[s] += add[s];
+  return EMS_OK;
+}
+
+ems_status ems_run(ems_ctx* c) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  const auto t0 = std::chrono::steady_clock::now();
+  const uint32_t K = c->cfg.steps_per_launch ? c->cfg.steps_per_launch : 16;
+  HIPCHK(c, launch_plan(c->args, c->stream));
+  uint64_t launches = 0;
+  double kms = 0.0;
+  for (;;) {
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_step(c->args, c->blocks, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    launches += K;
+    HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    kms += ms;
+    const Ctl& s = *c->pin_ctl;
+    if (s.error & kErrOverflow) {
+      c->failed = true;
+      return fail(EMS_E_CAPACITY, "track queue overflow");
+    }
+    if (s.error & kErrStall) {
+      c->failed = true;
+      return fail(EMS_E_CAPACITY, "track queues too small to make progress");
+    }
+    if (s.live == 0) break;
+    // a track lives at most max_steps iterations; generations are few
+    if ((uint64_t)s.iteration > 64ull * c->cfg.max_steps_per_track + 4096) {
+      c->failed = true;
+      return fail(EMS_E_STATE, "iteration guard reached");
+    }
+  }
+  const Ctl& s = *c->pin_ctl;
+  ems_run_stats& st = c->stats;
+  st.iterations = s.iteration;
+  for (int i = 0; i < 3; ++i) {
+    st.steps[i] = s.steps[i];
+    st.created[i] = s.created[i];
+    st.peak_live[i] = s.peak[i];
+  }
+  st.deferred = s.deferred;
+  st.launches += launches;
+  st.steplog_overflow = (c->args.log_cap && s.log_n > c->args.log_cap) ? 1u : 0u;
+  st.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  st.step_kernel_ms += kms;
+  for (int i = 0; i < 3; ++i) c->pending[i] = 0;
+  return EMS_OK;
+}
+
+ems_status ems_read_edep(ems_ctx* c, uint32_t first, uint32_t n, double* out) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!out || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
+  const uint64_t row = c->geo.n_slabs * 8ull;
+  HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.edep + first * row, n * row, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EMS_OK;
+}
+
+ems_status ems_read_ledger(ems_ctx* c, uint32_t first, uint32_t n, ems_ledger* out) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!out || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
+  HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.ledger + first * sizeof(LedgerDev), n * sizeof(LedgerDev),
+                           hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> ed((size_t)n * c->geo.n_slabs);
+  const uint64_t row = c->geo.n_slabs * 8ull;
+  HIPCHK(c, hipMemcpyAsync(ed.data(), c->ws + c->L.edep + first * row, n * row, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (uint32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (uint32_t k = 0; k < c->geo.n_slabs; ++k) s += ed[(size_t)i * c->geo.n_slabs + k];
+    out[i].edep = s;
+  }
+  return EMS_OK;
+}
+
+ems_status ems_reset_tallies(ems_ctx* c) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  const Layout& L = c->L;
+  HIPCHK(c, hipMemsetAsync(c->ws + L.edep, 0, (uint64_t)c->cfg.max_events * c->geo.n_slabs * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + L.ledger, 0, (uint64_t)c->cfg.max_events * sizeof(LedgerDev), c->stream));
+  if (c->args.profile_cap)
+    HIPCHK(c, hipMemsetAsync(c->ws + L.profile, 0, (uint64_t)c->args.profile_cap * 12, c->stream));
+  // keep the queues (empty after a run) but restart counters and statistics
+  HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Ctl fresh{};
+  fresh.cur = c->pin_ctl->cur;
+  for (int s = 0; s < 3; ++s) fresh.n_cur[s] = c->pin_ctl->n_cur[s];
+  *c->pin_ctl = fresh;
+  HIPCHK(c, hipMemcpyAsync(c->ws + L.ctl, c->pin_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::fill(c->row_count.begin(), c->row_count.end(), 0);
+  c->stats = ems_run_stats{};
+  return EMS_OK;
+}
+
+ems_status ems_read_steplog(ems_ctx* c, ems_step_record* out, uint64_t cap, uint64_t* n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!n) return fail(EMS_E_INVALID, "null count");
+  HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const uint64_t total = c->pin_ctl->log_n;
+  *n = total;
+  const uint64_t k = std::min<uint64_t>(std::min<uint64_t>(total, c->args.log_cap), out ? cap : 0);
+  if (k) {
+    HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.log, k * sizeof(StepRec), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return EMS_OK;
+}
+
+ems_status ems_read_profile(ems_ctx* c, uint32_t* out, uint32_t cap, uint32_t* n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!n) return fail(EMS_E_INVALID, "null count");
+  HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *n = c->pin_ctl->iteration;
+  const uint32_t k = std::min<uint32_t>(std::min<uint32_t>(*n, c->args.profile_cap), out ? cap : 0);
+  if (k) {
+    HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.profile, k * 12ull, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return EMS_OK;
+}
+
+ems_status ems_stats(ems_ctx* c, ems_run_stats* out) {
+  if (!c || !out) return fail(EMS_E_INVALID, "null argument");
+  *out = c->stats;
+  return EMS_OK;
+}
+
+ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* geo, const ems_primary* prim,
+                                   uint64_t n, uint32_t n_events, const uint32_t* keys, double* edep,
+                                   ems_ledger* ledger, ems_step_record* log, uint64_t log_cap, uint64_t* log_n) {
+  ems_config c2 = *cfg;
+  c2.max_events = n_events ? n_events : 1;
+  ems_status st = check_inputs(&c2, geo);
+  if (st) return st;
+  if (!edep || !ledger || (n && !prim)) return fail(EMS_E_INVALID, "null buffers");
+  TableSet ts = tables_for(&c2, geo);
+  StepEnv env = env_for(&c2, geo, ts);
+  env.tab = ts.v.data();
+  env.zplane = geo->z_mm;
+  env.slab_mat = geo->material;
+  env.mat = ts.rt.data();
+  std::vector<uint64_t> rows(n_events, 0);
+  std::vector<InjRec> recs;
+  st = prepare(*geo, n_events, prim, n, rows, recs);
+  if (st) return st;
+  memset(edep, 0, sizeof(double) * n_events * geo->n_slabs);
+  memset(ledger, 0, sizeof(ems_ledger) * n_events);
+  std::vector<Trk> cur[3], nxt[3];
+  for (const InjRec& r : recs) {
+    Trk t{r.x, r.y, r.z, r.ux, r.uy, r.uz, r.E, r.id, r.ev, keys ? keys[r.ev] : r.ev, 0, r.slab};
+    cur[r.sp].push_back(t);
+  }
+  uint64_t nlog = 0;
+  for (;;) {
+    if (cur[0].empty() && cur[1].empty() && cur[2].empty()) break;
+    for (int sp = 0; sp < 3; ++sp) {
+      for (Trk t : cur[sp]) {
+        const double e0 = t.E;
+        StepOut o;
+        take_step(env, sp, t, o);
+        ems_ledger& L = ledger[t.ev];
+        edep[(size_t)t.ev * geo->n_slabs + o.slab] += o.dep;
+        L.escaped[sp] += o.escaped;
+        L.killed += o.killed;
+        L.charged_len += o.clen;
+        L.n_steps += 1;
+        L.n_null += o.null;
+        L.n_pair += o.pair;
+        L.n_annih += o.annih;
+        for (int k = 0; k < o.nsec; ++k) {
+          const Sec& s = o.sec[k];
+          L.n_created[s.sp] += 1;
+          nxt[s.sp].push_back(Trk{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});
+        }
+        if (t.slab >= 0) nxt[sp].push_back(t);
+        if (log && nlog < log_cap) {
+          ems_step_record& r = log[nlog];
+          r.event = t.ev;
+          r.species = (uint32_t)sp;
+          r.id = t.id;
+          r.step = t.n - 1;
+          r.slab_after = t.slab;
+          r.limiter = o.limiter;
+          r.process = o.process;
+          r.e_before = e0;
+          r.e_after = t.E;
+          r.pos_after[0] = t.x;
+          r.pos_after[1] = t.y;
+          r.pos_after[2] = t.z;
+          r.step_len = o.step_len;
+          r.edep = o.dep;
+        }
+        ++nlog;
+      }
+      cur[sp].clear();
+    }
+    for (int sp = 0; sp < 3; ++sp) cur[sp].swap(nxt[sp]);
+  }
+  for (uint32_t e = 0; e < n_events; ++e) {
+    double s = 0.0;
+    for (uint32_t k = 0; k < geo->n_slabs; ++k) s += edep[(size_t)e * geo->n_slabs + k];
+    ledger[e].edep = s;
+  }
+  if (log_n) *log_n = nlog;
+  return EMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// ems_core.hpp -- constants, counter-based RNG and small vector helpers shared
+// by the host table builder, the host test hook and the gfx950 kernels.
+//
+// The RNG abstraction follows the paper's physics section (2.2): the physics
+// run-time functions take their random numbers from an abstracted generator.
+// Here every draw is addressed by (seed, event key, track id, step, index)
+// through Philox4x32-10 (Salmon et al., SC'11), so the breadth-first GPU loop
+// reproduces per-track histories regardless of scheduling.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define EMS_HD __host__ __device__ inline
+#else
+#define EMS_HD inline
+#endif
+
+#include <math.h>
+
+namespace ems {
+
+// CODATA 2018 values; kB converts p [MeV/c] = kB * B [T] * R [mm].
+constexpr double kMe = 0.51099895;
+constexpr double kRe = 2.8179403262e-12;  // mm
+constexpr double kAlpha = 1.0 / 137.035999084;
+constexpr double kNA = 6.02214076e23;
+constexpr double kKB = 0.299792458;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+constexpr int kMaxTrials = 1000;      // rejection loops accept the last candidate
+constexpr double kSafetyMin = 1e-6;   // mm: helix track this close to a wall escapes
+constexpr uint32_t kChildBit = 0x80000000u;
+
+enum Species : int { kGamma = 0, kElectron = 1, kPositron = 2 };
+
+// process mask bits (same values as the public header)
+enum : uint32_t {
+  kPCompton = 1u << 0, kPPhot = 1u << 1, kPConv = 1u << 2, kPEIoni = 1u << 3,
+  kPEBrem = 1u << 4, kPAnnih = 1u << 5, kPCont = 1u << 6
+};
+// step-log limiter / process codes (same values as the oracle's log)
+enum : uint32_t {
+  kLimZ = 0, kLimWall = 1, kLimSafety = 2, kLimCont = 3, kLimDiscrete = 4,
+  kLimStopped = 5, kLimSubcut = 6, kLimEscapeSafety = 7
+};
+enum : uint32_t {
+  kXNone = 0, kXCompton = 1, kXPhot = 2, kXConv = 3, kXMoller = 4, kXBhabha = 5,
+  kXBrem = 6, kXAnnih = 7, kXAnnihRest = 8, kXNull = 9
+};
+
+// ---------------------------------------------------------------- Philox
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+EMS_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t a = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)b;
+    n.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)a;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// 64 bits (hi:lo) -> (0,1): top 52 bits plus one half ulp, exactly representable
+EMS_HD double to_unit(uint32_t lo, uint32_t hi) {
+  const uint64_t v = ((uint64_t)hi << 32) | lo;
+  return (double)(v >> 12) * 0x1p-52 + 0x1p-53;
+}
+
+// The draws of one track step.  Block j of Philox(key, (id_lo, id_hi, step, j))
+// yields U_{2j} (words x,y) and U_{2j+1} (words z,w).  next() hands out U_2,
+// U_3, ... in program order; U_0 and U_1 come from block 0.
+struct Draws {
+  uint32_t k0, k1, id_lo, id_hi, step;
+  uint32_t idx;     // next index for next()
+  uint32_t cached;  // block number held in buf (or ~0u)
+  U4 buf;
+
+  EMS_HD void init(uint32_t seed, uint32_t key, uint64_t id, uint32_t n) {
+    k0 = seed;
+    k1 = key;
+    id_lo = (uint32_t)id;
+    id_hi = (uint32_t)(id >> 32);
+    step = n;
+    idx = 2;
+    cached = ~0u;
+  }
+  EMS_HD double at(uint32_t i) {
+    const uint32_t blk = i >> 1;
+    if (blk != cached) {
+      buf = philox4x32_10(U4{id_lo, id_hi, step, blk}, k0, k1);
+      cached = blk;
+    }
+    return (i & 1u) ? to_unit(buf.z, buf.w) : to_unit(buf.x, buf.y);
+  }
+  EMS_HD double next() { return at(idx++); }
+  EMS_HD uint64_t child_id(uint32_t k) const {
+    const U4 r = philox4x32_10(U4{id_lo, id_hi, step, kChildBit | k}, k0, k1);
+    return (uint64_t)r.x | ((uint64_t)r.y << 32);
+  }
+};
+
+// ---------------------------------------------------------------- vectors
+struct V3 {
+  double x, y, z;
+};
+
+EMS_HD V3 unit(V3 v) {
+  const double n = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+  return V3{v.x / n, v.y / n, v.z / n};
+}
+
+// Direction with polar angle (cos t, sin t) and azimuth p about the axis u:
+// the frame is (e1, e2, u) with e2 = z^ x u / |z^ x u| and e1 = e2 x u;
+// u = +-z^ uses e1 = (+-1, 0, 0), e2 = (0, 1, 0).
+EMS_HD V3 about_axis(V3 u, double cost, double sint, double phi) {
+  const double a = sint * cos(phi), b = sint * sin(phi);
+  const double t2 = u.x * u.x + u.y * u.y;
+  if (t2 > 0.0) {
+    const double t = sqrt(t2);
+    return V3{(u.x * u.z * a - u.y * b) / t + u.x * cost,
+              (u.y * u.z * a + u.x * b) / t + u.y * cost,
+              -t * a + u.z * cost};
+  }
+  if (u.z > 0.0) return V3{a, b, cost};
+  return V3{-a, b, -cost};
+}
+
+}  // namespace ems

@@ -1,0 +1,100 @@
+// ems_device.hpp -- device-side data layout shared by the kernels and the
+// host runtime: SoA track queues, the loop-control block, kernel arguments.
+#pragma once
+#include "ems_step.hpp"
+
+namespace ems {
+
+// One species queue buffer, structure of arrays (76 bytes per track):
+// position, direction, energy in FP64; 64-bit id; event row, step, slab.
+// The six buffers (2 x 3 species) are consecutive blocks of cap * 76 bytes.
+struct Queue {
+  double *x, *y, *z, *ux, *uy, *uz, *E;
+  uint64_t* id;
+  uint32_t *ev, *n;
+  int32_t* slab;
+};
+constexpr size_t kTrackBytes = 7 * 8 + 8 + 3 * 4;
+
+EMS_HD Queue queue_view(char* base, uint64_t cap, uint32_t buf, uint32_t sp) {
+  char* b = base + (size_t)(buf * 3u + sp) * cap * kTrackBytes;
+  Queue q;
+  q.x = reinterpret_cast<double*>(b);
+  q.y = q.x + cap;
+  q.z = q.y + cap;
+  q.ux = q.z + cap;
+  q.uy = q.ux + cap;
+  q.uz = q.uy + cap;
+  q.E = q.uz + cap;
+  q.id = reinterpret_cast<uint64_t*>(q.E + cap);
+  q.ev = reinterpret_cast<uint32_t*>(q.id + cap);
+  q.n = q.ev + cap;
+  q.slab = reinterpret_cast<int32_t*>(q.n + cap);
+  return q;
+}
+
+// Loop control, written by the last block of each step launch.
+struct Ctl {
+  uint32_t cur;          // index of the current buffer (0/1)
+  uint32_t n_cur[3];     // tracks in the current queues
+  uint32_t n_next[3];    // append counters of the next queues
+  uint32_t m[3];         // tracks stepped this iteration; the rest are carried
+  uint32_t blocks_done;  // completion ticket of the running launch
+  uint32_t iteration;
+  uint32_t live;
+  uint32_t error;        // kErr* bits
+  uint32_t peak[3];
+  uint32_t pad0;
+  unsigned long long steps[3], created[3], deferred, log_n;
+};
+enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u };
+
+// Track prepared on the host for injection (slab located, direction unit).
+struct InjRec {
+  double x, y, z, ux, uy, uz, E;
+  uint64_t id;
+  uint32_t ev, sp;
+  int32_t slab;
+  uint32_t pad;
+};
+
+// Per-event ledger as laid out in the public header.
+struct LedgerDev {
+  double edep, escaped[3], killed, charged_len;
+  unsigned long long n_steps, n_created[3], n_null;
+  uint32_t n_pair, n_annih;
+};
+
+struct StepRec {
+  uint32_t event, species;
+  uint64_t id;
+  uint32_t step;
+  int32_t slab_after;
+  uint32_t limiter, process;
+  double e_before, e_after, pos[3], step_len, edep;
+};
+
+enum : uint32_t { kFlagSteplog = 1u, kFlagFullLedger = 2u, kFlagProfile = 4u };
+
+struct KArgs {
+  char* qbase;         // six queue buffers, see queue_view
+  Ctl* ctl;
+  double* edep;        // [rows][n_slabs]
+  LedgerDev* ledger;   // [rows]
+  const uint32_t* keys;
+  const double* tab;   // global copy of the tables
+  const double* zplane;
+  const uint32_t* slab_mat;
+  const MatRT* mat;
+  StepRec* log;
+  uint32_t* profile;   // [profile_cap][3]
+  uint64_t cap;        // tracks per species per buffer
+  uint64_t log_cap;
+  uint32_t profile_cap;
+  uint32_t flags;
+  uint32_t n_mat;
+  uint32_t lds_bytes;
+  StepEnv env;         // scalars; its pointers are set per block
+};
+
+}  // namespace ems

@@ -1,0 +1,465 @@
+// ems_step.hpp -- one transport step of one track.
+//
+// This is the per-thread body of the paper's stepping workflow (section 3):
+// a thread takes one track of a species' current array, moves it one step
+// (physics step limit, geometry limit, field propagation, continuous loss,
+// discrete interaction) and hands back the surviving track plus at most two
+// secondaries, which the caller appends to the next arrays.  The function is
+// pure: every random number comes from the (seed, event key, id, step) Philox
+// stream, so results do not depend on which thread or iteration runs it.
+#pragma once
+#include "ems_models.hpp"
+#include "ems_tables.hpp"
+
+namespace ems {
+
+constexpr double kInf = __builtin_huge_val();
+
+struct StepEnv {
+  const double* tab;        // [mat][kNumTables][nodes]
+  const double* zplane;     // n_slabs + 1
+  const uint32_t* slab_mat;  // n_slabs
+  const MatRT* mat;
+  uint32_t nodes, n_slabs;
+  double lnemin, dlog, inv_dlog;
+  double half_xy, bz;
+  double ecut, tcut, kcut;
+  double alpha, rho, lin;
+  uint32_t mask, seed, max_steps;
+
+  EMS_HD const double* T(uint32_t m, int t) const { return tab + ((size_t)m * kNumTables + t) * nodes; }
+};
+
+struct Trk {
+  double x, y, z, ux, uy, uz, E;
+  uint64_t id;
+  uint32_t ev, key, n;
+  int32_t slab;  // < 0: track has ended
+};
+
+struct Sec {
+  int sp;
+  double E, ux, uy, uz;
+  uint64_t id;
+};
+
+struct StepOut {
+  int nsec;
+  Sec sec[2];
+  int slab;        // slab the step was taken in (deposits, secondaries)
+  double dep;      // energy deposited in that slab
+  double escaped;  // kinetic energy of the track leaving the stack
+  double killed;   // kinetic energy removed by the watchdog
+  double clen;     // charged path length
+  int pair, annih, null;
+  uint32_t limiter, process;
+  double step_len;
+};
+
+struct Bin {
+  int j;
+  double u;
+};
+
+EMS_HD Bin bin_of(const StepEnv& e, double lnE) {
+  const double x = (lnE - e.lnemin) * e.inv_dlog;
+  double f = floor(x);
+  const double top = (double)(e.nodes - 2);
+  f = f < 0.0 ? 0.0 : (f > top ? top : f);
+  int j = (int)f;  // clamped again as an integer: a NaN never indexes outside
+  j = j < 0 ? 0 : (j > (int)e.nodes - 2 ? (int)e.nodes - 2 : j);
+  double u = x - (double)j;
+  u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+  return Bin{j, u};
+}
+EMS_HD double lerp(const double* f, Bin b) { return f[b.j] + b.u * (f[b.j + 1] - f[b.j]); }
+
+// largest node j <= jhi with R_j <= r (clamped to the last bin), then the
+// exact inverse of the range interpolant
+EMS_HD double inverse_range(const StepEnv& e, const double* R, double r, int jhi) {
+  int lo = 0, hi = jhi;
+  if (hi > (int)e.nodes - 1) hi = (int)e.nodes - 1;
+  if (r >= R[hi]) {
+    lo = hi;
+  } else if (r >= R[0]) {
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (R[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+  }
+  if (lo > (int)e.nodes - 2) lo = (int)e.nodes - 2;
+  return exp(e.lnemin + lo * e.dlog + e.dlog * (r - R[lo]) / (R[lo + 1] - R[lo]));
+}
+
+// energy lost over path s by a charged track of kinetic energy T
+EMS_HD double cont_loss(const StepEnv& e, const double* R, int jT, double T, double S, double Rt, double s) {
+  double L;
+  if (s >= Rt) L = T;
+  else if (s < e.lin * Rt) L = s * S;
+  else L = T - inverse_range(e, R, Rt - s, jT + 1);
+  return (T - L < e.ecut) ? T : L;
+}
+
+EMS_HD void land_on_plane(const StepEnv& e, Trk& t, StepOut& o) {
+  if (t.uz > 0.0) {
+    t.z = e.zplane[t.slab + 1];
+    t.slab += 1;
+  } else {
+    t.z = e.zplane[t.slab];
+    t.slab -= 1;
+  }
+  if (t.slab < 0 || t.slab >= (int)e.n_slabs) {
+    o.escaped += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+  }
+}
+
+EMS_HD double dist_to_planes(const StepEnv& e, const Trk& t) {
+  if (t.uz > 0.0) return (e.zplane[t.slab + 1] - t.z) / t.uz;
+  if (t.uz < 0.0) return (e.zplane[t.slab] - t.z) / t.uz;
+  return kInf;
+}
+EMS_HD double dist_to_walls(const StepEnv& e, const Trk& t) {
+  const double h = e.half_xy;
+  const double sx = t.ux > 0.0 ? (h - t.x) / t.ux : (t.ux < 0.0 ? (-h - t.x) / t.ux : kInf);
+  const double sy = t.uy > 0.0 ? (h - t.y) / t.uy : (t.uy < 0.0 ? (-h - t.y) / t.uy : kInf);
+  return sx < sy ? sx : sy;
+}
+
+// hand the interaction outcome to the caller: secondaries below the tracking
+// cut (gamma, e-) are deposited where they are born, the rest are pushed
+EMS_HD void put_sec(Sec& s, const Outcome& oc, int k, Draws& r) {
+  s.sp = oc.sp[k];
+  s.E = oc.e[k];
+  s.ux = oc.u[k].x;
+  s.uy = oc.u[k].y;
+  s.uz = oc.u[k].z;
+  s.id = r.child_id((uint32_t)k);
+}
+EMS_HD void settle(const StepEnv& e, Trk& t, const Outcome& oc, Draws& r, StepOut& o) {
+  // (constant indices only: keeps the small arrays in registers)
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (k >= oc.n) break;
+    if (oc.sp[k] != kPositron && oc.e[k] < e.ecut) {
+      o.dep += oc.e[k];
+      continue;
+    }
+    if (o.nsec == 0) put_sec(o.sec[0], oc, k, r);
+    else put_sec(o.sec[1], oc, k, r);
+    o.nsec += 1;
+  }
+  if (oc.survives) {
+    t.E = oc.e_parent;
+    t.ux = oc.u_parent.x;
+    t.uy = oc.u_parent.y;
+    t.uz = oc.u_parent.z;
+  } else {
+    t.E = 0.0;
+    t.slab = -1;
+  }
+}
+
+EMS_HD void gamma_step(const StepEnv& e, Trk& t, StepOut& o) {
+  if (t.E < e.ecut) {
+    o.dep += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+    o.limiter = kLimSubcut;
+    return;
+  }
+  const uint32_t m = e.slab_mat[t.slab];
+  const double E = t.E;
+  const Bin b = bin_of(e, log(E));
+  const double sc = lerp(e.T(m, tCompt), b);
+  const double sp = lerp(e.T(m, tPhot), b);
+  const double sv = E > 2.0 * kMe ? lerp(e.T(m, tConv), b) : 0.0;
+  const double sig = sc + sp + sv;
+  const double sz = dist_to_planes(e, t), sw = dist_to_walls(e, t);
+  const double sg = sz <= sw ? sz : sw;
+  Draws r;
+  r.init(e.seed, t.key, t.id, t.n);
+  const double sphys = sig > 0.0 ? -log(r.at(0)) / sig : kInf;
+  if (sg <= sphys) {
+    t.x += sg * t.ux;
+    t.y += sg * t.uy;
+    t.z += sg * t.uz;
+    o.step_len = sg;
+    if (sz <= sw) {
+      o.limiter = kLimZ;
+      land_on_plane(e, t, o);
+    } else {
+      o.limiter = kLimWall;
+      o.escaped += t.E;
+      t.E = 0.0;
+      t.slab = -1;
+    }
+    return;
+  }
+  t.x += sphys * t.ux;
+  t.y += sphys * t.uy;
+  t.z += sphys * t.uz;
+  o.step_len = sphys;
+  o.limiter = kLimDiscrete;
+  const double pick = r.at(1) * sig;
+  const V3 u{t.ux, t.uy, t.uz};
+  Outcome oc;
+  if (pick < sc) {
+    o.process = kXCompton;
+    compton(E, u, r, oc);
+  } else if (pick < sc + sp) {
+    o.process = kXPhot;
+    photo(E, u, oc);
+  } else {
+    o.process = kXConv;
+    pair(e.mat[m], E, u, r, oc);
+    o.pair += 1;
+  }
+  settle(e, t, oc, r, o);
+}
+
+// discrete e-/e+ processes: table id and threshold (cross section is zero at
+// and below it), in selection order
+struct LeptonProcs {
+  int n;
+  int tab[3];
+  double th[3];
+  uint32_t code[3];
+};
+EMS_HD LeptonProcs lepton_procs(const StepEnv& e, bool positron) {
+  LeptonProcs p;
+  if (positron) {
+    p.n = 3;
+    p.tab[0] = tBhabha; p.th[0] = e.tcut; p.code[0] = kXBhabha;
+    p.tab[1] = tBrem;   p.th[1] = e.kcut; p.code[1] = kXBrem;
+    p.tab[2] = tAnnih;  p.th[2] = 0.0;    p.code[2] = kXAnnih;
+  } else {
+    p.n = 2;
+    p.tab[0] = tMoller; p.th[0] = 2.0 * e.tcut; p.code[0] = kXMoller;
+    p.tab[1] = tBrem;   p.th[1] = e.kcut;       p.code[1] = kXBrem;
+    p.tab[2] = tBrem;   p.th[2] = 0.0;          p.code[2] = kXNone;
+  }
+  return p;
+}
+
+// right-continuous discrete total (process counted at its threshold)
+EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, double E) {
+  const Bin b = bin_of(e, log(E));
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (i < p.n && E >= p.th[i]) s += lerp(e.T(m, p.tab[i]), b);
+  return s;
+}
+
+// maximum of the discrete total over [a, b]: endpoints, grid nodes and
+// thresholds inside; when a is the tracking cut the nodes below b come from
+// the running-maximum table
+EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p, bool positron, double a,
+                             double b, double lnb, bool from_cut) {
+  double best = total_upper(e, m, p, a);
+  const double vb = total_upper(e, m, p, b);
+  best = vb > best ? vb : best;
+  const double xb = (lnb - e.lnemin) * e.inv_dlog;
+  int jb = (int)ceil(xb) - 1;
+  jb = jb > (int)e.nodes - 1 ? (int)e.nodes - 1 : jb;
+  if (jb >= 0) {
+    if (from_cut) {
+      const double v = e.T(m, positron ? tPMep : tPMem)[jb];
+      best = v > best ? v : best;
+    } else {
+      const double xa = (log(a) - e.lnemin) * e.inv_dlog;
+      int j = (int)floor(xa) + 1;
+      j = j < 0 ? 0 : j;
+      for (; j <= jb; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          if (i < p.n) s += e.T(m, p.tab[i])[j];
+        best = s > best ? s : best;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i < p.n && p.th[i] > a && p.th[i] < b) {
+      const double v = total_upper(e, m, p, p.th[i]);
+      best = v > best ? v : best;
+    }
+  }
+  return best;
+}
+
+EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
+  Draws r;
+  r.init(e.seed, t.key, t.id, t.n);
+  Outcome oc;
+  const double T = t.E;
+  if (T < e.ecut) {
+    o.dep += T;
+    o.limiter = kLimSubcut;
+    t.E = 0.0;
+    if (positron) {
+      o.process = kXAnnihRest;
+      annihilate_at_rest(r, oc);
+      o.annih += 1;
+      settle(e, t, oc, r, o);
+    }
+    t.slab = -1;
+    return;
+  }
+  const bool field = e.bz != 0.0;
+  const double sz = dist_to_planes(e, t);
+  double sg;
+  bool zlim;
+  if (field) {
+    const double ax = fabs(t.x), ay = fabs(t.y);
+    const double dw = e.half_xy - (ax > ay ? ax : ay);
+    if (dw < kSafetyMin) {
+      o.limiter = kLimEscapeSafety;
+      o.escaped += T;
+      t.E = 0.0;
+      t.slab = -1;
+      return;
+    }
+    zlim = sz <= dw;
+    sg = zlim ? sz : dw;
+  } else {
+    const double sw = dist_to_walls(e, t);
+    zlim = sz <= sw;
+    sg = zlim ? sz : sw;
+  }
+  const uint32_t m = e.slab_mat[t.slab];
+  const bool cont = (e.mask & kPCont) != 0;
+  const double lnT = log(T);
+  const Bin b = bin_of(e, lnT);
+  const double* Rt = e.T(m, positron ? tRep : tRem);
+  double S = 0.0, R = kInf, scont = kInf;
+  if (cont) {
+    S = lerp(e.T(m, positron ? tSep : tSem), b);
+    R = lerp(Rt, b);
+    scont = R <= e.rho ? R : e.alpha * R + e.rho * (1.0 - e.alpha) * (2.0 - e.rho / R);
+  }
+  const double smax = scont <= sg ? scont : sg;
+  double elo = T;
+  if (cont) {
+    elo = T - cont_loss(e, Rt, b.j, T, S, R, smax);
+    const double lin = e.lin * R;
+    if (smax >= lin) {
+      const double e2 = T - lin * S;
+      elo = e2 < elo ? e2 : elo;
+    }
+  }
+  const bool from_cut = !(elo > e.ecut);
+  const double a = from_cut ? e.ecut : elo;
+  const LeptonProcs pl = lepton_procs(e, positron);
+  const double bound = thinning_bound(e, m, pl, positron, a, T, lnT, from_cut);
+  const double sphys = bound > 0.0 ? -log(r.at(0)) / bound : kInf;
+  double s;
+  uint32_t lim;
+  if (sphys < smax) {
+    s = sphys;
+    lim = kLimDiscrete;
+  } else if (sg <= scont) {
+    s = sg;
+    lim = zlim ? kLimZ : (field ? kLimSafety : kLimWall);
+  } else {
+    s = scont;
+    lim = kLimCont;
+  }
+  if (field) {
+    const double p = sqrt(T * (T + 2.0 * kMe));
+    const double kap = (positron ? kKB : -kKB) * e.bz / p;
+    const double ph = kap * s;
+    const double sp = sin(ph), cp = cos(ph), h = sin(0.5 * ph);
+    const double omc = 2.0 * h * h;
+    const double ux = t.ux, uy = t.uy;
+    t.x += (ux * sp + uy * omc) / kap;
+    t.y += (uy * sp - ux * omc) / kap;
+    t.z += t.uz * s;
+    t.ux = ux * cp + uy * sp;
+    t.uy = -ux * sp + uy * cp;
+  } else {
+    t.x += s * t.ux;
+    t.y += s * t.uy;
+    t.z += s * t.uz;
+  }
+  o.step_len = s;
+  o.clen += s;
+  const double dE = cont ? cont_loss(e, Rt, b.j, T, S, R, s) : 0.0;
+  o.dep += dE;
+  const double Tp = T - dE;
+  t.E = Tp;
+  o.limiter = lim;
+  if (Tp == 0.0) {
+    o.limiter = kLimStopped;
+    if (positron) {
+      o.process = kXAnnihRest;
+      annihilate_at_rest(r, oc);
+      o.annih += 1;
+      settle(e, t, oc, r, o);
+    }
+    t.slab = -1;
+    return;
+  }
+  if (lim == kLimZ) {
+    land_on_plane(e, t, o);
+    return;
+  }
+  if (lim == kLimWall) {
+    o.escaped += Tp;
+    t.E = 0.0;
+    t.slab = -1;
+    return;
+  }
+  if (lim != kLimDiscrete) return;
+  const double pick = r.at(1) * bound;
+  const Bin bp = bin_of(e, log(Tp));
+  double cum = 0.0;
+  uint32_t code = kXNull;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= pl.n || code != kXNull) continue;
+    if (Tp > pl.th[i]) cum += lerp(e.T(m, pl.tab[i]), bp);
+    if (pick < cum) code = pl.code[i];
+  }
+  if (code == kXNull) {
+    o.process = kXNull;
+    o.null += 1;
+    return;
+  }
+  o.process = code;
+  const V3 u{t.ux, t.uy, t.uz};
+  switch (code) {
+    case kXMoller: moller(Tp, e.tcut, u, r, oc); break;
+    case kXBhabha: bhabha(Tp, e.tcut, u, r, oc); break;
+    case kXBrem: brem(e.mat[m], Tp, e.kcut, u, r, oc); break;
+    default:
+      annihilate(Tp, u, r, oc);
+      o.annih += 1;
+      break;
+  }
+  settle(e, t, oc, r, o);
+}
+
+// One full step of a track of species sp: dispatch, step counter, watchdog.
+EMS_HD void take_step(const StepEnv& e, int sp, Trk& t, StepOut& o) {
+  o.nsec = 0;
+  o.slab = t.slab;
+  o.dep = o.escaped = o.killed = o.clen = o.step_len = 0.0;
+  o.pair = o.annih = o.null = 0;
+  o.limiter = 0;
+  o.process = kXNone;
+  if (sp == kGamma) gamma_step(e, t, o);
+  else lepton_step(e, sp == kPositron, t, o);
+  t.n += 1;
+  if (t.slab >= 0 && t.n >= e.max_steps) {
+    o.killed += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+  }
+}
+
+}  // namespace ems

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP transport loop (through the C ABI) against the FP64
+oracle on the same seeded inputs.
+
+FP64 bar: step-by-step history equality on tiny inputs (energies to 1e-9
+relative, positions to 1e-7 mm), identical integer counts, per-event energy
+conservation to 1e-9, per-slab deposits equal to 1e-9 on small workloads,
+and at the full 10^4-event workload exact agreement on oracle-sampled events
+plus per-layer means within 3 sigma + 0.5% of the oracle's sample.
+"""
+import numpy as np
+import pytest
+
+import ems_inputs as I
+from parity_util import compare_logs, ledger_residual, tiny_mixed_primaries
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_15445_amd as E
+    E.lib()
+    return E
+
+
+def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
+            blocks=0):
+    c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
+                      profile_capacity=profile_cap, launch_blocks=blocks)
+    t = E.Transport(c, geo)
+    if keys is not None:
+        t.set_event_keys(keys)
+    t.enqueue(prim)
+    t.run()
+    out = dict(edep=t.edep(), ledger=t.ledger(), stats=t.stats())
+    if log_cap:
+        out["log"], out["n_log"] = t.steplog()
+    if profile_cap:
+        out["profile"], out["n_iter"] = t.profile()
+    t.close()
+    return out
+
+
+@pytest.mark.parametrize("bz", [0.0, 3.8])
+def test_history_parity_tiny(E, oracle_mod, bz):
+    print(f"history parity bz={bz}", flush=True)
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=11, bz_tesla=bz)
+    prim = tiny_mixed_primaries()
+    g = run_gpu(E, geo, cfg, prim, 48, flags=E.F_STEPLOG | E.F_FULL_LEDGER, log_cap=400000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, log_cap=400000)
+    assert g["n_log"] == r["n_log"]
+    compare_logs(g["log"], r["log"], e_rtol=1e-9, pos_atol=1e-7)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(g["ledger"][f], r["ledger"][f]), f
+    assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
+def test_random_tracks_everywhere(E, oracle_mod):
+    print("random tracks", flush=True)
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=5, bz_tesla=3.8)
+    prim = I.random_tracks(600, 20, geo, 1e-3, 50.0, seed=8)
+    g = run_gpu(E, geo, cfg, prim, 20, flags=E.F_STEPLOG, log_cap=400000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=20, log_cap=400000)
+    compare_logs(g["log"], r["log"], e_rtol=1e-9, pos_atol=1e-7)
+
+
+def test_1gev_32_events_all_slabs(E, oracle_mod):
+    print("1 GeV x 32", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    g = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER | E.F_PROFILE, profile_cap=20000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, profile_cap=20000)
+    assert np.array_equal(g["ledger"]["n_steps"], r["ledger"]["n_steps"])
+    assert np.array_equal(g["ledger"]["n_created"], r["ledger"]["n_created"])
+    assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+    # breadth-first iteration profile equals the oracle's bookkeeping
+    assert g["n_iter"] == r["n_iter"]
+    assert np.array_equal(g["profile"].astype(np.uint64), r["profile"])
+    assert g["stats"]["steps"] == [int(x) for x in r["profile"].sum(axis=0)]
+
+
+def test_capacity_deferral_gives_identical_results(E):
+    print("deferral", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    a = run_gpu(E, geo, cfg, prim[:8], 8, capacity=1 << 20)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, capacity=256)
+    assert b["stats"]["deferred"] > 0 and a["stats"]["deferred"] == 0
+    assert max(b["stats"]["peak_live"]) <= 256
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(a["stats"]["steps"], b["stats"]["steps"])
+
+
+def test_event_keys_and_rerun(E, oracle_mod):
+    print("event keys / rerun", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    p = prim[:3].copy()
+    keys = np.array([900, 17, 4242], dtype=np.uint32)
+    c = E.make_config(cfg, 3)
+    t = E.Transport(c, geo)
+    t.set_event_keys(keys)
+    t.enqueue(p)
+    t.run()
+    first = t.edep()
+    t.reset()
+    t.enqueue(p)
+    t.run()
+    second = t.edep()
+    t.close()
+    r = oracle_mod.Oracle(geo, cfg).run(p, n_events=3, event_keys=keys)
+    assert np.allclose(first, r["edep"], rtol=1e-9, atol=1e-9)
+    assert np.allclose(first, second, rtol=1e-12, atol=1e-12)
+
+
+def test_invalid_enqueue_is_all_or_nothing(E, oracle_mod):
+    print("invalid enqueue", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    c = E.make_config(cfg, 4, track_capacity=1024)
+    t = E.Transport(c, geo)
+    bad = prim[:4].copy()
+    bad["ekin"][3] = np.nan
+    with pytest.raises(E.EmsError) as ei:
+        t.enqueue(bad)
+    assert ei.value.code == E.E_INVALID
+    too_many = I.beam(2000, I.ELECTRON, 10.0)
+    too_many["event"] = 0
+    with pytest.raises(E.EmsError) as ei:
+        t.enqueue(too_many)
+    assert ei.value.code == E.E_CAPACITY
+    t.enqueue(prim[:4])
+    t.run()
+    got = t.edep()
+    t.close()
+    r = oracle_mod.Oracle(geo, cfg).run(prim[:4])
+    assert np.allclose(got, r["edep"], rtol=1e-9, atol=1e-9)
+
+
+def test_empty_run_and_edges(E):
+    print("empty run", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    c = E.make_config(cfg, 2)
+    t = E.Transport(c, geo)
+    t.run()
+    assert np.all(t.edep() == 0)
+    # a primary on the back face moving out, and one below the tracking cut
+    p = I.primaries(2)
+    p["event"] = [0, 1]
+    p["species"] = [I.ELECTRON, I.POSITRON]
+    p["ekin"] = [5.0, 5e-4]
+    p["pos"] = [[0, 0, geo.z_mm[-1]], [0, 0, 1.0]]
+    p["dir"] = [[0, 0, 1.0], [0, 0, 1.0]]
+    t.enqueue(p)
+    t.run()
+    L = t.ledger()
+    e = t.edep()
+    t.close()
+    assert L["escaped"][0][1] == 5.0 and e[0].sum() == 0.0
+    assert L["n_annih"][1] == 1 and abs(e[1].sum() + L["escaped"][1].sum() - (5e-4 + 2 * 0.51099895)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k"])
+def test_full_size_workload_sampled(E, oracle_mod, name):
+    """The benchmark workload in the benchmark's launch configuration: every
+    event conserves energy, oracle-sampled events agree exactly, per-layer
+    means agree with the oracle sample within 3 sigma + 0.5%."""
+    print(f"full size {name}", flush=True)
+    geo, cfg, prim = I.workload(name)
+    n = len(prim)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 24)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(n, 24, replace=False))
+    p = prim[sample].copy()
+    p["event"] = np.arange(len(sample))
+    r = oracle_mod.Oracle(geo, cfg).run(p, n_events=len(sample), event_keys=sample.astype(np.uint32))
+    assert np.allclose(g["edep"][sample], r["edep"], rtol=1e-8, atol=1e-8)
+    # per-layer statistics
+    gl = g["edep"].reshape(n, 50, 2).sum(axis=2)
+    ol = r["edep"].reshape(len(sample), 50, 2).sum(axis=2)
+    mg, mo = gl.mean(axis=0), ol.mean(axis=0)
+    sig = np.sqrt(gl.var(axis=0) / n + ol.var(axis=0) / len(sample))
+    assert np.all(np.abs(mg - mo) <= 3 * sig + 0.005 * np.abs(mo) + 1e-9)
