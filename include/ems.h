@@ -97,7 +97,7 @@ typedef struct {
   uint32_t max_steps_per_track;  /* watchdog (>= 1)                          */
   uint32_t seed;                 /* Philox key word 0                        */
   uint32_t max_events;           /* tally rows (>= 1)                        */
-  uint64_t track_capacity;       /* tracks per species per queue buffer      */
+  uint64_t track_capacity;       /* tracks per species per queue, 64..2^28 */
   uint32_t steps_per_launch;     /* iterations enqueued between status reads */
   uint32_t launch_blocks;        /* step-kernel grid (0 = library default)   */
   uint64_t steplog_capacity;     /* records kept when EMS_F_STEPLOG is set   */

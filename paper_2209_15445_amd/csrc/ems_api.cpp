@@ -20,7 +20,7 @@
 namespace ems {
 hipError_t launch_step(const KArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
-hipError_t launch_plan(const KArgs& a, hipStream_t s);
+hipError_t launch_census(const KArgs& a, hipStream_t s);
 hipError_t set_step_lds(uint32_t bytes);
 }  // namespace ems
 
@@ -77,8 +77,8 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
     return fail(EMS_E_INVALID, "bad step-function parameters");
   if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
   if (c->max_steps_per_track < 1 || c->max_events < 1) return fail(EMS_E_INVALID, "max_steps and max_events >= 1");
-  if (c->track_capacity < 64 || c->track_capacity > (1ull << 31))
-    return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^31]");
+  if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
+    return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
   return EMS_OK;
 }
 
@@ -385,7 +385,7 @@ ems_status ems_run(ems_ctx* c) {
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   const auto t0 = std::chrono::steady_clock::now();
   const uint32_t K = c->cfg.steps_per_launch ? c->cfg.steps_per_launch : 16;
-  HIPCHK(c, launch_plan(c->args, c->stream));
+  HIPCHK(c, launch_census(c->args, c->stream));
   uint64_t launches = 0;
   double kms = 0.0;
   for (;;) {
@@ -472,7 +472,10 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   Ctl fresh{};
   fresh.cur = c->pin_ctl->cur;
-  for (int s = 0; s < 3; ++s) fresh.n_cur[s] = c->pin_ctl->n_cur[s];
+  for (int s = 0; s < 3; ++s) {
+    fresh.n_home[s] = c->pin_ctl->n_home[s];
+    fresh.n_sec[s] = c->pin_ctl->n_sec[s];
+  }
   *c->pin_ctl = fresh;
   HIPCHK(c, hipMemcpyAsync(c->ws + L.ctl, c->pin_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

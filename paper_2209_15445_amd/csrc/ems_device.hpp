@@ -34,16 +34,27 @@ EMS_HD Queue queue_view(char* base, uint64_t cap, uint32_t buf, uint32_t sp) {
 }
 
 // Loop control, written by the last block of each step launch.
+//
+// Each next-queue buffer of capacity cap has two regions: survivors and
+// carried tracks of that species fill it from the bottom (home region), new
+// secondaries from the top (position cap-1-s for secondary slot s).  The
+// secondaries of species q may use at most cap - n_cur[q] slots, which leaves
+// room for every survivor, so a step whose secondaries do not fit is simply
+// not taken: the track is carried unchanged and stepped again later (its
+// random numbers depend only on its id and step count).
 struct Ctl {
-  uint32_t cur;          // index of the current buffer (0/1)
-  uint32_t n_cur[3];     // tracks in the current queues
-  uint32_t n_next[3];    // append counters of the next queues
-  uint32_t m[3];         // tracks stepped this iteration; the rest are carried
-  uint32_t blocks_done;  // completion ticket of the running launch
+  uint32_t cur;           // index of the current buffer (0/1)
+  uint32_t n_home[3];     // current queues: tracks in the home region
+  uint32_t n_sec[3];      // current queues: tracks in the secondary region
+  uint32_t next_home[3];  // append counters of the next queues
+  uint32_t next_sec[3];
+  uint32_t blocks_done;   // completion ticket of the running launch
   uint32_t iteration;
-  uint32_t live;
-  uint32_t error;        // kErr* bits
+  uint32_t live;          // tracks in the current queues (after the swap)
+  uint32_t error;         // kErr* bits
   uint32_t peak[3];
+  uint32_t commits;       // steps taken in the running launch
+  uint32_t carried;       // live tracks carried unstepped in the running launch
   uint32_t pad0;
   unsigned long long steps[3], created[3], deferred, log_n;
 };

@@ -11,9 +11,11 @@
 //  - appends are aggregated per wave (ballot + popcount prefix, one atomic
 //    per wave and species);
 //  - cross-section tables, slab planes and materials are staged in LDS;
-//  - the last block to finish swaps the queues and decides how many tracks
-//    of each species fit in the next step (the rest are carried unchanged),
-//    so a chain of launches needs no host round trip.
+//  - secondaries are reserved against a per-species limit that always leaves
+//    room for every survivor; a track whose secondaries do not fit is carried
+//    unstepped, so a full queue defers work instead of losing it;
+//  - the last block to finish swaps the queues, so a chain of launches needs
+//    no host round trip.
 #include <hip/hip_runtime.h>
 
 #include "ems_device.hpp"
@@ -64,41 +66,13 @@ __device__ inline void store_track(const Queue& q, uint32_t i, const Trk& t) {
   q.slab[i] = t.slab;
 }
 
-// How many tracks of each species can be stepped so that every next queue
-// can hold the worst case: stepped tracks yield at most (A[q][s]) tracks of
-// species q, carried tracks stay where they are.
-__device__ void plan_iteration(Ctl* c, uint64_t cap) {
-  const int A[3][3] = {{1, 1, 2}, {1, 2, 1}, {1, 0, 1}};
-  const uint64_t n[3] = {c->n_cur[0], c->n_cur[1], c->n_cur[2]};
-  double f = 1.0;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int64_t grow = (int64_t)(A[q][0] * n[0] + A[q][1] * n[1] + A[q][2] * n[2]) - (int64_t)n[q];
-    if (grow > 0) {
-      const double fq = (double)(cap - n[q]) / (double)grow;
-      f = fq < f ? fq : f;
-    }
-  }
-  uint64_t m[3];
-  for (int attempt = 0; attempt < 64; ++attempt) {
-#pragma unroll
-    for (int s = 0; s < 3; ++s) m[s] = f >= 1.0 ? n[s] : (uint64_t)floor(f * (double)n[s]);
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const uint64_t w = (n[q] - m[q]) + A[q][0] * m[0] + A[q][1] * m[1] + A[q][2] * m[2];
-      ok = ok && (w <= cap);
-    }
-    if (ok) break;
-    f *= 0.99;
-    if (attempt == 63) m[0] = m[1] = m[2] = 0;
-  }
-  uint64_t live = n[0] + n[1] + n[2];
-  if (live > 0 && m[0] + m[1] + m[2] == 0) c->error |= kErrStall;
-  for (int s = 0; s < 3; ++s) c->m[s] = (uint32_t)m[s];
-  c->deferred += (n[0] - m[0]) + (n[1] - m[1]) + (n[2] - m[2]);
-  c->live = (uint32_t)live;
+// position of the idx-th track of a queue with `home` tracks in the bottom
+// region (the rest are in the top region, counted downwards)
+__device__ inline uint32_t queue_pos(uint32_t idx, uint32_t home, uint64_t cap) {
+  return idx < home ? idx : (uint32_t)(cap - 1 - (idx - home));
 }
+
+__device__ inline void store_dead(const Queue& q, uint32_t i) { q.slab[i] = -1; }
 
 }  // namespace
 
@@ -106,8 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
   extern __shared__ double lds[];
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
-  const uint32_t n0 = ctl->n_cur[0], n1 = ctl->n_cur[1], n2 = ctl->n_cur[2];
-  const uint32_t m0 = ctl->m[0], m1 = ctl->m[1], m2 = ctl->m[2];
+  const uint32_t h0 = ctl->n_home[0], h1 = ctl->n_home[1], h2 = ctl->n_home[2];
+  const uint32_t n0 = h0 + ctl->n_sec[0], n1 = h1 + ctl->n_sec[1], n2 = h2 + ctl->n_sec[2];
   const uint32_t ntot = n0 + n1 + n2;
   const uint32_t need = (ntot + kBlock - 1) / kBlock;
   const bool work = blockIdx.x < need && ctl->error == 0;
@@ -132,86 +106,130 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
     const uint32_t nxt = cur ^ 1u;
     const bool full = (a.flags & kFlagFullLedger) != 0;
     const bool logging = (a.flags & kFlagSteplog) != 0;
+    // secondary slots per species that leave room for all survivors
+    const uint32_t lim0 = (uint32_t)(a.cap - n0), lim1 = (uint32_t)(a.cap - n1), lim2 = (uint32_t)(a.cap - n2);
 
     for (uint32_t base = blockIdx.x * kBlock; base < ntot; base += gridDim.x * kBlock) {
       const uint32_t i = base + threadIdx.x;
       const bool active = i < ntot;
       int sp = 0;
-      uint32_t idx = i, msp = m0;
+      uint32_t idx = i, home = h0;
       if (i >= n0 + n1) {
         sp = 2;
         idx = i - n0 - n1;
-        msp = m2;
+        home = h2;
       } else if (i >= n0) {
         sp = 1;
         idx = i - n0;
-        msp = m1;
+        home = h1;
       }
+      const uint32_t pos = queue_pos(idx, home, a.cap);
+      const Queue src = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
       Trk t;
       StepOut o;
       o.nsec = 0;
       o.dep = o.escaped = o.killed = o.clen = 0.0;
       o.pair = o.annih = o.null = 0;
-      bool stepped = false;
+      bool live_in = false;
       double e_before = 0.0;
       if (active) {
-        const Queue q = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
-        t.x = q.x[idx];
-        t.y = q.y[idx];
-        t.z = q.z[idx];
-        t.ux = q.ux[idx];
-        t.uy = q.uy[idx];
-        t.uz = q.uz[idx];
-        t.E = q.E[idx];
-        t.id = q.id[idx];
-        t.ev = q.ev[idx];
-        t.n = q.n[idx];
-        t.slab = q.slab[idx];
-        t.key = a.keys[t.ev];
-        if (idx < msp) {
-          e_before = t.E;
-          take_step(env, sp, t, o);
-          stepped = true;
-        }
+        t.slab = src.slab[pos];
+        live_in = t.slab >= 0;  // slots of refused secondaries hold slab -1
       }
-      const bool alive = active && t.slab >= 0;
+      if (live_in) {
+        t.x = src.x[pos];
+        t.y = src.y[pos];
+        t.z = src.z[pos];
+        t.ux = src.ux[pos];
+        t.uy = src.uy[pos];
+        t.uz = src.uz[pos];
+        t.E = src.E[pos];
+        t.id = src.id[pos];
+        t.ev = src.ev[pos];
+        t.n = src.n[pos];
+        t.key = a.keys[t.ev];
+        e_before = t.E;
+        take_step(env, sp, t, o);
+      }
 
-      // append survivors and secondaries to the next queues
+      // reserve secondary slots (top regions); the step commits only if all
+      // of this track's secondaries fit
+      uint32_t d[3];
 #pragma unroll
-      for (int qs = 0; qs < 3; ++qs) {
-        uint32_t cnt = (alive && sp == qs) ? 1u : 0u;
-        const bool s0 = o.nsec > 0 && o.sec[0].sp == qs, s1 = o.nsec > 1 && o.sec[1].sp == qs;
-        cnt += (uint32_t)s0 + (uint32_t)s1;
-        const uint32_t slot0 = wave_reserve(&ctl->n_next[qs], cnt);
-        if (cnt == 0) continue;
-        const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)qs);
-        uint32_t slot = slot0;
-        if (slot + cnt > a.cap) {
-          atomicOr(&ctl->error, kErrOverflow);
-          continue;
-        }
-        if (alive && sp == qs) store_track(dq, slot++, t);
+      for (int q = 0; q < 3; ++q)
+        d[q] = (o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
+      uint32_t slot[3];
+      bool commit = live_in;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        slot[q] = wave_reserve(&ctl->next_sec[q], d[q]);
+        const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
+        if (d[q] && slot[q] + d[q] > lim) commit = false;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (!d[q]) continue;
+        const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
+        const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+        uint32_t s = slot[q];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          if (!(k < o.nsec && o.sec[k].sp == qs)) continue;
-          Trk c;
-          c.x = t.x;
-          c.y = t.y;
-          c.z = t.z;
-          c.ux = o.sec[k].ux;
-          c.uy = o.sec[k].uy;
-          c.uz = o.sec[k].uz;
-          c.E = o.sec[k].E;
-          c.id = o.sec[k].id;
-          c.ev = t.ev;
-          c.n = 0;
-          c.slab = o.slab;
-          store_track(dq, slot++, c);
+          if (!(k < o.nsec && o.sec[k].sp == q)) continue;
+          if (s < lim) {
+            const uint32_t p = (uint32_t)(a.cap - 1 - s);
+            if (commit) {
+              Trk c;
+              c.x = t.x;
+              c.y = t.y;
+              c.z = t.z;
+              c.ux = o.sec[k].ux;
+              c.uy = o.sec[k].uy;
+              c.uz = o.sec[k].uz;
+              c.E = o.sec[k].E;
+              c.id = o.sec[k].id;
+              c.ev = t.ev;
+              c.n = 0;
+              c.slab = o.slab;
+              store_track(dq, p, c);
+            } else {
+              store_dead(dq, p);
+            }
+          }
+          ++s;
         }
       }
 
-      // tallies
-      if (stepped) {
+      // home region: survivors of committed steps, or the unstepped track
+      const bool carry = live_in && !commit;
+      const bool keep = carry || (commit && t.slab >= 0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const uint32_t hs = wave_reserve(&ctl->next_home[q], (keep && sp == q) ? 1u : 0u);
+        if (keep && sp == q) {
+          const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+          if (hs >= a.cap) {
+            atomicOr(&ctl->error, kErrOverflow);
+          } else if (carry) {
+            // the current buffer is untouched during the launch
+            dq.x[hs] = src.x[pos];
+            dq.y[hs] = src.y[pos];
+            dq.z[hs] = src.z[pos];
+            dq.ux[hs] = src.ux[pos];
+            dq.uy[hs] = src.uy[pos];
+            dq.uz[hs] = src.uz[pos];
+            dq.E[hs] = src.E[pos];
+            dq.id[hs] = src.id[pos];
+            dq.ev[hs] = src.ev[pos];
+            dq.n[hs] = src.n[pos];
+            dq.slab[hs] = src.slab[pos];
+          } else {
+            store_track(dq, hs, t);
+          }
+        }
+      }
+
+      // tallies of committed steps
+      if (commit) {
         if (o.dep != 0.0) atomicAdd(&a.edep[(size_t)t.ev * env.n_slabs + o.slab], o.dep);
         LedgerDev& L = a.ledger[t.ev];
         if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
@@ -223,13 +241,13 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
           if (o.clen != 0.0) atomicAdd(&L.charged_len, o.clen);
           if (o.null) atomicAdd(&L.n_null, 1ull);
 #pragma unroll
-          for (int k = 0; k < 2; ++k)
-            if (k < o.nsec) atomicAdd(&L.n_created[o.sec[k].sp], 1ull);
+          for (int q = 0; q < 3; ++q)
+            if (d[q]) atomicAdd(&L.n_created[q], (unsigned long long)d[q]);
         }
         if (logging) {
-          const unsigned long long slot = atomicAdd(&ctl->log_n, 1ull);
-          if (slot < a.log_cap) {
-            StepRec& r = a.log[slot];
+          const unsigned long long ls = atomicAdd(&ctl->log_n, 1ull);
+          if (ls < a.log_cap) {
+            StepRec& r = a.log[ls];
             r.event = t.ev;
             r.species = (uint32_t)sp;
             r.id = t.id;
@@ -249,11 +267,21 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
       }
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        wave_count(&ctl->steps[s], (stepped && sp == s) ? 1u : 0u);
-        uint32_t made = 0;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) made += (k < o.nsec && o.sec[k].sp == s) ? 1u : 0u;
-        wave_count(&ctl->created[s], made);
+        wave_count(&ctl->steps[s], (commit && sp == s) ? 1u : 0u);
+        wave_count(&ctl->created[s], commit ? d[s] : 0u);
+      }
+      wave_count(&ctl->deferred, carry ? 1u : 0u);
+      {
+        // per-launch progress counters (32-bit, reset by the last block)
+        uint32_t c = commit ? 1u : 0u, k = carry ? 1u : 0u;
+        for (int off = 32; off > 0; off >>= 1) {
+          c += __shfl_xor(c, off);
+          k += __shfl_xor(k, off);
+        }
+        if (__lane_id() == 0) {
+          if (c) atomicAdd(&ctl->commits, c);
+          if (k) atomicAdd(&ctl->carried, k);
+        }
       }
     }
   }
@@ -269,18 +297,32 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
   if (last && threadIdx.x == 0) {
     __threadfence();
     if (a.flags & kFlagProfile) {
-      if (ctl->iteration < a.profile_cap)
-        for (int s = 0; s < 3; ++s) a.profile[(size_t)ctl->iteration * 3 + s] = ctl->n_cur[s];
+      if (ctl->iteration < a.profile_cap) {
+        a.profile[(size_t)ctl->iteration * 3 + 0] = n0;
+        a.profile[(size_t)ctl->iteration * 3 + 1] = n1;
+        a.profile[(size_t)ctl->iteration * 3 + 2] = n2;
+      }
     }
     if (ntot > 0) ctl->iteration += 1;
-    for (int s = 0; s < 3; ++s) {
-      const uint32_t v = atomicAdd(&ctl->n_next[s], 0u);
-      ctl->n_cur[s] = v;
-      ctl->n_next[s] = 0;
-      ctl->peak[s] = v > ctl->peak[s] ? v : ctl->peak[s];
+    const uint32_t commits = atomicAdd(&ctl->commits, 0u), carried = atomicAdd(&ctl->carried, 0u);
+    if (carried > 0 && commits == 0) ctl->error |= kErrStall;  // nothing can move: queues too small
+    uint32_t live = 0;
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t lim = (uint32_t)(a.cap - (q == 0 ? n0 : (q == 1 ? n1 : n2)));
+      const uint32_t hv = atomicAdd(&ctl->next_home[q], 0u);
+      uint32_t sv = atomicAdd(&ctl->next_sec[q], 0u);
+      sv = sv < lim ? sv : lim;
+      ctl->n_home[q] = hv;
+      ctl->n_sec[q] = sv;
+      ctl->next_home[q] = 0;
+      ctl->next_sec[q] = 0;
+      ctl->peak[q] = hv + sv > ctl->peak[q] ? hv + sv : ctl->peak[q];
+      live += hv + sv;
     }
+    ctl->live = live;
+    ctl->commits = 0;
+    ctl->carried = 0;
     ctl->cur = cur ^ 1u;
-    plan_iteration(ctl, a.cap);
     ctl->blocks_done = 0;
     __threadfence();
   }
@@ -297,9 +339,9 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
     if (active) r = rec[i];
     for (int qs = 0; qs < 3; ++qs) {
       const uint32_t cnt = (active && (int)r.sp == qs) ? 1u : 0u;
-      const uint32_t slot = wave_reserve(&ctl->n_cur[qs], cnt);
+      const uint32_t slot = wave_reserve(&ctl->n_home[qs], cnt);
       if (!cnt) continue;
-      if (slot >= a.cap) {
+      if (slot + ctl->n_sec[qs] >= a.cap) {
         atomicOr(&ctl->error, kErrOverflow);
         continue;
       }
@@ -320,15 +362,6 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
   }
 }
 
-// One thread: plan the first iteration after injection.
-__global__ void k_plan(KArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctl* c = a.ctl;
-    for (int s = 0; s < 3; ++s) c->peak[s] = c->n_cur[s] > c->peak[s] ? c->n_cur[s] : c->peak[s];
-    plan_iteration(c, a.cap);
-  }
-}
-
 hipError_t launch_step(const KArgs& a, uint32_t blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_step, dim3(blocks), dim3(kBlock), a.lds_bytes, s, a);
   return hipGetLastError();
@@ -338,8 +371,21 @@ hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStrea
   hipLaunchKernelGGL(k_inject, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
   return hipGetLastError();
 }
-hipError_t launch_plan(const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, a);
+// live count after injection (one thread)
+__global__ void k_census(KArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* c = a.ctl;
+    uint32_t live = 0;
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t n = c->n_home[q] + c->n_sec[q];
+      c->peak[q] = n > c->peak[q] ? n : c->peak[q];
+      live += n;
+    }
+    c->live = live;
+  }
+}
+hipError_t launch_census(const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_census, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 hipError_t set_step_lds(uint32_t bytes) {
