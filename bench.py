@@ -67,9 +67,21 @@ def main():
     ap.add_argument("--capacity", type=int, default=8 << 20)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
+    ap.add_argument("--steps-per-visit", type=int, default=16)
     ap.add_argument("--cpu-events", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); events shard across GPUs with no "
               "exchange during transport, so the one-GPU figure is the per-GPU throughput", file=sys.stderr)
@@ -83,7 +95,7 @@ def main():
     geo, cfg, prim = I.workload(args.workload)
     n = len(prim)
     c = E.make_config(cfg, n, track_capacity=args.capacity, steps_per_launch=args.steps_per_launch,
-                      launch_blocks=args.blocks)
+                      launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -131,10 +143,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "events": n, "primary": "e-", "energy_MeV": float(prim["ekin"][0]),
                    "geometry": "50 x (2.3 mm Pb + 5.7 mm lAr), 40x40 cm", "bz_tesla": cfg.bz_tesla,
-                   "precision": "fp64", "track_steps_per_step": sum(steps) // args.steps},
+                   "precision": "fp64", "track_steps_per_step": sum(steps) // args.steps,
+                   "steps_per_visit": args.steps_per_visit},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step", "bytes_per_launch": per_launch, "avg_launch_us": avg_launch_s * 1e6,
+                     "kernel": "k_visit (photon + e-/e+ launch per iteration)", "bytes_per_launch": per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6,
                      "launches": launches},
     }
     if not args.no_cpu:

@@ -102,7 +102,11 @@ typedef struct {
   uint32_t launch_blocks;        /* step-kernel grid (0 = library default)   */
   uint64_t steplog_capacity;     /* records kept when EMS_F_STEPLOG is set   */
   uint32_t profile_capacity;     /* iterations kept when EMS_F_PROFILE       */
-  uint32_t reserved;
+  uint32_t steps_per_visit;      /* steps one thread may take of one track per
+                                    launch, stopping at the first step that
+                                    creates secondaries (results do not
+                                    depend on it); 1 = strictly one step of
+                                    the whole population per iteration      */
 } ems_config;
 
 /* One primary track (64 bytes). event is the tally row (< max_events); the

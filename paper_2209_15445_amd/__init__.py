@@ -44,7 +44,7 @@ class Config(C.Structure):
                 ("flags", C.c_uint32), ("max_steps_per_track", C.c_uint32), ("seed", C.c_uint32),
                 ("max_events", C.c_uint32), ("track_capacity", C.c_uint64), ("steps_per_launch", C.c_uint32),
                 ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("steps_per_visit", C.c_uint32)]
 
 
 class RunStats(C.Structure):
@@ -133,7 +133,7 @@ class _GeoHolder:
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
-                launch_blocks=0, steplog_capacity=0, profile_capacity=0):
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
     c = Config()
@@ -149,6 +149,7 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
     c.launch_blocks = launch_blocks
     c.steplog_capacity = steplog_capacity
     c.profile_capacity = profile_capacity
+    c.steps_per_visit = steps_per_visit
     return c
 
 

@@ -18,10 +18,10 @@
 #include "ems_device.hpp"
 
 namespace ems {
-hipError_t launch_step(const KArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s);
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
 hipError_t launch_census(const KArgs& a, hipStream_t s);
-hipError_t set_step_lds(uint32_t bytes);
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 }  // namespace ems
 
 using namespace ems;
@@ -77,6 +77,7 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
     return fail(EMS_E_INVALID, "bad step-function parameters");
   if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
   if (c->max_steps_per_track < 1 || c->max_events < 1) return fail(EMS_E_INVALID, "max_steps and max_events >= 1");
+  if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
     return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
   return EMS_OK;
@@ -93,7 +94,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
     return at;
   };
   L.ctl = take(sizeof(Ctl));
-  L.tab = take(g->n_materials * kNumTables * nodes * 8);
+  L.tab = take(g->n_materials * kNumTables * nodes * 8);  // photon block, then lepton block
   L.zp = take((g->n_slabs + 1) * 8ull);
   L.smat = take(g->n_slabs * 4ull);
   L.mat = take(g->n_materials * sizeof(MatRT));
@@ -203,7 +204,7 @@ struct ems_ctx {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   KArgs args{};
-  uint32_t blocks = 0;
+  uint32_t blocks_g = 0, blocks_l = 0;
   std::vector<uint64_t> row_count;
   uint64_t pending[3] = {0, 0, 0};
   InjRec* pin_inj = nullptr;
@@ -279,13 +280,11 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
     return bad(fail(EMS_E_DEVICE, "no HIP device"));
-  const uint32_t lds = (uint32_t)(geo->n_materials * kNumTables * (cfg->n_bins + 1) * 8 + (geo->n_slabs + 1) * 8 +
-                                  geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
-  if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) return bad(fail(EMS_E_INVALID, "tables exceed LDS"));
-  if (set_step_lds(lds) != hipSuccess) return bad(fail(EMS_E_DEVICE, "cannot reserve LDS for the step kernel"));
-  // blocks resident per CU are bounded by LDS; keep the grid one wave of them
-  const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160u * 1024u) / lds));
-  c->blocks = cfg->launch_blocks ? cfg->launch_blocks : (uint32_t)prop.multiProcessorCount * per_cu;
+  const uint64_t nodes = cfg->n_bins + 1;
+  const uint32_t common = (uint32_t)((geo->n_slabs + 1) * 8 + geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
+  const uint32_t lds_g = (uint32_t)(geo->n_materials * kGammaTables * nodes * 8) + common;
+  const uint32_t lds_l = (uint32_t)(geo->n_materials * kLeptonTables * nodes * 8) + common;
+  if (lds_l > 160u * 1024u) return bad(fail(EMS_E_INVALID, "tables exceed LDS"));
 
   KArgs& a = c->args;
   a.qbase = c->ws + L.queues;
@@ -293,29 +292,49 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.edep = reinterpret_cast<double*>(c->ws + L.edep);
   a.ledger = reinterpret_cast<LedgerDev*>(c->ws + L.ledger);
   a.keys = reinterpret_cast<const uint32_t*>(c->ws + L.keys);
-  a.tab = reinterpret_cast<const double*>(c->ws + L.tab);
+  a.tab_g = reinterpret_cast<const double*>(c->ws + L.tab);
+  a.tab_l = a.tab_g + geo->n_materials * kGammaTables * nodes;
   a.zplane = reinterpret_cast<const double*>(c->ws + L.zp);
   a.slab_mat = reinterpret_cast<const uint32_t*>(c->ws + L.smat);
   a.mat = reinterpret_cast<const MatRT*>(c->ws + L.mat);
   a.log = reinterpret_cast<StepRec*>(c->ws + L.log);
   a.profile = reinterpret_cast<uint32_t*>(c->ws + L.profile);
   a.cap = L.cap;
+  a.max_events = cfg->max_events;
   a.log_cap = (cfg->flags & EMS_F_STEPLOG) ? cfg->steplog_capacity : 0;
   a.profile_cap = (cfg->flags & EMS_F_PROFILE) ? cfg->profile_capacity : 0;
   a.flags = cfg->flags;
   a.n_mat = geo->n_materials;
-  a.lds_bytes = lds;
+  a.lds_g = lds_g;
+  a.lds_l = lds_l;
+  a.steps_per_visit = cfg->steps_per_visit;
   a.env = env_for(cfg, geo, c->ts);
+  int per_g = 0, per_l = 0;
+  if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
+    return bad(fail(EMS_E_DEVICE, "cannot configure the visit kernels"));
+  // one resident wave of blocks per launch; blocks grid-stride over the queue
+  const uint32_t cus = (uint32_t)prop.multiProcessorCount;
+  c->blocks_g = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_g;
+  c->blocks_l = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_l;
 
   if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_inj), kInjectChunk * sizeof(InjRec)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return bad(fail(EMS_E_DEVICE, "pinned host allocation or event creation failed"));
+  // device table layout: photon block [mat][3][nodes], then lepton block [mat][10][nodes]
+  std::vector<double> packed;
+  packed.reserve(c->ts.v.size());
+  for (uint32_t m = 0; m < geo->n_materials; ++m)
+    for (int t = 0; t < kGammaTables; ++t)
+      for (uint64_t j = 0; j < nodes; ++j) packed.push_back(c->ts.at(m, t, (uint32_t)j));
+  for (uint32_t m = 0; m < geo->n_materials; ++m)
+    for (int t = kGammaTables; t < kNumTables; ++t)
+      for (uint64_t j = 0; j < nodes; ++j) packed.push_back(c->ts.at(m, t, (uint32_t)j));
   std::vector<uint32_t> keys(cfg->max_events);
   for (uint32_t i = 0; i < cfg->max_events; ++i) keys[i] = i;
   hipStream_t s = c->stream;
   bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
-            hipMemcpyAsync(c->ws + L.tab, c->ts.v.data(), c->ts.v.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.mat, c->ts.rt.data(), c->ts.rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
@@ -323,6 +342,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
             hipMemcpyAsync(c->ws + L.keys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.edep, 0, (L.ledger - L.edep) + (uint64_t)cfg->max_events * sizeof(LedgerDev), s) ==
                 hipSuccess &&
+            hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * kTrackBytes, s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
     (void)hipHostFree(c->pin_inj);
@@ -390,7 +410,7 @@ ems_status ems_run(ems_ctx* c) {
   double kms = 0.0;
   for (;;) {
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_step(c->args, c->blocks, c->stream));
+    for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_iteration(c->args, c->blocks_g, c->blocks_l, c->stream));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     launches += K;
     HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
@@ -406,6 +426,10 @@ ems_status ems_run(ems_ctx* c) {
     if (s.error & kErrStall) {
       c->failed = true;
       return fail(EMS_E_CAPACITY, "track queues too small to make progress");
+    }
+    if (s.error & kErrCorrupt) {
+      c->failed = true;
+      return fail(EMS_E_STATE, "a queue record indexed outside the tallies or the slab stack");
     }
     if (s.live == 0) break;
     // a track lives at most max_steps iterations; generations are few
@@ -531,7 +555,15 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
   if (!edep || !ledger || (n && !prim)) return fail(EMS_E_INVALID, "null buffers");
   TableSet ts = tables_for(&c2, geo);
   StepEnv env = env_for(&c2, geo, ts);
-  env.tab = ts.v.data();
+  std::vector<double> tg, tl;
+  for (uint32_t m = 0; m < geo->n_materials; ++m) {
+    for (int t = 0; t < kGammaTables; ++t)
+      for (uint32_t j = 0; j < ts.nodes; ++j) tg.push_back(ts.at(m, t, j));
+    for (int t = kGammaTables; t < kNumTables; ++t)
+      for (uint32_t j = 0; j < ts.nodes; ++j) tl.push_back(ts.at(m, t, j));
+  }
+  env.tg = tg.data();
+  env.tl = tl.data();
   env.zplane = geo->z_mm;
   env.slab_mat = geo->material;
   env.mat = ts.rt.data();
@@ -546,52 +578,65 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
     Trk t{r.x, r.y, r.z, r.ux, r.uy, r.uz, r.E, r.id, r.ev, keys ? keys[r.ev] : r.ev, 0, r.slab};
     cur[r.sp].push_back(t);
   }
-  uint64_t nlog = 0;
+  struct HostSink {
+    const ems_geometry* geo;
+    double* edep;
+    ems_ledger* ledger;
+    ems_step_record* log;
+    uint64_t log_cap, nlog;
+    void apply(int sp, const Trk& t, const StepOut& o, double e0) {
+      ems_ledger& L = ledger[t.ev];
+      edep[(size_t)t.ev * geo->n_slabs + o.slab] += o.dep;
+      L.escaped[sp] += o.escaped;
+      L.killed += o.killed;
+      L.charged_len += o.clen;
+      L.n_steps += 1;
+      L.n_null += o.null;
+      L.n_pair += o.pair;
+      L.n_annih += o.annih;
+      for (int k = 0; k < o.nsec; ++k) L.n_created[o.sec[k].sp] += 1;
+      if (log && nlog < log_cap) {
+        ems_step_record& r = log[nlog];
+        r.event = t.ev;
+        r.species = (uint32_t)sp;
+        r.id = t.id;
+        r.step = t.n - 1;
+        r.slab_after = t.slab;
+        r.limiter = o.limiter;
+        r.process = o.process;
+        r.e_before = e0;
+        r.e_after = t.E;
+        r.pos_after[0] = t.x;
+        r.pos_after[1] = t.y;
+        r.pos_after[2] = t.z;
+        r.step_len = o.step_len;
+        r.edep = o.dep;
+      }
+      ++nlog;
+    }
+  } sink{geo, edep, ledger, log, log_cap, 0};
+  const int max_visit = (int)c2.steps_per_visit;
   for (;;) {
     if (cur[0].empty() && cur[1].empty() && cur[2].empty()) break;
     for (int sp = 0; sp < 3; ++sp) {
       for (Trk t : cur[sp]) {
-        const double e0 = t.E;
+        Trk before;
         StepOut o;
-        take_step(env, sp, t, o);
-        ems_ledger& L = ledger[t.ev];
-        edep[(size_t)t.ev * geo->n_slabs + o.slab] += o.dep;
-        L.escaped[sp] += o.escaped;
-        L.killed += o.killed;
-        L.charged_len += o.clen;
-        L.n_steps += 1;
-        L.n_null += o.null;
-        L.n_pair += o.pair;
-        L.n_annih += o.annih;
-        for (int k = 0; k < o.nsec; ++k) {
-          const Sec& s = o.sec[k];
-          L.n_created[s.sp] += 1;
-          nxt[s.sp].push_back(Trk{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});
+        visit<2>(env, sp, t, o, before, max_visit, sink);
+        if (o.nsec > 0) {
+          sink.apply(sp, t, o, before.E);
+          for (int k = 0; k < o.nsec; ++k) {
+            const Sec& s = o.sec[k];
+            nxt[s.sp].push_back(Trk{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});
+          }
         }
         if (t.slab >= 0) nxt[sp].push_back(t);
-        if (log && nlog < log_cap) {
-          ems_step_record& r = log[nlog];
-          r.event = t.ev;
-          r.species = (uint32_t)sp;
-          r.id = t.id;
-          r.step = t.n - 1;
-          r.slab_after = t.slab;
-          r.limiter = o.limiter;
-          r.process = o.process;
-          r.e_before = e0;
-          r.e_after = t.E;
-          r.pos_after[0] = t.x;
-          r.pos_after[1] = t.y;
-          r.pos_after[2] = t.z;
-          r.step_len = o.step_len;
-          r.edep = o.dep;
-        }
-        ++nlog;
       }
       cur[sp].clear();
     }
     for (int sp = 0; sp < 3; ++sp) cur[sp].swap(nxt[sp]);
   }
+  const uint64_t nlog = sink.nlog;
   for (uint32_t e = 0; e < n_events; ++e) {
     double s = 0.0;
     for (uint32_t k = 0; k < geo->n_slabs; ++k) s += edep[(size_t)e * geo->n_slabs + k];

@@ -58,7 +58,7 @@ struct Ctl {
   uint32_t pad0;
   unsigned long long steps[3], created[3], deferred, log_n;
 };
-enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u };
+enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
 // Track prepared on the host for injection (slab located, direction unit).
 struct InjRec {
@@ -93,18 +93,21 @@ struct KArgs {
   double* edep;        // [rows][n_slabs]
   LedgerDev* ledger;   // [rows]
   const uint32_t* keys;
-  const double* tab;   // global copy of the tables
+  const double* tab_g;  // photon table block [mat][3][nodes]
+  const double* tab_l;  // lepton table block [mat][10][nodes]
   const double* zplane;
   const uint32_t* slab_mat;
   const MatRT* mat;
   StepRec* log;
   uint32_t* profile;   // [profile_cap][3]
   uint64_t cap;        // tracks per species per buffer
+  uint32_t max_events;  // tally rows
   uint64_t log_cap;
   uint32_t profile_cap;
   uint32_t flags;
   uint32_t n_mat;
-  uint32_t lds_bytes;
+  uint32_t lds_g, lds_l;      // dynamic LDS of the photon / lepton kernels
+  uint32_t steps_per_visit;   // steps a thread may take per launch
   StepEnv env;         // scalars; its pointers are set per block
 };
 

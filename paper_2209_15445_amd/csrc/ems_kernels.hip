@@ -3,19 +3,24 @@
 // The paper steps the whole track population once per iteration with one
 // kernel per species in three streams, appending secondaries to per-species
 // "next" index arrays with an atomic counter and swapping current/next after
-// each step (section 3).  On MI355X this is one fused launch per iteration:
-//  - threads map to a concatenated index space [gamma | e- | e+], so a wave
-//    almost always holds one species and no stream synchronisation is needed;
-//  - the queues hold the tracks themselves (SoA, coalesced), and survivors
-//    are rewritten compactly each step, so slots are reused by construction;
+// each step (section 3).  On MI355X:
+//  - one launch per iteration for photons and one for e-/e+ (a concatenated
+//    index space [e- | e+]), in stream order, so the light photon kernel is
+//    not held to the lepton kernel's register budget and each stages only
+//    its own tables in LDS;
+//  - the queues hold the tracks themselves (SoA, coalesced); survivors are
+//    rewritten compactly each iteration, so slots are reused by construction;
+//  - a thread keeps stepping its track (a "visit") until a step creates
+//    secondaries or ends the track, so the many boundary crossings of photons
+//    in the thin slabs do not each cost a queue round trip; every step still
+//    draws from its own (id, step) stream, so histories are unchanged;
 //  - appends are aggregated per wave (ballot + popcount prefix, one atomic
 //    per wave and species);
-//  - cross-section tables, slab planes and materials are staged in LDS;
 //  - secondaries are reserved against a per-species limit that always leaves
 //    room for every survivor; a track whose secondaries do not fit is carried
-//    unstepped, so a full queue defers work instead of losing it;
-//  - the last block to finish swaps the queues, so a chain of launches needs
-//    no host round trip.
+//    from before that step, so a full queue defers work instead of losing it;
+//  - the last block of the e-/e+ launch swaps the queues, so a chain of
+//    launches needs no host round trip.
 #include <hip/hip_runtime.h>
 
 #include "ems_device.hpp"
@@ -26,29 +31,31 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ inline uint64_t lanes_below() { return __lanemask_lt(); }
-
 // Reserve `count` (0..3) consecutive slots per lane in an append counter with
-// one atomic per wave; returns this lane's first slot.
+// one atomic per wave; returns this lane's first slot.  Every lane of the wave
+// must pass the same counter.
 __device__ inline uint32_t wave_reserve(uint32_t* counter, uint32_t count) {
   const uint64_t b0 = __ballot(count & 1u);
   const uint64_t b1 = __ballot((count >> 1) & 1u);
   const uint32_t total = (uint32_t)(__popcll(b0) + 2 * __popcll(b1));
   if (total == 0) return 0;
-  const uint64_t lt = lanes_below();
+  const uint64_t lt = __lanemask_lt();
   const uint32_t prefix = (uint32_t)(__popcll(b0 & lt) + 2 * __popcll(b1 & lt));
-  const uint64_t any = b0 | b1;
-  const int leader = __ffsll((unsigned long long)any) - 1;
+  const int leader = __ffsll((unsigned long long)(b0 | b1)) - 1;
   uint32_t base = 0;
   if ((int)__lane_id() == leader) base = atomicAdd(counter, total);
   base = __shfl(base, leader);
   return base + prefix;
 }
 
+__device__ inline uint32_t wave_sum(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // sum over the wave of a per-lane count, one atomic by lane 0
 __device__ inline void wave_count(unsigned long long* counter, uint32_t v) {
-  uint32_t s = v;
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  const uint32_t s = wave_sum(v);
   if (__lane_id() == 0 && s) atomicAdd(counter, (unsigned long long)s);
 }
 
@@ -72,69 +79,132 @@ __device__ inline uint32_t queue_pos(uint32_t idx, uint32_t home, uint64_t cap) 
   return idx < home ? idx : (uint32_t)(cap - 1 - (idx - home));
 }
 
-__device__ inline void store_dead(const Queue& q, uint32_t i) { q.slab[i] = -1; }
+// Tallies of one applied step: FP64 atomic scoring per (event, slab), energy
+// ledger, optional per-event counts and step log.
+struct DevSink {
+  double* edep;
+  LedgerDev* ledger;
+  Ctl* ctl;
+  StepRec* log;
+  unsigned long long log_cap;
+  uint32_t n_slabs;
+  bool full, logging;
+  uint32_t applied;  // steps applied by this lane in the current visit
+
+  __device__ void apply(int sp, const Trk& t, const StepOut& o, double e_before) {
+    ++applied;
+    if (o.dep != 0.0) atomicAdd(&edep[(size_t)t.ev * n_slabs + o.slab], o.dep);
+    LedgerDev& L = ledger[t.ev];
+    if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
+    if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
+    if (o.pair) atomicAdd(&L.n_pair, (uint32_t)o.pair);
+    if (o.annih) atomicAdd(&L.n_annih, (uint32_t)o.annih);
+    if (full) {
+      atomicAdd(&L.n_steps, 1ull);
+      if (o.clen != 0.0) atomicAdd(&L.charged_len, o.clen);
+      if (o.null) atomicAdd(&L.n_null, 1ull);
+      if (o.nsec > 0) atomicAdd(&L.n_created[0] + o.sec[0].sp, 1ull);
+      if (o.nsec > 1) atomicAdd(&L.n_created[0] + o.sec[1].sp, 1ull);
+    }
+    if (logging) {
+      const unsigned long long ls = atomicAdd(&ctl->log_n, 1ull);
+      if (ls < log_cap) {
+        StepRec& r = log[ls];
+        r.event = t.ev;
+        r.species = (uint32_t)sp;
+        r.id = t.id;
+        r.step = t.n - 1;
+        r.slab_after = t.slab;
+        r.limiter = o.limiter;
+        r.process = o.process;
+        r.e_before = e_before;
+        r.e_after = t.E;
+        r.pos[0] = t.x;
+        r.pos[1] = t.y;
+        r.pos[2] = t.z;
+        r.step_len = o.step_len;
+        r.edep = o.dep;
+      }
+    }
+  }
+};
+
+// Stage a table block, the slab planes, slab materials and material
+// constants in LDS; returns the environment pointing there.
+__device__ StepEnv stage(const KArgs& a, double* lds, bool photons) {
+  const uint32_t nt = photons ? kGammaTables : kLeptonTables;
+  const uint32_t ntab = a.n_mat * nt * a.env.nodes;
+  const double* src = photons ? a.tab_g : a.tab_l;
+  for (uint32_t i = threadIdx.x; i < ntab; i += kBlock) lds[i] = src[i];
+  double* zp = lds + ntab;
+  for (uint32_t i = threadIdx.x; i <= a.env.n_slabs; i += kBlock) zp[i] = a.zplane[i];
+  MatRT* mr = reinterpret_cast<MatRT*>(zp + a.env.n_slabs + 1);
+  if (threadIdx.x < a.n_mat) mr[threadIdx.x] = a.mat[threadIdx.x];
+  uint32_t* sm = reinterpret_cast<uint32_t*>(mr + a.n_mat);
+  for (uint32_t i = threadIdx.x; i < a.env.n_slabs; i += kBlock) sm[i] = a.slab_mat[i];
+  __syncthreads();
+  StepEnv env = a.env;
+  env.tg = photons ? lds : nullptr;
+  env.tl = photons ? nullptr : lds;
+  env.zplane = zp;
+  env.mat = mr;
+  env.slab_mat = sm;
+  return env;
+}
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
+// One iteration for the photons (PHOTONS) or for the e-/e+ (otherwise).
+#ifndef EMS_PHOTON_WAVES
+#define EMS_PHOTON_WAVES 1
+#endif
+template <bool PHOTONS>
+__global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : 1) void k_visit(KArgs a) {
   extern __shared__ double lds[];
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
   const uint32_t h0 = ctl->n_home[0], h1 = ctl->n_home[1], h2 = ctl->n_home[2];
   const uint32_t n0 = h0 + ctl->n_sec[0], n1 = h1 + ctl->n_sec[1], n2 = h2 + ctl->n_sec[2];
-  const uint32_t ntot = n0 + n1 + n2;
-  const uint32_t need = (ntot + kBlock - 1) / kBlock;
+  const uint32_t nmine = PHOTONS ? n0 : n1 + n2;
+  const uint32_t need = (nmine + kBlock - 1) / kBlock;
   const bool work = blockIdx.x < need && ctl->error == 0;
 
   if (work) {
-    // stage tables, slab planes, slab materials and material constants
-    const uint32_t ntab = a.n_mat * kNumTables * a.env.nodes;
-    for (uint32_t i = threadIdx.x; i < ntab; i += kBlock) lds[i] = a.tab[i];
-    double* zp = lds + ntab;
-    for (uint32_t i = threadIdx.x; i <= a.env.n_slabs; i += kBlock) zp[i] = a.zplane[i];
-    MatRT* mr = reinterpret_cast<MatRT*>(zp + a.env.n_slabs + 1);
-    if (threadIdx.x < a.n_mat) mr[threadIdx.x] = a.mat[threadIdx.x];
-    uint32_t* sm = reinterpret_cast<uint32_t*>(mr + a.n_mat);
-    for (uint32_t i = threadIdx.x; i < a.env.n_slabs; i += kBlock) sm[i] = a.slab_mat[i];
-    __syncthreads();
-
-    StepEnv env = a.env;
-    env.tab = lds;
-    env.zplane = zp;
-    env.mat = mr;
-    env.slab_mat = sm;
+    const StepEnv env = stage(a, lds, PHOTONS);
     const uint32_t nxt = cur ^ 1u;
-    const bool full = (a.flags & kFlagFullLedger) != 0;
-    const bool logging = (a.flags & kFlagSteplog) != 0;
+    const int max_visit = (int)a.steps_per_visit;
     // secondary slots per species that leave room for all survivors
     const uint32_t lim0 = (uint32_t)(a.cap - n0), lim1 = (uint32_t)(a.cap - n1), lim2 = (uint32_t)(a.cap - n2);
+    DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
+                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u};
 
-    for (uint32_t base = blockIdx.x * kBlock; base < ntot; base += gridDim.x * kBlock) {
+    for (uint32_t base = blockIdx.x * kBlock; base < nmine; base += gridDim.x * kBlock) {
       const uint32_t i = base + threadIdx.x;
-      const bool active = i < ntot;
-      int sp = 0;
-      uint32_t idx = i, home = h0;
-      if (i >= n0 + n1) {
+      const bool active = i < nmine;
+      int sp = PHOTONS ? 0 : 1;
+      uint32_t idx = i, home = PHOTONS ? h0 : h1;
+      if (!PHOTONS && i >= n1) {
         sp = 2;
-        idx = i - n0 - n1;
+        idx = i - n1;
         home = h2;
-      } else if (i >= n0) {
-        sp = 1;
-        idx = i - n0;
-        home = h1;
       }
       const uint32_t pos = queue_pos(idx, home, a.cap);
       const Queue src = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
-      Trk t;
+      Trk t, before;
       StepOut o;
       o.nsec = 0;
-      o.dep = o.escaped = o.killed = o.clen = 0.0;
-      o.pair = o.annih = o.null = 0;
       bool live_in = false;
-      double e_before = 0.0;
+      sink.applied = 0;
       if (active) {
         t.slab = src.slab[pos];
         live_in = t.slab >= 0;  // slots of refused secondaries hold slab -1
+        t.ev = live_in ? src.ev[pos] : 0u;
+        // a record that would index outside the tallies or the slab stack is
+        // reported, never used
+        if (live_in && (t.slab >= (int32_t)a.env.n_slabs || t.ev >= a.max_events)) {
+          atomicOr(&ctl->error, kErrCorrupt);
+          live_in = false;
+        }
       }
       if (live_in) {
         t.x = src.x[pos];
@@ -145,27 +215,27 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
         t.uz = src.uz[pos];
         t.E = src.E[pos];
         t.id = src.id[pos];
-        t.ev = src.ev[pos];
         t.n = src.n[pos];
         t.key = a.keys[t.ev];
-        e_before = t.E;
-        take_step(env, sp, t, o);
+        visit<PHOTONS ? 0 : 1>(env, sp, t, o, before, max_visit, sink);
       }
 
-      // reserve secondary slots (top regions); the step commits only if all
-      // of this track's secondaries fit
+      // reserve secondary slots (top regions); the last step commits only if
+      // all of its secondaries fit
       uint32_t d[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
         d[q] = (o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
       uint32_t slot[3];
-      bool commit = live_in;
+      bool fits = true;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         slot[q] = wave_reserve(&ctl->next_sec[q], d[q]);
         const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
-        if (d[q] && slot[q] + d[q] > lim) commit = false;
+        if (d[q] && slot[q] + d[q] > lim) fits = false;
       }
+      const bool pending = o.nsec > 0;
+      const bool commit = pending && fits;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         if (!d[q]) continue;
@@ -192,101 +262,52 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
               c.slab = o.slab;
               store_track(dq, p, c);
             } else {
-              store_dead(dq, p);
+              dq.slab[p] = -1;  // refused: the next iteration skips this slot
             }
           }
           ++s;
         }
       }
+      if (commit) sink.apply(sp, t, o, before.E);
+      const bool carry = pending && !commit;  // back to the state before the last step
+      const bool keep = live_in && (carry ? before.slab >= 0 : t.slab >= 0);
 
-      // home region: survivors of committed steps, or the unstepped track
-      const bool carry = live_in && !commit;
-      const bool keep = carry || (commit && t.slab >= 0);
+      // home region: survivors, or tracks carried from before their last step
+      // (one counter per wave_reserve call: a wave may hold e- and e+)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const uint32_t hs = wave_reserve(&ctl->next_home[q], (keep && sp == q) ? 1u : 0u);
-        if (keep && sp == q) {
+      for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
+        const bool mine = keep && sp == q;
+        const uint32_t hs = wave_reserve(&ctl->next_home[q], mine ? 1u : 0u);
+        if (mine) {
           const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
-          if (hs >= a.cap) {
-            atomicOr(&ctl->error, kErrOverflow);
-          } else if (carry) {
-            // the current buffer is untouched during the launch
-            dq.x[hs] = src.x[pos];
-            dq.y[hs] = src.y[pos];
-            dq.z[hs] = src.z[pos];
-            dq.ux[hs] = src.ux[pos];
-            dq.uy[hs] = src.uy[pos];
-            dq.uz[hs] = src.uz[pos];
-            dq.E[hs] = src.E[pos];
-            dq.id[hs] = src.id[pos];
-            dq.ev[hs] = src.ev[pos];
-            dq.n[hs] = src.n[pos];
-            dq.slab[hs] = src.slab[pos];
-          } else {
-            store_track(dq, hs, t);
-          }
+          if (hs >= a.cap) atomicOr(&ctl->error, kErrOverflow);
+          else if (carry) store_track(dq, hs, before);
+          else store_track(dq, hs, t);
         }
       }
 
-      // tallies of committed steps
-      if (commit) {
-        if (o.dep != 0.0) atomicAdd(&a.edep[(size_t)t.ev * env.n_slabs + o.slab], o.dep);
-        LedgerDev& L = a.ledger[t.ev];
-        if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
-        if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
-        if (o.pair) atomicAdd(&L.n_pair, (uint32_t)o.pair);
-        if (o.annih) atomicAdd(&L.n_annih, (uint32_t)o.annih);
-        if (full) {
-          atomicAdd(&L.n_steps, 1ull);
-          if (o.clen != 0.0) atomicAdd(&L.charged_len, o.clen);
-          if (o.null) atomicAdd(&L.n_null, 1ull);
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-            if (d[q]) atomicAdd(&L.n_created[q], (unsigned long long)d[q]);
-        }
-        if (logging) {
-          const unsigned long long ls = atomicAdd(&ctl->log_n, 1ull);
-          if (ls < a.log_cap) {
-            StepRec& r = a.log[ls];
-            r.event = t.ev;
-            r.species = (uint32_t)sp;
-            r.id = t.id;
-            r.step = t.n - 1;
-            r.slab_after = t.slab;
-            r.limiter = o.limiter;
-            r.process = o.process;
-            r.e_before = e_before;
-            r.e_after = t.E;
-            r.pos[0] = t.x;
-            r.pos[1] = t.y;
-            r.pos[2] = t.z;
-            r.step_len = o.step_len;
-            r.edep = o.dep;
-          }
-        }
+      // statistics and per-launch progress
+      if (PHOTONS) {
+        wave_count(&ctl->steps[0], sink.applied);
+      } else {
+        wave_count(&ctl->steps[1], sp == 1 ? sink.applied : 0u);
+        wave_count(&ctl->steps[2], sp == 2 ? sink.applied : 0u);
       }
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        wave_count(&ctl->steps[s], (commit && sp == s) ? 1u : 0u);
-        wave_count(&ctl->created[s], commit ? d[s] : 0u);
-      }
+      for (int q = 0; q < 3; ++q) wave_count(&ctl->created[q], commit ? d[q] : 0u);
       wave_count(&ctl->deferred, carry ? 1u : 0u);
-      {
-        // per-launch progress counters (32-bit, reset by the last block)
-        uint32_t c = commit ? 1u : 0u, k = carry ? 1u : 0u;
-        for (int off = 32; off > 0; off >>= 1) {
-          c += __shfl_xor(c, off);
-          k += __shfl_xor(k, off);
-        }
-        if (__lane_id() == 0) {
-          if (c) atomicAdd(&ctl->commits, c);
-          if (k) atomicAdd(&ctl->carried, k);
-        }
+      const uint32_t c = wave_sum(sink.applied), k = wave_sum(carry ? 1u : 0u);
+      if (__lane_id() == 0) {
+        if (c) atomicAdd(&ctl->commits, c);
+        if (k) atomicAdd(&ctl->carried, k);
       }
     }
   }
 
-  // the last block to finish publishes the next iteration
+  if (PHOTONS) return;
+
+  // the last block of the e-/e+ launch publishes the next iteration (the
+  // photon launch of this iteration finished before this launch started)
   __shared__ uint32_t last;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -303,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
         a.profile[(size_t)ctl->iteration * 3 + 2] = n2;
       }
     }
-    if (ntot > 0) ctl->iteration += 1;
+    if (n0 + n1 + n2 > 0) ctl->iteration += 1;
     const uint32_t commits = atomicAdd(&ctl->commits, 0u), carried = atomicAdd(&ctl->carried, 0u);
     if (carried > 0 && commits == 0) ctl->error |= kErrStall;  // nothing can move: queues too small
     uint32_t live = 0;
@@ -328,7 +349,8 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs a) {
   }
 }
 
-// Injection: prepared tracks appended to the current queues.
+// Injection: prepared tracks appended to the home regions of the current
+// queues.
 __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, uint32_t n) {
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
@@ -362,15 +384,6 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
   }
 }
 
-hipError_t launch_step(const KArgs& a, uint32_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_step, dim3(blocks), dim3(kBlock), a.lds_bytes, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
-  const uint32_t blocks = n == 0 ? 1 : (n + kBlock - 1) / kBlock < 4096 ? (n + kBlock - 1) / kBlock : 4096;
-  hipLaunchKernelGGL(k_inject, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
-  return hipGetLastError();
-}
 // live count after injection (one thread)
 __global__ void k_census(KArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -384,13 +397,33 @@ __global__ void k_census(KArgs a) {
     c->live = live;
   }
 }
+
+hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
+  hipLaunchKernelGGL(k_visit<true>, dim3(blocks_g), dim3(kBlock), a.lds_g, s, a);
+  hipLaunchKernelGGL(k_visit<false>, dim3(blocks_l), dim3(kBlock), a.lds_l, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
+  const uint32_t want = (n + kBlock - 1) / kBlock;
+  const uint32_t blocks = n == 0 ? 1 : (want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(k_inject, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
+  return hipGetLastError();
+}
 hipError_t launch_census(const KArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_census, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
-hipError_t set_step_lds(uint32_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+// blocks of each visit kernel that fit on one CU (registers and LDS)
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true>, kBlock, a.lds_g);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false>, kBlock, a.lds_l);
 }
 
 }  // namespace ems

@@ -10,10 +10,14 @@
 
 namespace ems {
 
-// Material constants needed at run time by the samplers.
+// Material constants needed at run time by the samplers and the
+// null-collision bound.
 struct MatRT {
   double c136;    // 136 Z^{-1/3}: screening variable prefactor
   double gshift;  // ln Z / 3 + f_c: subtracted from phi / 4
+  // right-continuous discrete totals at the process thresholds (1/mm):
+  // e- at 2 T_cut (Moller) and k_c (brems); e+ at T_cut (Bhabha) and k_c
+  double up_em[2], up_ep[2];
 };
 
 // Thomas-Fermi screening functions in the Butcher-Messel parametrisation.

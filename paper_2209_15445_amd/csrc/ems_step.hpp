@@ -15,9 +15,15 @@ namespace ems {
 
 constexpr double kInf = __builtin_huge_val();
 
+// Tables are held in two blocks so each kernel stages only its own: the
+// photon block [mat][3][nodes] (tables 0..2) and the lepton block
+// [mat][10][nodes] (tables 3..12).
+constexpr int kGammaTables = 3, kLeptonTables = kNumTables - kGammaTables;
+
 struct StepEnv {
-  const double* tab;        // [mat][kNumTables][nodes]
-  const double* zplane;     // n_slabs + 1
+  const double* tg;          // photon table block
+  const double* tl;          // lepton table block
+  const double* zplane;      // n_slabs + 1
   const uint32_t* slab_mat;  // n_slabs
   const MatRT* mat;
   uint32_t nodes, n_slabs;
@@ -27,7 +33,10 @@ struct StepEnv {
   double alpha, rho, lin;
   uint32_t mask, seed, max_steps;
 
-  EMS_HD const double* T(uint32_t m, int t) const { return tab + ((size_t)m * kNumTables + t) * nodes; }
+  EMS_HD const double* T(uint32_t m, int t) const {
+    return t < kGammaTables ? tg + ((size_t)m * kGammaTables + t) * nodes
+                            : tl + ((size_t)m * kLeptonTables + (t - kGammaTables)) * nodes;
+  }
 };
 
 struct Trk {
@@ -245,8 +254,7 @@ EMS_HD LeptonProcs lepton_procs(const StepEnv& e, bool positron) {
 }
 
 // right-continuous discrete total (process counted at its threshold)
-EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, double E) {
-  const Bin b = bin_of(e, log(E));
+EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, double E, Bin b) {
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -256,11 +264,12 @@ EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, do
 
 // maximum of the discrete total over [a, b]: endpoints, grid nodes and
 // thresholds inside; when a is the tracking cut the nodes below b come from
-// the running-maximum table
+// the running-maximum table; the values at the thresholds are precomputed
 EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p, bool positron, double a,
-                             double b, double lnb, bool from_cut) {
-  double best = total_upper(e, m, p, a);
-  const double vb = total_upper(e, m, p, b);
+                             double b, Bin bb, double lnb, bool from_cut) {
+  const double lna = log(a);
+  double best = total_upper(e, m, p, a, bin_of(e, lna));
+  const double vb = total_upper(e, m, p, b, bb);
   best = vb > best ? vb : best;
   const double xb = (lnb - e.lnemin) * e.inv_dlog;
   int jb = (int)ceil(xb) - 1;
@@ -270,7 +279,7 @@ EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p,
       const double v = e.T(m, positron ? tPMep : tPMem)[jb];
       best = v > best ? v : best;
     } else {
-      const double xa = (log(a) - e.lnemin) * e.inv_dlog;
+      const double xa = (lna - e.lnemin) * e.inv_dlog;
       int j = (int)floor(xa) + 1;
       j = j < 0 ? 0 : j;
       for (; j <= jb; ++j) {
@@ -282,10 +291,11 @@ EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p,
       }
     }
   }
+  const MatRT& mr = e.mat[m];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    if (i < p.n && p.th[i] > a && p.th[i] < b) {
-      const double v = total_upper(e, m, p, p.th[i]);
+  for (int i = 0; i < 2; ++i) {
+    if (p.th[i] > a && p.th[i] < b) {
+      const double v = positron ? mr.up_ep[i] : mr.up_em[i];
       best = v > best ? v : best;
     }
   }
@@ -355,7 +365,7 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
   const bool from_cut = !(elo > e.ecut);
   const double a = from_cut ? e.ecut : elo;
   const LeptonProcs pl = lepton_procs(e, positron);
-  const double bound = thinning_bound(e, m, pl, positron, a, T, lnT, from_cut);
+  const double bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
   const double sphys = bound > 0.0 ? -log(r.at(0)) / bound : kInf;
   double s;
   uint32_t lim;
@@ -445,20 +455,46 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
 }
 
 // One full step of a track of species sp: dispatch, step counter, watchdog.
-EMS_HD void take_step(const StepEnv& e, int sp, Trk& t, StepOut& o) {
+// KIND: 0 = photons only, 1 = e-/e+ only, 2 = any species (host use).
+template <int KIND>
+EMS_HD void take_step_k(const StepEnv& e, int sp, Trk& t, StepOut& o) {
   o.nsec = 0;
   o.slab = t.slab;
   o.dep = o.escaped = o.killed = o.clen = o.step_len = 0.0;
   o.pair = o.annih = o.null = 0;
   o.limiter = 0;
   o.process = kXNone;
-  if (sp == kGamma) gamma_step(e, t, o);
+  if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step(e, t, o);
   else lepton_step(e, sp == kPositron, t, o);
   t.n += 1;
   if (t.slab >= 0 && t.n >= e.max_steps) {
     o.killed += t.E;
     t.E = 0.0;
     t.slab = -1;
+  }
+}
+EMS_HD void take_step(const StepEnv& e, int sp, Trk& t, StepOut& o) { take_step_k<2>(e, sp, t, o); }
+
+// A visit: consecutive steps of one track by one thread, until a step
+// produces secondaries, the track ends, or max_steps steps were taken.  The
+// sequence of steps is exactly the one-step-at-a-time sequence (every step
+// draws from its own (id, step) stream); only the queue round trips between
+// them are saved.  Steps without secondaries are handed to sink.apply() as
+// they happen.  If the last step produced secondaries it is NOT applied: `o`
+// holds it, `before` holds the track as it was before that step, and the
+// caller either commits it (sink.apply + push) or carries `before`.
+// Returns the number of steps taken.
+template <int KIND, class Sink>
+EMS_HD int visit(const StepEnv& e, int sp, Trk& t, StepOut& o, Trk& before, int max_steps, Sink& sink) {
+  int k = 0;
+  for (;;) {
+    before = t;
+    const double e0 = t.E;
+    take_step_k<KIND>(e, sp, t, o);
+    ++k;
+    if (o.nsec > 0) return k;
+    sink.apply(sp, t, o, e0);
+    if (t.slab < 0 || k >= max_steps) return k;
   }
 }
 

@@ -103,6 +103,7 @@ MatFull derive_material(const MaterialIn& in) {
   const double fc = az2 * (1.0 / (1.0 + az2) + 0.20206 + az2 * (-0.0369 + az2 * (0.0083 - 0.002 * az2)));
   m.rt.c136 = 136.0 / cbrt(in.Z);
   m.rt.gshift = log(in.Z) / 3.0 + fc;
+  m.rt.up_em[0] = m.rt.up_em[1] = m.rt.up_ep[0] = m.rt.up_ep[1] = 0.0;
   return m;
 }
 
@@ -263,6 +264,10 @@ TableSet build_tables(const TableParams& p, const std::vector<MaterialIn>& mats)
         if (E >= pr[i].th) s += interp_at(pr[i].t, E);
       return s;
     };
+    ts.rt[mi].up_em[0] = upper_total(pe, 2, pe[0].th);
+    ts.rt[mi].up_em[1] = upper_total(pe, 2, pe[1].th);
+    ts.rt[mi].up_ep[0] = upper_total(pp, 3, pp[0].th);
+    ts.rt[mi].up_ep[1] = upper_total(pp, 3, pp[1].th);
     for (int which = 0; which < 2; ++which) {
       const Proc* pr = which ? pp : pe;
       const int np = which ? 3 : 2;

@@ -27,9 +27,9 @@ def E():
 
 
 def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
-            blocks=0):
+            blocks=0, visit=16):
     c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
-                      profile_capacity=profile_cap, launch_blocks=blocks)
+                      profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit)
     t = E.Transport(c, geo)
     if keys is not None:
         t.set_event_keys(keys)
@@ -73,7 +73,8 @@ def test_random_tracks_everywhere(E, oracle_mod):
 def test_1gev_32_events_all_slabs(E, oracle_mod):
     print("1 GeV x 32", flush=True)
     geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
-    g = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER | E.F_PROFILE, profile_cap=20000)
+    # one step of the whole population per iteration, as in the paper's loop
+    g = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER | E.F_PROFILE, profile_cap=20000, visit=1)
     r = oracle_mod.Oracle(geo, cfg).run(prim, profile_cap=20000)
     assert np.array_equal(g["ledger"]["n_steps"], r["ledger"]["n_steps"])
     assert np.array_equal(g["ledger"]["n_created"], r["ledger"]["n_created"])
@@ -85,11 +86,26 @@ def test_1gev_32_events_all_slabs(E, oracle_mod):
     assert g["stats"]["steps"] == [int(x) for x in r["profile"].sum(axis=0)]
 
 
+@pytest.mark.parametrize("visit", [2, 16, 1024])
+def test_visit_length_does_not_change_results(E, visit):
+    print(f"visit length {visit}", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, flags=E.F_FULL_LEDGER)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=visit, flags=E.F_FULL_LEDGER)
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
+    assert a["stats"]["steps"] == b["stats"]["steps"]
+    assert b["stats"]["iterations"] < a["stats"]["iterations"]
+
+
 def test_capacity_deferral_gives_identical_results(E):
     print("deferral", flush=True)
     geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
     a = run_gpu(E, geo, cfg, prim[:8], 8, capacity=1 << 20)
     b = run_gpu(E, geo, cfg, prim[:8], 8, capacity=256)
+    c = run_gpu(E, geo, cfg, prim[:8], 8, capacity=256, visit=1)
+    assert np.allclose(a["edep"], c["edep"], rtol=1e-12, atol=1e-12)
     assert b["stats"]["deferred"] > 0 and a["stats"]["deferred"] == 0
     assert max(b["stats"]["peak_live"]) <= 256
     assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
@@ -171,7 +187,7 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     print(f"full size {name}", flush=True)
     geo, cfg, prim = I.workload(name)
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 24)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=8 << 20)  # as bench.py
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
