@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
     ap.add_argument("--steps-per-visit", type=int, default=16)
+    ap.add_argument("--refill-below", type=int, default=8)
     ap.add_argument("--cpu-events", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -95,7 +96,8 @@ def main():
     geo, cfg, prim = I.workload(args.workload)
     n = len(prim)
     c = E.make_config(cfg, n, track_capacity=args.capacity, steps_per_launch=args.steps_per_launch,
-                      launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit)
+                      launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit,
+                      refill_below=args.refill_below)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -111,6 +113,7 @@ def main():
     launches = 0
     steps = [0, 0, 0]
     created = [0, 0, 0]
+    visits = [0, 0, 0]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         edep = one_step()
@@ -119,12 +122,15 @@ def main():
         launches += s["launches"]
         steps = [a + b for a, b in zip(steps, s["steps"])]
         created = [a + b for a, b in zip(created, s["created"])]
+        visits = [a + b for a, b in zip(visits, s["visits"])]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     eng.close()
 
     value = n * args.steps / dt
-    alg_bytes = TRACK_BYTES * (2 * sum(steps) + sum(created))
+    # each visit reads one track record and writes at most one (survivor or
+    # carried track); each secondary record is written once
+    alg_bytes = TRACK_BYTES * (2 * sum(visits) + sum(created))
     per_launch = alg_bytes / max(launches, 1)
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
@@ -144,7 +150,8 @@ def main():
         "config": {"workload": args.workload, "events": n, "primary": "e-", "energy_MeV": float(prim["ekin"][0]),
                    "geometry": "50 x (2.3 mm Pb + 5.7 mm lAr), 40x40 cm", "bz_tesla": cfg.bz_tesla,
                    "precision": "fp64", "track_steps_per_step": sum(steps) // args.steps,
-                   "steps_per_visit": args.steps_per_visit},
+                   "visits_per_step": sum(visits) // args.steps,
+                   "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_visit (photon + e-/e+ launch per iteration)", "bytes_per_launch": per_launch,

@@ -107,6 +107,10 @@ typedef struct {
                                     creates secondaries (results do not
                                     depend on it); 1 = strictly one step of
                                     the whole population per iteration      */
+  uint32_t refill_below;         /* a wave commits the visits that ended and
+                                    refills those lanes once at most this
+                                    many of its 64 lanes are still stepping
+                                    (0..63; results do not depend on it)    */
 } ems_config;
 
 /* One primary track (64 bytes). event is the tally row (< max_events); the
@@ -158,6 +162,8 @@ typedef struct {
   double step_kernel_ms;         /* device time of the step launches, from
                                     HIP events around each chain of launches
                                     on the bound stream (gaps included)     */
+  uint64_t visits[3];            /* track records loaded per species (one
+                                    per visit of a thread to a track)       */
 } ems_run_stats;
 
 typedef struct ems_ctx ems_ctx;

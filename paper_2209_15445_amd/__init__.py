@@ -44,13 +44,14 @@ class Config(C.Structure):
                 ("flags", C.c_uint32), ("max_steps_per_track", C.c_uint32), ("seed", C.c_uint32),
                 ("max_events", C.c_uint32), ("track_capacity", C.c_uint64), ("steps_per_launch", C.c_uint32),
                 ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
-                ("steps_per_visit", C.c_uint32)]
+                ("steps_per_visit", C.c_uint32), ("refill_below", C.c_uint32)]
 
 
 class RunStats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("steps", C.c_uint64 * 3), ("created", C.c_uint64 * 3),
                 ("deferred", C.c_uint64), ("launches", C.c_uint64), ("peak_live", C.c_uint32 * 3),
-                ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double)]
+                ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double),
+                ("visits", C.c_uint64 * 3)]
 
 
 LEDGER_DTYPE = np.dtype([("edep", "<f8"), ("escaped", "<f8", (3,)), ("killed", "<f8"), ("charged_len", "<f8"),
@@ -133,7 +134,7 @@ class _GeoHolder:
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
-                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16):
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=8):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
     c = Config()
@@ -150,6 +151,7 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
     c.steplog_capacity = steplog_capacity
     c.profile_capacity = profile_capacity
     c.steps_per_visit = steps_per_visit
+    c.refill_below = refill_below
     return c
 
 
@@ -276,4 +278,4 @@ class Transport:
         _check(lib().ems_stats(self._h, C.byref(s)))
         return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
-                    run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms)
+                    run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits))

@@ -78,6 +78,7 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
   if (c->max_steps_per_track < 1 || c->max_events < 1) return fail(EMS_E_INVALID, "max_steps and max_events >= 1");
   if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");
+  if (c->refill_below > 63) return fail(EMS_E_INVALID, "refill_below in [0, 63]");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
     return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
   return EMS_OK;
@@ -308,6 +309,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.lds_g = lds_g;
   a.lds_l = lds_l;
   a.steps_per_visit = cfg->steps_per_visit;
+  a.refill_below = cfg->refill_below;
   a.env = env_for(cfg, geo, c->ts);
   int per_g = 0, per_l = 0;
   if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
@@ -443,6 +445,7 @@ ems_status ems_run(ems_ctx* c) {
   st.iterations = s.iteration;
   for (int i = 0; i < 3; ++i) {
     st.steps[i] = s.steps[i];
+    st.visits[i] = s.visits[i];
     st.created[i] = s.created[i];
     st.peak_live[i] = s.peak[i];
   }
@@ -620,11 +623,16 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
     if (cur[0].empty() && cur[1].empty() && cur[2].empty()) break;
     for (int sp = 0; sp < 3; ++sp) {
       for (Trk t : cur[sp]) {
-        Trk before;
+        VisitState vs;
         StepOut o;
-        visit<2>(env, sp, t, o, before, max_visit, sink);
+        visit_begin<2>(env, sp, t, vs);
+        for (;;) {
+          const double e0 = t.E;
+          const bool end = visit_step<2>(env, sp, vs, t, o, max_visit);
+          sink.apply(sp, t, o, e0);
+          if (end) break;
+        }
         if (o.nsec > 0) {
-          sink.apply(sp, t, o, before.E);
           for (int k = 0; k < o.nsec; ++k) {
             const Sec& s = o.sec[k];
             nxt[s.sp].push_back(Trk{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});

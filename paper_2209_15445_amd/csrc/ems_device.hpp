@@ -55,8 +55,9 @@ struct Ctl {
   uint32_t peak[3];
   uint32_t commits;       // steps taken in the running launch
   uint32_t carried;       // live tracks carried unstepped in the running launch
-  uint32_t pad0;
+  uint32_t cursor[2];     // next queue index handed out (photon, e-/e+ launch)
   unsigned long long steps[3], created[3], deferred, log_n;
+  unsigned long long visits[3];  // track records loaded (one per visit)
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
@@ -108,6 +109,7 @@ struct KArgs {
   uint32_t n_mat;
   uint32_t lds_g, lds_l;      // dynamic LDS of the photon / lepton kernels
   uint32_t steps_per_visit;   // steps a thread may take per launch
+  uint32_t refill_below;      // batch commit/refill when at most this many lanes still step
   StepEnv env;         // scalars; its pointers are set per block
 };
 

@@ -155,11 +155,22 @@ __device__ StepEnv stage(const KArgs& a, double* lds, bool photons) {
 }  // namespace
 
 // One iteration for the photons (PHOTONS) or for the e-/e+ (otherwise).
+//
+// Batched lane refill: the lanes of a wave keep stepping their tracks while
+// more than refill_below of them are still inside a visit.  Then the lanes
+// whose visit ended commit together (secondaries, survivors, carried tracks:
+// a few atomics for the whole batch) and empty lanes take the next tracks of
+// the queue from a per-launch cursor.  Lanes thus stay busy instead of
+// waiting for the wave's longest visit, without paying one atomic per track.
+// The order in which tracks are visited does not change any result.
 #ifndef EMS_PHOTON_WAVES
-#define EMS_PHOTON_WAVES 1
+#define EMS_PHOTON_WAVES 2
+#endif
+#ifndef EMS_LEPTON_WAVES
+#define EMS_LEPTON_WAVES 2
 #endif
 template <bool PHOTONS>
-__global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : 1) void k_visit(KArgs a) {
+__global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAVES) void k_visit(KArgs a) {
   extern __shared__ double lds[];
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
@@ -168,6 +179,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : 1) void k_visi
   const uint32_t nmine = PHOTONS ? n0 : n1 + n2;
   const uint32_t need = (nmine + kBlock - 1) / kBlock;
   const bool work = blockIdx.x < need && ctl->error == 0;
+  constexpr int KIND = PHOTONS ? 0 : 1;
 
   if (work) {
     const StepEnv env = stage(a, lds, PHOTONS);
@@ -177,130 +189,179 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : 1) void k_visi
     const uint32_t lim0 = (uint32_t)(a.cap - n0), lim1 = (uint32_t)(a.cap - n1), lim2 = (uint32_t)(a.cap - n2);
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
                  (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u};
+    uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
 
-    for (uint32_t base = blockIdx.x * kBlock; base < nmine; base += gridDim.x * kBlock) {
-      const uint32_t i = base + threadIdx.x;
-      const bool active = i < nmine;
-      int sp = PHOTONS ? 0 : 1;
-      uint32_t idx = i, home = PHOTONS ? h0 : h1;
-      if (!PHOTONS && i >= n1) {
-        sp = 2;
-        idx = i - n1;
-        home = h2;
-      }
-      const uint32_t pos = queue_pos(idx, home, a.cap);
-      const Queue src = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
-      Trk t, before;
-      StepOut o;
-      o.nsec = 0;
-      bool live_in = false;
-      sink.applied = 0;
-      if (active) {
-        t.slab = src.slab[pos];
-        live_in = t.slab >= 0;  // slots of refused secondaries hold slab -1
-        t.ev = live_in ? src.ev[pos] : 0u;
-        // a record that would index outside the tallies or the slab stack is
-        // reported, never used
-        if (live_in && (t.slab >= (int32_t)a.env.n_slabs || t.ev >= a.max_events)) {
-          atomicOr(&ctl->error, kErrCorrupt);
-          live_in = false;
-        }
-      }
-      if (live_in) {
-        t.x = src.x[pos];
-        t.y = src.y[pos];
-        t.z = src.z[pos];
-        t.ux = src.ux[pos];
-        t.uy = src.uy[pos];
-        t.uz = src.uz[pos];
-        t.E = src.E[pos];
-        t.id = src.id[pos];
-        t.n = src.n[pos];
-        t.key = a.keys[t.ev];
-        visit<PHOTONS ? 0 : 1>(env, sp, t, o, before, max_visit, sink);
-      }
-
-      // reserve secondary slots (top regions); the last step commits only if
-      // all of its secondaries fit
-      uint32_t d[3];
+    bool has = false;   // lane holds a track (inside a visit or waiting to commit)
+    bool fin = false;   // its visit ended; outputs wait for the batch commit
+    bool drained = false;
+    int sp = PHOTONS ? 0 : 1;
+    Trk t, before;
+    VisitState vs;
+    StepOut o;
+    o.nsec = 0;
+    uint32_t visits_e = 0, visits_p = 0, steps_e = 0, steps_p = 0, carried_n = 0;
+    uint32_t made0 = 0, made1 = 0, made2 = 0;
+    for (;;) {
+      const uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin));
+      const bool any_fin = __ballot(fin) != 0;
+      // batch point: few lanes still stepping (or none, once the queue is drained)
+      if (stepping <= (drained ? 0u : a.refill_below)) {
+        if (any_fin) {
+          // secondaries into the top regions (a step commits only if all of
+          // its secondaries fit), then survivors or carried tracks
+          uint32_t d[3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        d[q] = (o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
-      uint32_t slot[3];
-      bool fits = true;
+          for (int q = 0; q < 3; ++q)
+            d[q] = (fin && o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (fin && o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
+          uint32_t slot[3];
+          bool fits = true;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        slot[q] = wave_reserve(&ctl->next_sec[q], d[q]);
-        const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
-        if (d[q] && slot[q] + d[q] > lim) fits = false;
-      }
-      const bool pending = o.nsec > 0;
-      const bool commit = pending && fits;
+          for (int q = 0; q < 3; ++q) {
+            slot[q] = wave_reserve(&ctl->next_sec[q], d[q]);
+            const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
+            if (d[q] && slot[q] + d[q] > lim) fits = false;
+          }
+          const bool pending = fin && o.nsec > 0;
+          const bool commit = pending && fits;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        if (!d[q]) continue;
-        const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
-        const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
-        uint32_t s = slot[q];
+          for (int q = 0; q < 3; ++q) {
+            if (!d[q]) continue;
+            const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
+            const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+            uint32_t s = slot[q];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          if (!(k < o.nsec && o.sec[k].sp == q)) continue;
-          if (s < lim) {
-            const uint32_t p = (uint32_t)(a.cap - 1 - s);
-            if (commit) {
-              Trk c;
-              c.x = t.x;
-              c.y = t.y;
-              c.z = t.z;
-              c.ux = o.sec[k].ux;
-              c.uy = o.sec[k].uy;
-              c.uz = o.sec[k].uz;
-              c.E = o.sec[k].E;
-              c.id = o.sec[k].id;
-              c.ev = t.ev;
-              c.n = 0;
-              c.slab = o.slab;
-              store_track(dq, p, c);
-            } else {
-              dq.slab[p] = -1;  // refused: the next iteration skips this slot
+            for (int k = 0; k < 2; ++k) {
+              if (!(k < o.nsec && o.sec[k].sp == q)) continue;
+              if (s < lim) {
+                const uint32_t p = (uint32_t)(a.cap - 1 - s);
+                if (commit) {
+                  Trk c;
+                  c.x = t.x;
+                  c.y = t.y;
+                  c.z = t.z;
+                  c.ux = o.sec[k].ux;
+                  c.uy = o.sec[k].uy;
+                  c.uz = o.sec[k].uz;
+                  c.E = o.sec[k].E;
+                  c.id = o.sec[k].id;
+                  c.ev = t.ev;
+                  c.n = 0;
+                  c.slab = o.slab;
+                  store_track(dq, p, c);
+                } else {
+                  dq.slab[p] = -1;  // refused: the next iteration skips this slot
+                }
+              }
+              ++s;
             }
           }
-          ++s;
+          if (commit) {
+            sink.apply(sp, t, o, before.E);
+            if (sp == 2) ++steps_p;
+            else ++steps_e;
+            made0 += d[0];
+            made1 += d[1];
+            made2 += d[2];
+          }
+          const bool carry = pending && !commit;  // back to the state before the last step
+          if (carry) ++carried_n;
+          const bool keep = fin && (carry ? before.slab >= 0 : t.slab >= 0);
+          // (one counter per wave_reserve call: a wave may hold e- and e+)
+#pragma unroll
+          for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
+            const bool mine = keep && sp == q;
+            const uint32_t hs = wave_reserve(&ctl->next_home[q], mine ? 1u : 0u);
+            if (mine) {
+              const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+              if (hs >= a.cap) atomicOr(&ctl->error, kErrOverflow);
+              else if (carry) store_track(dq, hs, before);
+              else store_track(dq, hs, t);
+            }
+          }
+          if (fin) {
+            has = false;
+            fin = false;
+            o.nsec = 0;
+          }
+        }
+        // refill empty lanes
+        if (!drained) {
+          const bool want = !has;
+          const uint32_t i = wave_reserve(cursor, want ? 1u : 0u);
+          if (want && i < nmine) {
+            sp = PHOTONS ? 0 : 1;
+            uint32_t idx = i, home = PHOTONS ? h0 : h1;
+            if (!PHOTONS && i >= n1) {
+              sp = 2;
+              idx = i - n1;
+              home = h2;
+            }
+            const uint32_t pos = queue_pos(idx, home, a.cap);
+            const Queue src = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
+            t.slab = src.slab[pos];
+            t.ev = t.slab >= 0 ? src.ev[pos] : 0u;
+            has = t.slab >= 0;  // slots of refused secondaries hold slab -1
+            // a record that would index outside the tallies or the slab
+            // stack is reported, never used
+            if (has && (t.slab >= (int32_t)a.env.n_slabs || t.ev >= a.max_events)) {
+              atomicOr(&ctl->error, kErrCorrupt);
+              has = false;
+            }
+            if (has) {
+              t.x = src.x[pos];
+              t.y = src.y[pos];
+              t.z = src.z[pos];
+              t.ux = src.ux[pos];
+              t.uy = src.uy[pos];
+              t.uz = src.uz[pos];
+              t.E = src.E[pos];
+              t.id = src.id[pos];
+              t.n = src.n[pos];
+              t.key = a.keys[t.ev];
+              visit_begin<KIND>(env, sp, t, vs);
+              if (sp == 2) ++visits_p;
+              else ++visits_e;
+            }
+          }
+          drained = __ballot(want && i >= nmine) != 0;
+        }
+        if (__ballot(has) == 0) {
+          if (drained) break;
+          continue;
         }
       }
-      if (commit) sink.apply(sp, t, o, before.E);
-      const bool carry = pending && !commit;  // back to the state before the last step
-      const bool keep = live_in && (carry ? before.slab >= 0 : t.slab >= 0);
 
-      // home region: survivors, or tracks carried from before their last step
-      // (one counter per wave_reserve call: a wave may hold e- and e+)
-#pragma unroll
-      for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
-        const bool mine = keep && sp == q;
-        const uint32_t hs = wave_reserve(&ctl->next_home[q], mine ? 1u : 0u);
-        if (mine) {
-          const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
-          if (hs >= a.cap) atomicOr(&ctl->error, kErrOverflow);
-          else if (carry) store_track(dq, hs, before);
-          else store_track(dq, hs, t);
+      // one step of every lane inside a visit
+      if (has && !fin) {
+        before = t;
+        const double e0 = t.E;
+        fin = visit_step<KIND>(env, sp, vs, t, o, max_visit);
+        if (o.nsec == 0) {
+          sink.apply(sp, t, o, e0);
+          if (sp == 2) ++steps_p;
+          else ++steps_e;
         }
       }
+    }
 
-      // statistics and per-launch progress
-      if (PHOTONS) {
-        wave_count(&ctl->steps[0], sink.applied);
-      } else {
-        wave_count(&ctl->steps[1], sp == 1 ? sink.applied : 0u);
-        wave_count(&ctl->steps[2], sp == 2 ? sink.applied : 0u);
-      }
-#pragma unroll
-      for (int q = 0; q < 3; ++q) wave_count(&ctl->created[q], commit ? d[q] : 0u);
-      wave_count(&ctl->deferred, carry ? 1u : 0u);
-      const uint32_t c = wave_sum(sink.applied), k = wave_sum(carry ? 1u : 0u);
-      if (__lane_id() == 0) {
-        if (c) atomicAdd(&ctl->commits, c);
-        if (k) atomicAdd(&ctl->carried, k);
-      }
+    // statistics and per-launch progress
+    if (PHOTONS) {
+      wave_count(&ctl->steps[0], steps_e);
+      wave_count(&ctl->visits[0], visits_e);
+    } else {
+      wave_count(&ctl->steps[1], steps_e);
+      wave_count(&ctl->steps[2], steps_p);
+      wave_count(&ctl->visits[1], visits_e);
+      wave_count(&ctl->visits[2], visits_p);
+    }
+    wave_count(&ctl->deferred, carried_n);
+    wave_count(&ctl->created[0], made0);
+    wave_count(&ctl->created[1], made1);
+    wave_count(&ctl->created[2], made2);
+    const uint32_t c = wave_sum(steps_e + steps_p), k = wave_sum(carried_n);
+    if (__lane_id() == 0) {
+      if (c) atomicAdd(&ctl->commits, c);
+      if (k) atomicAdd(&ctl->carried, k);
     }
   }
 
@@ -343,6 +404,8 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : 1) void k_visi
     ctl->live = live;
     ctl->commits = 0;
     ctl->carried = 0;
+    ctl->cursor[0] = 0;
+    ctl->cursor[1] = 0;
     ctl->cur = cur ^ 1u;
     ctl->blocks_done = 0;
     __threadfence();

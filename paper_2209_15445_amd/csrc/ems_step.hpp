@@ -83,20 +83,12 @@ EMS_HD Bin bin_of(const StepEnv& e, double lnE) {
 }
 EMS_HD double lerp(const double* f, Bin b) { return f[b.j] + b.u * (f[b.j + 1] - f[b.j]); }
 
-// largest node j <= jhi with R_j <= r (clamped to the last bin), then the
-// exact inverse of the range interpolant
+// largest node j <= jhi with R_j <= r (0 if none; clamped to the last bin),
+// then the exact inverse of the range interpolant.  The loss over one step
+// spans few bins, so the scan starts at the track's own bin and walks down.
 EMS_HD double inverse_range(const StepEnv& e, const double* R, double r, int jhi) {
-  int lo = 0, hi = jhi;
-  if (hi > (int)e.nodes - 1) hi = (int)e.nodes - 1;
-  if (r >= R[hi]) {
-    lo = hi;
-  } else if (r >= R[0]) {
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (R[mid] <= r) lo = mid;
-      else hi = mid;
-    }
-  }
+  int lo = jhi > (int)e.nodes - 1 ? (int)e.nodes - 1 : jhi;
+  while (lo > 0 && R[lo] > r) --lo;
   if (lo > (int)e.nodes - 2) lo = (int)e.nodes - 2;
   return exp(e.lnemin + lo * e.dlog + e.dlog * (r - R[lo]) / (R[lo + 1] - R[lo]));
 }
@@ -267,18 +259,20 @@ EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, do
 // the running-maximum table; the values at the thresholds are precomputed
 EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p, bool positron, double a,
                              double b, Bin bb, double lnb, bool from_cut) {
-  const double lna = log(a);
-  double best = total_upper(e, m, p, a, bin_of(e, lna));
-  const double vb = total_upper(e, m, p, b, bb);
-  best = vb > best ? vb : best;
+  double best = total_upper(e, m, p, b, bb);
   const double xb = (lnb - e.lnemin) * e.inv_dlog;
   int jb = (int)ceil(xb) - 1;
   jb = jb > (int)e.nodes - 1 ? (int)e.nodes - 1 : jb;
-  if (jb >= 0) {
-    if (from_cut) {
-      const double v = e.T(m, positron ? tPMep : tPMem)[jb];
-      best = v > best ? v : best;
-    } else {
+  if (from_cut && jb >= 0) {
+    // a is the tracking cut = node 0: the running maximum covers a and the
+    // nodes below b
+    const double v = e.T(m, positron ? tPMep : tPMem)[jb];
+    best = v > best ? v : best;
+  } else {
+    const double lna = log(a);
+    const double va = total_upper(e, m, p, a, bin_of(e, lna));
+    best = va > best ? va : best;
+    if (jb >= 0) {
       const double xa = (lna - e.lnemin) * e.inv_dlog;
       int j = (int)floor(xa) + 1;
       j = j < 0 ? 0 : j;
@@ -353,9 +347,10 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
     scont = R <= e.rho ? R : e.alpha * R + e.rho * (1.0 - e.alpha) * (2.0 - e.rho / R);
   }
   const double smax = scont <= sg ? scont : sg;
-  double elo = T;
+  double elo = T, loss_max = 0.0;
   if (cont) {
-    elo = T - cont_loss(e, Rt, b.j, T, S, R, smax);
+    loss_max = cont_loss(e, Rt, b.j, T, S, R, smax);
+    elo = T - loss_max;
     const double lin = e.lin * R;
     if (smax >= lin) {
       const double e2 = T - lin * S;
@@ -398,7 +393,8 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
   }
   o.step_len = s;
   o.clen += s;
-  const double dE = cont ? cont_loss(e, Rt, b.j, T, S, R, s) : 0.0;
+  // the step ends at s_max unless a discrete interaction came first
+  const double dE = !cont ? 0.0 : (lim == kLimDiscrete ? cont_loss(e, Rt, b.j, T, S, R, s) : loss_max);
   o.dep += dE;
   const double Tp = T - dE;
   t.E = Tp;
@@ -484,18 +480,132 @@ EMS_HD void take_step(const StepEnv& e, int sp, Trk& t, StepOut& o) { take_step_
 // holds it, `before` holds the track as it was before that step, and the
 // caller either commits it (sink.apply + push) or carries `before`.
 // Returns the number of steps taken.
-template <int KIND, class Sink>
-EMS_HD int visit(const StepEnv& e, int sp, Trk& t, StepOut& o, Trk& before, int max_steps, Sink& sink) {
-  int k = 0;
-  for (;;) {
-    before = t;
-    const double e0 = t.E;
-    take_step_k<KIND>(e, sp, t, o);
-    ++k;
-    if (o.nsec > 0) return k;
-    sink.apply(sp, t, o, e0);
-    if (t.slab < 0 || k >= max_steps) return k;
+// Photon visit state: between interactions a photon keeps its energy and
+// direction, so ln E, its table bin and the inverse direction are computed
+// once per visit; each crossing then costs one Philox block, one log and the
+// geometry.
+struct PhotonCache {
+  Bin b;
+  bool conv;
+  double iux, iuy, iuz;
+};
+
+EMS_HD void photon_begin(const StepEnv& e, const Trk& t, PhotonCache& pc) {
+  pc.b = bin_of(e, log(t.E > e.ecut ? t.E : e.ecut));
+  pc.conv = t.E > 2.0 * kMe;
+  pc.iux = 1.0 / t.ux;
+  pc.iuy = 1.0 / t.uy;
+  pc.iuz = 1.0 / t.uz;
+}
+
+// One photon step with the visit cache: exactly gamma_step followed by the
+// step count and watchdog of take_step.  Returns true when the visit must
+// end after it (the photon interacted or is gone).
+EMS_HD bool photon_substep(const StepEnv& e, const PhotonCache& pc, Trk& t, StepOut& o) {
+  o.nsec = 0;
+  o.slab = t.slab;
+  o.dep = o.escaped = o.killed = o.clen = o.step_len = 0.0;
+  o.pair = o.annih = o.null = 0;
+  o.limiter = 0;
+  o.process = kXNone;
+  const double E = t.E;
+  if (E < e.ecut) {
+    o.dep += E;
+    t.E = 0.0;
+    t.slab = -1;
+    o.limiter = kLimSubcut;
+  } else {
+    const uint32_t m = e.slab_mat[t.slab];
+    const double sc = lerp(e.T(m, tCompt), pc.b);
+    const double sp = lerp(e.T(m, tPhot), pc.b);
+    const double sv = pc.conv ? lerp(e.T(m, tConv), pc.b) : 0.0;
+    const double sig = sc + sp + sv;
+    const double h = e.half_xy;
+    const double sz = t.uz > 0.0 ? (e.zplane[t.slab + 1] - t.z) * pc.iuz
+                                 : (t.uz < 0.0 ? (e.zplane[t.slab] - t.z) * pc.iuz : kInf);
+    const double sx = t.ux > 0.0 ? (h - t.x) * pc.iux : (t.ux < 0.0 ? (-h - t.x) * pc.iux : kInf);
+    const double sy = t.uy > 0.0 ? (h - t.y) * pc.iuy : (t.uy < 0.0 ? (-h - t.y) * pc.iuy : kInf);
+    const double sw = sx < sy ? sx : sy;
+    const double sg = sz <= sw ? sz : sw;
+    Draws r;
+    r.init(e.seed, t.key, t.id, t.n);
+    const double sphys = sig > 0.0 ? -log(r.at(0)) / sig : kInf;
+    if (sg <= sphys) {
+      t.x += sg * t.ux;
+      t.y += sg * t.uy;
+      t.z += sg * t.uz;
+      o.step_len = sg;
+      if (sz <= sw) {
+        o.limiter = kLimZ;
+        land_on_plane(e, t, o);
+      } else {
+        o.limiter = kLimWall;
+        o.escaped += t.E;
+        t.E = 0.0;
+        t.slab = -1;
+      }
+    } else {
+      t.x += sphys * t.ux;
+      t.y += sphys * t.uy;
+      t.z += sphys * t.uz;
+      o.step_len = sphys;
+      o.limiter = kLimDiscrete;
+      const double pick = r.at(1) * sig;
+      const V3 u{t.ux, t.uy, t.uz};
+      Outcome oc;
+      if (pick < sc) {
+        o.process = kXCompton;
+        compton(E, u, r, oc);
+      } else if (pick < sc + sp) {
+        o.process = kXPhot;
+        photo(E, u, oc);
+      } else {
+        o.process = kXConv;
+        pair(e.mat[m], E, u, r, oc);
+        o.pair += 1;
+      }
+      settle(e, t, oc, r, o);
+    }
   }
+  t.n += 1;
+  if (t.slab >= 0 && t.n >= e.max_steps) {
+    o.killed += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+  }
+  // any interaction changes E and u (even one whose electron was deposited
+  // on the spot), so the visit ends there
+  return t.slab < 0 || o.limiter == kLimDiscrete;
+}
+
+// Per-lane state of a visit.  KIND: 0 = photons, 1 = e-/e+, 2 = any (host).
+struct VisitState {
+  PhotonCache pc;
+  int steps;  // steps taken in this visit
+};
+
+template <int KIND>
+EMS_HD void visit_begin(const StepEnv& e, int sp, const Trk& t, VisitState& vs) {
+  vs.steps = 0;
+  if (KIND == 0 || (KIND == 2 && sp == kGamma)) photon_begin(e, t, vs.pc);
+}
+
+// One step of a visit; returns true when the visit ends after it.  A visit
+// is a run of consecutive steps of one track by one thread; it ends at a
+// step that creates secondaries, when the track ends, or after max_steps
+// steps.  Every step draws from its own (id, step) stream, so a run of
+// visits is step for step the one-step-at-a-time loop.
+template <int KIND>
+EMS_HD bool visit_step(const StepEnv& e, int sp, VisitState& vs, Trk& t, StepOut& o, int max_steps) {
+  bool end;
+  if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
+    end = photon_substep(e, vs.pc, t, o);
+  } else {
+    take_step_k<1>(e, sp, t, o);
+    end = t.slab < 0;
+  }
+  vs.steps += 1;
+  return end || o.nsec > 0 || vs.steps >= max_steps;
 }
 
 }  // namespace ems

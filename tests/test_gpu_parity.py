@@ -27,9 +27,10 @@ def E():
 
 
 def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
-            blocks=0, visit=16):
+            blocks=0, visit=16, refill=8):
     c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
-                      profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit)
+                      profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit,
+                      refill_below=refill)
     t = E.Transport(c, geo)
     if keys is not None:
         t.set_event_keys(keys)
@@ -97,6 +98,17 @@ def test_visit_length_does_not_change_results(E, visit):
         assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
     assert a["stats"]["steps"] == b["stats"]["steps"]
     assert b["stats"]["iterations"] < a["stats"]["iterations"]
+
+
+@pytest.mark.parametrize("refill", [0, 31, 63])
+def test_refill_threshold_does_not_change_results(E, refill):
+    print(f"refill threshold {refill}", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, refill=0, flags=E.F_FULL_LEDGER)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=64, refill=refill, flags=E.F_FULL_LEDGER)
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
 
 
 def test_capacity_deferral_gives_identical_results(E):
