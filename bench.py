@@ -58,6 +58,82 @@ def cpu_baseline(geo, cfg, prim, n_events, threads):
                 sample=f"first {n_events} events of the workload, {len(ts)} threads, {dt:.1f} s wall")
 
 
+def serving(E, I, args):
+    """Offload-server leg: a pool of requests (1..200 tracks, lognormal total
+    energy, mixed species, Bz 3.8 T) first submitted as fast as producers can
+    (saturated throughput), then at 80% of that request rate with Poisson
+    arrivals (latency p50/p99 from submission to completion)."""
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=5, bz_tesla=3.8)
+    P = args.serve_producers
+    pools = []
+    for p in range(P):
+        rng = np.random.Generator(np.random.Philox(5 + p))
+        pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
+    c = E.make_config(cfg, args.serve_slots, track_capacity=args.capacity, steps_per_launch=4,
+                      steps_per_visit=args.steps_per_visit, refill_below=args.refill_below)
+    srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
+
+    def closed(p, n, out):
+        ts = [srv.submit(pools[p][i % len(pools[p])], p * 1_000_000 + i) for i in range(n)]
+        for t in ts:
+            srv.wait(t, timeout_s=300)
+        out[p] = sum(len(pools[p][i % len(pools[p])]) for i in range(n))
+
+    # warm-up, then the saturated phase
+    out = [0] * P
+    closed(0, 16, out)
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=closed, args=(p, args.serve_requests // P, out)) for p in range(P)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    wall = time.perf_counter() - t0
+    sat = srv.stats()
+    n_req = (args.serve_requests // P) * P
+    sat_rps = n_req / wall
+    res = {"workload": "serving: requests of U{1..200} e-/e+/gamma tracks, lognormal(ln 5 GeV, 1) total, Bz 3.8 T",
+           "slots": args.serve_slots, "producers": P, "admit_cap_bytes": args.serve_admit_gib << 30,
+           "saturated": {"requests": n_req, "primaries_per_s": sum(out) / wall, "requests_per_s": sat_rps,
+                         "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
+                         "peak_admitted_bytes": sat["peak_admitted_bytes"]}}
+    # Poisson arrivals at 80% of the saturated request rate
+    rate = 0.8 * sat_rps / P
+    n_each = max(1, int(rate * args.serve_seconds))
+    srv.reset_stats()
+
+    def open_loop(p):
+        rng = np.random.default_rng(100 + p)
+        gaps = rng.exponential(1.0 / rate, n_each)
+        t_next = time.perf_counter()
+        ts = []
+        for i in range(n_each):
+            t_next += gaps[i]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ts.append(srv.submit(pools[p][i % len(pools[p])], 500_000 + p * 1_000_000 + i))
+        for t in ts:
+            srv.wait(t, timeout_s=300)
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=open_loop, args=(p,)) for p in range(P)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    wall = time.perf_counter() - t0
+    po = srv.stats()
+    srv.close()
+    res["poisson_80pct"] = {"requests": n_each * P, "offered_requests_per_s": rate * P,
+                            "achieved_requests_per_s": n_each * P / wall, "p50_ms": po["p50_ms"],
+                            "p99_ms": po["p99_ms"], "mean_ms": po["mean_ms"], "max_ms": po["max_ms"],
+                            "primaries_per_s": po["primaries_completed"] / wall}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +147,13 @@ def main():
     ap.add_argument("--refill-below", type=int, default=8)
     ap.add_argument("--cpu-events", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-producers", type=int, default=8)
+    ap.add_argument("--serve-pool", type=int, default=256, help="distinct requests per producer (reused, new keys)")
+    ap.add_argument("--serve-requests", type=int, default=16384)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-admit-gib", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
@@ -158,6 +241,8 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6,
                      "launches": launches},
     }
+    if not args.no_serve:
+        out["serving"] = serving(E, I, args)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(geo, cfg, prim, min(args.cpu_events, n), threads)

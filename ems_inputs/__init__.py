@@ -152,3 +152,30 @@ def random_tracks(n: int, n_events: int, geo: Geometry, e_lo: float, e_hi: float
     d /= np.linalg.norm(d, axis=1)[:, None]
     p["dir"] = d
     return p
+
+
+def serving_request(rng, e_median_MeV: float = 5000.0, sigma: float = 1.0, max_tracks: int = 200,
+                    half_xy_mm: float = 200.0) -> np.ndarray:
+    """One offload request: n ~ U{1..max_tracks} EM tracks of uniformly drawn
+    species; total energy lognormal(ln e_median, sigma) clamped to
+    [10 MeV, 2 TeV], split by a flat Dirichlet with every track >= 1 MeV;
+    positions (N(0, 10 mm), N(0, 10 mm), 0) on the front face; directions +z
+    with independent 1 mrad Gaussian slope smears.  `rng` is a
+    numpy Generator."""
+    etot = float(np.clip(rng.lognormal(math.log(e_median_MeV), sigma), 10.0, 2e6))
+    n = int(rng.integers(1, max_tracks + 1))
+    n = max(1, min(n, int(etot)))
+    w = rng.dirichlet(np.ones(n))
+    p = primaries(n)
+    p["species"] = rng.integers(0, 3, n)
+    p["ekin"] = 1.0 + (etot - n) * w
+    pos = np.zeros((n, 3))
+    pos[:, 0] = np.clip(rng.normal(0.0, 10.0, n), -0.9 * half_xy_mm, 0.9 * half_xy_mm)
+    pos[:, 1] = np.clip(rng.normal(0.0, 10.0, n), -0.9 * half_xy_mm, 0.9 * half_xy_mm)
+    p["pos"] = pos
+    d = np.zeros((n, 3))
+    d[:, 0] = np.tan(rng.normal(0.0, 1e-3, n))
+    d[:, 1] = np.tan(rng.normal(0.0, 1e-3, n))
+    d[:, 2] = 1.0
+    p["dir"] = d / np.linalg.norm(d, axis=1)[:, None]
+    return p

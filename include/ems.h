@@ -63,7 +63,9 @@ enum {
   EMS_F_FULL_LEDGER = 1u << 1, /* per-event step/secondary/null counts and
                                   charged path length (one more atomic per
                                   step); energy terms are always kept       */
-  EMS_F_PROFILE = 1u << 2      /* live tracks per species per iteration     */
+  EMS_F_PROFILE = 1u << 2,     /* live tracks per species per iteration     */
+  EMS_F_EVENT_LIVE = 1u << 3   /* per-event live-track counters (set by the
+                                  offload server to detect finished events) */
 };
 
 typedef struct {
@@ -214,6 +216,65 @@ ems_status ems_stats(ems_ctx* ctx, ems_run_stats* out);
 ems_status ems_destroy(ems_ctx* ctx);
 const char* ems_last_error(void);
 uint32_t ems_abi_version(void);
+
+/* ---------------------------------------------------------------------
+ * Offload server: a device-resident continuous-batching loop in front of one
+ * context, like the paper's hybrid workflow (section 4: particles of a
+ * region are handed to the GPU library, hits come back per event) with the
+ * staggered injection its analysis section proposes (section 5: new
+ * primaries injected while earlier showers are still developing).
+ *
+ * Producers (any number of host threads) submit requests: the EM tracks of
+ * one event.  A driver thread owned by the server admits requests in order
+ * while a tally slot is free and the estimated track-buffer bytes of the
+ * admitted requests stay within admit_cap_bytes, injects them between chunks
+ * of steps_per_launch iterations, detects completed events from per-event
+ * live-track counters, and hands their per-slab deposits and ledger back.
+ * A result depends only on (seed, event_key, tracks): the same request gives
+ * the same deposits alone or in any mix (up to FP64 atomic summation order).
+ * --------------------------------------------------------------------- */
+typedef struct ems_server ems_server;
+
+typedef struct {
+  uint64_t submitted, completed, in_flight, queued;
+  uint64_t admitted_bytes, admit_cap_bytes, peak_admitted_bytes;
+  uint64_t primaries_completed;
+  uint64_t chunks;              /* chunks of iterations launched            */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result latency      */
+  double wall_s;                /* since creation or the last stats reset   */
+  double primaries_per_s;       /* completed primaries / wall_s             */
+} ems_server_info;
+
+/* cfg->max_events is the number of tally slots (events in flight);
+ * EMS_F_STEPLOG and EMS_F_PROFILE are not available in a server.  Workspace
+ * and stream as for ems_create; the stream is used by the driver thread
+ * only.  admit_cap_bytes bounds the estimated track-buffer bytes of admitted
+ * requests (estimate: 152 B x (tracks + 0.1 per MeV of request energy)); a
+ * request larger than the cap is admitted alone. */
+ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, void* d_workspace,
+                             uint64_t bytes, void* hip_stream, uint64_t admit_cap_bytes,
+                             ems_server** out);
+/* Thread-safe.  Copies n (1..65536) tracks (their event field is ignored);
+ * EMS_E_INVALID as for ems_enqueue; EMS_E_BUSY when 2^20 requests wait. */
+ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t n,
+                             uint32_t event_key, uint64_t* ticket);
+/* Thread-safe.  Waits up to timeout_us (< 0: forever) for the ticket and
+ * copies its deposits (edep_out[n_slabs], may be NULL) and ledger (may be
+ * NULL); the ticket is released.  EMS_E_TIMEOUT, EMS_E_INVALID (unknown
+ * ticket), EMS_E_STATE (the device loop failed). */
+ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us,
+                           double* edep_out, ems_ledger* ledger_out);
+/* Thread-safe.  *done = 1 when the ticket's result is ready. */
+ems_status ems_server_poll(ems_server* s, uint64_t ticket, int* done);
+/* Blocks until every request submitted before the call has completed (the
+ * paper's Flush, section 4). */
+ems_status ems_server_flush(ems_server* s);
+ems_status ems_server_stats(ems_server* s, ems_server_info* out);
+/* Restarts the latency and throughput statistics. */
+ems_status ems_server_reset_stats(ems_server* s);
+/* Stops the driver thread (pending requests are dropped) and frees the
+ * server; workspace and stream remain the caller's. */
+ems_status ems_server_destroy(ems_server* s);
 
 /* Host-only table export (no device needed), layout
  * [n_materials][11][n_bins+1] with tables in the order: Compton, photo, pair

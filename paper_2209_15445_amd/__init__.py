@@ -54,6 +54,14 @@ class RunStats(C.Structure):
                 ("visits", C.c_uint64 * 3)]
 
 
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("in_flight", C.c_uint64),
+                ("queued", C.c_uint64), ("admitted_bytes", C.c_uint64), ("admit_cap_bytes", C.c_uint64),
+                ("peak_admitted_bytes", C.c_uint64), ("primaries_completed", C.c_uint64), ("chunks", C.c_uint64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+                ("wall_s", C.c_double), ("primaries_per_s", C.c_double)]
+
+
 LEDGER_DTYPE = np.dtype([("edep", "<f8"), ("escaped", "<f8", (3,)), ("killed", "<f8"), ("charged_len", "<f8"),
                          ("n_steps", "<u8"), ("n_created", "<u8", (3,)), ("n_null", "<u8"), ("n_pair", "<u4"),
                          ("n_annih", "<u4")], align=True)
@@ -94,6 +102,14 @@ def lib():
             "ems_host_tables": [C.POINTER(Config), C.POINTER(Geometry), vp, u64],
             "ems_debug_host_transport": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, u32, vp, vp, vp, vp, u64,
                                          C.POINTER(u64)],
+            "ems_server_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, u64, C.POINTER(vp)],
+            "ems_server_submit": [vp, vp, u32, u32, C.POINTER(u64)],
+            "ems_server_wait": [vp, u64, C.c_int64, vp, vp],
+            "ems_server_poll": [vp, u64, C.POINTER(C.c_int)],
+            "ems_server_flush": [vp],
+            "ems_server_stats": [vp, C.POINTER(ServerInfo)],
+            "ems_server_reset_stats": [vp],
+            "ems_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -279,3 +295,68 @@ class Transport:
         return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
                     run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits))
+
+
+class Server:
+    """Continuous-batching offload server (one driver thread on the device).
+
+    submit() and wait() may be called from any number of threads; ctypes
+    releases the GIL during the calls."""
+
+    def __init__(self, config, geometry, admit_cap_bytes, stream=None, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the server runs only on the GPU")
+        self.config = config
+        self._gh = _GeoHolder(geometry)
+        self.n_slabs = self._gh.n_slabs
+        nbytes = workspace_bytes(config, geometry)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib().ems_server_create(C.byref(config), C.byref(self._gh.g), C.c_void_p(ptr), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream), admit_cap_bytes, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ems_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, tracks, key):
+        p = _prim(tracks)
+        t = C.c_uint64()
+        _check(lib().ems_server_submit(self._h, p.ctypes.data_as(C.c_void_p), len(p), int(key), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout_s=None):
+        edep = np.empty(self.n_slabs)
+        led = np.zeros(1, dtype=LEDGER_DTYPE)
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        _check(lib().ems_server_wait(self._h, ticket, us, edep.ctypes.data_as(C.c_void_p),
+                                     led.ctypes.data_as(C.c_void_p)))
+        return edep, led[0]
+
+    def poll(self, ticket):
+        d = C.c_int()
+        _check(lib().ems_server_poll(self._h, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def flush(self):
+        _check(lib().ems_server_flush(self._h))
+
+    def reset_stats(self):
+        _check(lib().ems_server_reset_stats(self._h))
+
+    def stats(self):
+        s = ServerInfo()
+        _check(lib().ems_server_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerInfo._fields_}

@@ -14,15 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ems.h"
-#include "ems_device.hpp"
-
-namespace ems {
-hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s);
-hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
-hipError_t launch_census(const KArgs& a, hipStream_t s);
-hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
-}  // namespace ems
+#include "ems_runtime.hpp"
 
 using namespace ems;
 
@@ -30,24 +22,23 @@ static_assert(sizeof(ems_primary) == 64, "primary record is 64 bytes");
 static_assert(sizeof(LedgerDev) == sizeof(ems_ledger), "ledger layouts agree");
 static_assert(sizeof(StepRec) == sizeof(ems_step_record), "step record layouts agree");
 
+namespace ems {
 namespace {
-
 thread_local std::string g_err;
-
+}
 ems_status fail(ems_status code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+}  // namespace ems
+
+namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kInjectChunk = 1u << 18;
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Layout {
-  uint64_t ctl, tab, zp, smat, mat, keys, edep, ledger, profile, log, inj, queues, total;
-  uint64_t cap;
-};
 
 ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (!c || !g) return fail(EMS_E_INVALID, "null config or geometry");
@@ -102,6 +93,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.keys = take(c->max_events * 4ull);
   L.edep = take((uint64_t)c->max_events * g->n_slabs * 8);
   L.ledger = take((uint64_t)c->max_events * sizeof(LedgerDev));
+  L.live = take((uint64_t)c->max_events * 4);
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
   L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
@@ -194,35 +186,6 @@ ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary
 
 }  // namespace
 
-struct ems_ctx {
-  ems_config cfg;
-  std::vector<double> z;
-  std::vector<uint32_t> smat;
-  std::vector<ems_material> mats;
-  ems_geometry geo;
-  TableSet ts;
-  Layout L;
-  char* ws = nullptr;
-  hipStream_t stream = nullptr;
-  KArgs args{};
-  uint32_t blocks_g = 0, blocks_l = 0;
-  std::vector<uint64_t> row_count;
-  uint64_t pending[3] = {0, 0, 0};
-  InjRec* pin_inj = nullptr;
-  Ctl* pin_ctl = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool failed = false;
-  ems_run_stats stats{};
-};
-
-#define HIPCHK(ctx, call)                                                                      \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) {                                                                    \
-      (ctx)->failed = true;                                                                    \
-      return fail(EMS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
-    }                                                                                          \
-  } while (0)
 
 extern "C" {
 
@@ -281,6 +244,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
     return bad(fail(EMS_E_DEVICE, "no HIP device"));
+  c->device = dev;
   const uint64_t nodes = cfg->n_bins + 1;
   const uint32_t common = (uint32_t)((geo->n_slabs + 1) * 8 + geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
   const uint32_t lds_g = (uint32_t)(geo->n_materials * kGammaTables * nodes * 8) + common;
@@ -300,6 +264,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.mat = reinterpret_cast<const MatRT*>(c->ws + L.mat);
   a.log = reinterpret_cast<StepRec*>(c->ws + L.log);
   a.profile = reinterpret_cast<uint32_t*>(c->ws + L.profile);
+  a.live_ev = reinterpret_cast<int32_t*>(c->ws + L.live);
   a.cap = L.cap;
   a.max_events = cfg->max_events;
   a.log_cap = (cfg->flags & EMS_F_STEPLOG) ? cfg->steplog_capacity : 0;
@@ -342,8 +307,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
             hipMemcpyAsync(c->ws + L.mat, c->ts.rt.data(), c->ts.rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
             hipMemcpyAsync(c->ws + L.keys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
-            hipMemsetAsync(c->ws + L.edep, 0, (L.ledger - L.edep) + (uint64_t)cfg->max_events * sizeof(LedgerDev), s) ==
-                hipSuccess &&
+            hipMemsetAsync(c->ws + L.edep, 0, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * kTrackBytes, s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -378,28 +342,7 @@ ems_status ems_set_event_keys(ems_ctx* c, uint32_t first, uint32_t n, const uint
 ems_status ems_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
-  if (n == 0) return EMS_OK;
-  if (!p) return fail(EMS_E_INVALID, "null primaries");
-  uint64_t add[3] = {0, 0, 0};
-  for (uint64_t i = 0; i < n; ++i)
-    if (p[i].species <= EMS_POSITRON) add[p[i].species] += 1;
-  for (int s = 0; s < 3; ++s)
-    if (c->pending[s] + add[s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
-  std::vector<uint64_t> rows = c->row_count;
-  std::vector<InjRec> recs;
-  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, recs);
-  if (st) return st;
-  for (uint64_t done = 0; done < n; done += kInjectChunk) {
-    const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // pinned staging is free again
-    memcpy(c->pin_inj, recs.data() + done, k * sizeof(InjRec));
-    InjRec* d = reinterpret_cast<InjRec*>(c->ws + c->L.inj);
-    HIPCHK(c, hipMemcpyAsync(d, c->pin_inj, k * sizeof(InjRec), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_inject(c->args, d, k, c->stream));
-  }
-  c->row_count.swap(rows);
-  for (int s = 0; s < 3; ++s) c->pending[s] += add[s];
-  return EMS_OK;
+  return rt_enqueue(c, p, n);
 }
 
 ems_status ems_run(ems_ctx* c) {
@@ -407,32 +350,10 @@ ems_status ems_run(ems_ctx* c) {
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   const auto t0 = std::chrono::steady_clock::now();
   const uint32_t K = c->cfg.steps_per_launch ? c->cfg.steps_per_launch : 16;
-  HIPCHK(c, launch_census(c->args, c->stream));
-  uint64_t launches = 0;
-  double kms = 0.0;
   for (;;) {
-    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_iteration(c->args, c->blocks_g, c->blocks_l, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-    launches += K;
-    HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    float ms = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    kms += ms;
+    const ems_status st = rt_chunk(c, K);
+    if (st) return st;
     const Ctl& s = *c->pin_ctl;
-    if (s.error & kErrOverflow) {
-      c->failed = true;
-      return fail(EMS_E_CAPACITY, "track queue overflow");
-    }
-    if (s.error & kErrStall) {
-      c->failed = true;
-      return fail(EMS_E_CAPACITY, "track queues too small to make progress");
-    }
-    if (s.error & kErrCorrupt) {
-      c->failed = true;
-      return fail(EMS_E_STATE, "a queue record indexed outside the tallies or the slab stack");
-    }
     if (s.live == 0) break;
     // a track lives at most max_steps iterations; generations are few
     if ((uint64_t)s.iteration > 64ull * c->cfg.max_steps_per_track + 4096) {
@@ -440,20 +361,7 @@ ems_status ems_run(ems_ctx* c) {
       return fail(EMS_E_STATE, "iteration guard reached");
     }
   }
-  const Ctl& s = *c->pin_ctl;
-  ems_run_stats& st = c->stats;
-  st.iterations = s.iteration;
-  for (int i = 0; i < 3; ++i) {
-    st.steps[i] = s.steps[i];
-    st.visits[i] = s.visits[i];
-    st.created[i] = s.created[i];
-    st.peak_live[i] = s.peak[i];
-  }
-  st.deferred = s.deferred;
-  st.launches += launches;
-  st.steplog_overflow = (c->args.log_cap && s.log_n > c->args.log_cap) ? 1u : 0u;
-  st.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  st.step_kernel_ms += kms;
+  c->stats.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < 3; ++i) c->pending[i] = 0;
   return EMS_OK;
 }
@@ -492,6 +400,7 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   const Layout& L = c->L;
   HIPCHK(c, hipMemsetAsync(c->ws + L.edep, 0, (uint64_t)c->cfg.max_events * c->geo.n_slabs * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + L.ledger, 0, (uint64_t)c->cfg.max_events * sizeof(LedgerDev), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + L.live, 0, (uint64_t)c->cfg.max_events * 4, c->stream));
   if (c->args.profile_cap)
     HIPCHK(c, hipMemsetAsync(c->ws + L.profile, 0, (uint64_t)c->args.profile_cap * 12, c->stream));
   // keep the queues (empty after a run) but restart counters and statistics
@@ -655,3 +564,84 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
 }
 
 }  // extern "C"
+
+namespace ems {
+
+ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
+  if (n == 0) return EMS_OK;
+  if (!p) return fail(EMS_E_INVALID, "null primaries");
+  uint64_t add[3] = {0, 0, 0};
+  for (uint64_t i = 0; i < n; ++i)
+    if (p[i].species <= EMS_POSITRON) add[p[i].species] += 1;
+  for (int s = 0; s < 3; ++s)
+    if (c->pending[s] + add[s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
+  std::vector<uint64_t> rows = c->row_count;
+  std::vector<InjRec> recs;
+  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, recs);
+  if (st) return st;
+  for (uint64_t done = 0; done < n; done += kInjectChunk) {
+    const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // pinned staging is free again
+    memcpy(c->pin_inj, recs.data() + done, k * sizeof(InjRec));
+    InjRec* d = reinterpret_cast<InjRec*>(c->ws + c->L.inj);
+    HIPCHK(c, hipMemcpyAsync(d, c->pin_inj, k * sizeof(InjRec), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_inject(c->args, d, k, c->stream));
+  }
+  c->row_count.swap(rows);
+  for (int s = 0; s < 3; ++s) c->pending[s] += add[s];
+  return EMS_OK;
+}
+
+ems_status rt_chunk(ems_ctx* c, uint32_t K) {
+  HIPCHK(c, launch_census(c->args, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_iteration(c->args, c->blocks_g, c->blocks_l, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.0f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  const Ctl& s = *c->pin_ctl;
+  ems_run_stats& st = c->stats;
+  st.step_kernel_ms += ms;
+  st.launches += K;
+  st.iterations = s.iteration;
+  for (int i = 0; i < 3; ++i) {
+    st.steps[i] = s.steps[i];
+    st.visits[i] = s.visits[i];
+    st.created[i] = s.created[i];
+    st.peak_live[i] = s.peak[i];
+  }
+  st.deferred = s.deferred;
+  st.steplog_overflow = (c->args.log_cap && s.log_n > c->args.log_cap) ? 1u : 0u;
+  if (s.error & kErrOverflow) {
+    c->failed = true;
+    return fail(EMS_E_CAPACITY, "track queue overflow");
+  }
+  if (s.error & kErrStall) {
+    c->failed = true;
+    return fail(EMS_E_CAPACITY, "track queues too small to make progress");
+  }
+  if (s.error & kErrCorrupt) {
+    c->failed = true;
+    return fail(EMS_E_STATE, "a queue record indexed outside the tallies or the slab stack");
+  }
+  return EMS_OK;
+}
+
+ems_status rt_zero_rows(ems_ctx* c, uint32_t first, uint32_t n) {
+  const uint64_t row = c->geo.n_slabs * 8ull;
+  HIPCHK(c, hipMemsetAsync(c->ws + c->L.edep + first * row, 0, n * row, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->L.ledger + first * sizeof(LedgerDev), 0, n * sizeof(LedgerDev), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->L.live + first * 4ull, 0, n * 4ull, c->stream));
+  for (uint32_t i = 0; i < n; ++i) c->row_count[first + i] = 0;
+  return EMS_OK;
+}
+
+ems_status rt_read_live(ems_ctx* c, int32_t* host) {
+  HIPCHK(c, hipMemcpyAsync(host, c->ws + c->L.live, c->cfg.max_events * 4ull, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return EMS_OK;
+}
+
+}  // namespace ems

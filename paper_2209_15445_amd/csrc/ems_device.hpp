@@ -86,7 +86,7 @@ struct StepRec {
   double e_before, e_after, pos[3], step_len, edep;
 };
 
-enum : uint32_t { kFlagSteplog = 1u, kFlagFullLedger = 2u, kFlagProfile = 4u };
+enum : uint32_t { kFlagSteplog = 1u, kFlagFullLedger = 2u, kFlagProfile = 4u, kFlagEventLive = 8u };
 
 struct KArgs {
   char* qbase;         // six queue buffers, see queue_view
@@ -101,6 +101,7 @@ struct KArgs {
   const MatRT* mat;
   StepRec* log;
   uint32_t* profile;   // [profile_cap][3]
+  int32_t* live_ev;    // [rows] live tracks per event (kFlagEventLive)
   uint64_t cap;        // tracks per species per buffer
   uint32_t max_events;  // tally rows
   uint64_t log_cap;

@@ -190,6 +190,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
                  (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
+    const bool track_live = (a.flags & kFlagEventLive) != 0;
 
     bool has = false;   // lane holds a track (inside a visit or waiting to commit)
     bool fin = false;   // its visit ended; outputs wait for the batch commit
@@ -277,6 +278,12 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
               else if (carry) store_track(dq, hs, before);
               else store_track(dq, hs, t);
             }
+          }
+          if (fin && track_live) {
+            // net change of the event's live tracks: the visited track ends
+            // or stays, committed secondaries join
+            const int delta = (keep ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
+            if (delta != 0) atomicAdd(&a.live_ev[t.ev], delta);
           }
           if (fin) {
             has = false;
@@ -443,6 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
       t.n = 0;
       t.slab = r.slab;
       store_track(queue_view(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
+      if (a.flags & kFlagEventLive) atomicAdd(&a.live_ev[r.ev], 1);
     }
   }
 }

@@ -1,0 +1,77 @@
+// ems_runtime.hpp -- host runtime internals shared by the C ABI and the
+// offload server (not part of the public interface).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ems.h"
+#include "ems_device.hpp"
+
+namespace ems {
+
+hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s);
+hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
+hipError_t launch_census(const KArgs& a, hipStream_t s);
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
+
+// workspace regions (byte offsets) and the queue capacity
+struct Layout {
+  uint64_t ctl, tab, zp, smat, mat, keys, edep, ledger, live, profile, log, inj, queues, total;
+  uint64_t cap;
+};
+
+// sets the calling thread's error text and returns code
+ems_status fail(ems_status code, const std::string& msg);
+
+}  // namespace ems
+
+struct ems_ctx {
+  using TableSet = ems::TableSet;
+  using Layout = ems::Layout;
+  using KArgs = ems::KArgs;
+  using InjRec = ems::InjRec;
+  using Ctl = ems::Ctl;
+  int device = 0;
+  ems_config cfg;
+  std::vector<double> z;
+  std::vector<uint32_t> smat;
+  std::vector<ems_material> mats;
+  ems_geometry geo;
+  TableSet ts;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  KArgs args{};
+  uint32_t blocks_g = 0, blocks_l = 0;
+  std::vector<uint64_t> row_count;
+  uint64_t pending[3] = {0, 0, 0};
+  InjRec* pin_inj = nullptr;
+  Ctl* pin_ctl = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool failed = false;
+  ems_run_stats stats{};
+};
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (ctx)->failed = true;                                                                    \
+      return fail(EMS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    }                                                                                          \
+  } while (0)
+
+namespace ems {
+// validate, prepare and append n primaries to the current queues (all or
+// nothing); rows listed in fresh_rows restart their track ids at 0
+ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n);
+// K iterations (after a census of the injected tracks); the status block is
+// left in c->pin_ctl; queue errors are returned as status codes
+ems_status rt_chunk(ems_ctx* c, uint32_t K);
+// zero the deposits, ledgers and live counters of rows [first, first + n)
+ems_status rt_zero_rows(ems_ctx* c, uint32_t first, uint32_t n);
+// copy the live-track counters of all rows to host
+ems_status rt_read_live(ems_ctx* c, int32_t* host);
+}  // namespace ems

@@ -1,0 +1,329 @@
+// ems_server.cpp -- continuous-batching offload server over one transport
+// context.
+//
+// The paper's hybrid workflow buffers particles entering the GPU region and
+// processes a batch synchronously, with a Flush call to drain the rest
+// (section 4), and observes that injecting new primaries at regular intervals
+// would let staggered showers overlap on the device (section 5).  Here the
+// device loop never waits for a batch to finish: a driver thread admits
+// requests whenever a tally slot is free and the track-buffer budget allows,
+// injects them between chunks of iterations into the same queues as the
+// showers already in flight, and returns each event as soon as its last
+// track is gone (per-event live-track counters kept by the kernels).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <unordered_map>
+
+#include "ems_runtime.hpp"
+
+using namespace ems;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  uint32_t key = 0;
+  std::vector<ems_primary> tracks;
+  uint64_t add[3] = {0, 0, 0};  // tracks per species
+  uint64_t bytes = 0;           // admission estimate
+  int slot = -1;
+  bool done = false;
+  Clock::time_point t_submit;
+  std::vector<double> edep;
+  ems_ledger ledger{};
+};
+
+constexpr size_t kMaxQueued = 1u << 20;
+constexpr uint32_t kMaxTracks = 65536;
+
+}  // namespace
+
+struct ems_server {
+  ems_ctx* ctx = nullptr;
+  uint64_t cap_bytes = 0;
+  uint32_t chunk = 8;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+  std::set<uint64_t> unfinished;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool failed = false;
+  std::string fail_msg;
+
+  // admission state (under mu)
+  std::vector<std::shared_ptr<Request>> slots;
+  std::vector<uint32_t> free_slots;
+  uint64_t admitted_bytes = 0, peak_bytes = 0, in_flight = 0;
+
+  // statistics (under mu)
+  uint64_t submitted = 0, completed = 0, prim_completed = 0, chunks = 0;
+  std::vector<double> lat_ms;
+  Clock::time_point t0;
+
+  std::thread driver;
+
+  void fail_all(const std::string& msg) {
+    std::lock_guard<std::mutex> lk(mu);
+    failed = true;
+    fail_msg = msg;
+    cv_done.notify_all();
+  }
+
+  void run();
+};
+
+void ems_server::run() {
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    fail_all("driver thread cannot select the device");
+    return;
+  }
+  const uint64_t cap = ctx->L.cap;
+  std::vector<int32_t> live(ctx->cfg.max_events);
+  // tracks in the current queues after the last chunk, plus those injected since
+  uint64_t occupied[3] = {0, 0, 0};
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> admit;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (in_flight == 0 && queue.empty()) cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      if (stop) return;
+      while (!queue.empty() && !free_slots.empty()) {
+        const std::shared_ptr<Request>& r = queue.front();
+        if (in_flight > 0 && admitted_bytes + r->bytes > cap_bytes) break;
+        bool room = true;
+        for (int s = 0; s < 3; ++s) room = room && occupied[s] + r->add[s] <= cap;
+        if (!room) break;
+        for (int s = 0; s < 3; ++s) occupied[s] += r->add[s];
+        r->slot = (int)free_slots.back();
+        free_slots.pop_back();
+        slots[r->slot] = r;
+        admitted_bytes += r->bytes;
+        peak_bytes = std::max(peak_bytes, admitted_bytes);
+        in_flight += 1;
+        admit.push_back(r);
+        queue.pop_front();
+      }
+      if (in_flight == 0) continue;
+    }
+    // inject the admitted events into their slots (driver thread only)
+    for (const std::shared_ptr<Request>& r : admit) {
+      std::vector<ems_primary> p = r->tracks;
+      for (ems_primary& q : p) q.event = (uint32_t)r->slot;
+      ems_status st = rt_zero_rows(ctx, (uint32_t)r->slot, 1);
+      if (!st) st = ems_set_event_keys(ctx, (uint32_t)r->slot, 1, &r->key);
+      for (int s = 0; s < 3; ++s) ctx->pending[s] = 0;  // room was checked above
+      if (!st) st = rt_enqueue(ctx, p.data(), p.size());
+      if (st) {
+        fail_all(std::string("injection failed: ") + ems_last_error());
+        return;
+      }
+    }
+    const ems_status st = rt_chunk(ctx, chunk);
+    if (st) {
+      fail_all(std::string("device loop failed: ") + ems_last_error());
+      return;
+    }
+    for (int s = 0; s < 3; ++s) occupied[s] = ctx->pin_ctl->n_home[s] + ctx->pin_ctl->n_sec[s];
+    if (rt_read_live(ctx, live.data())) {
+      fail_all(std::string("live counters unreadable: ") + ems_last_error());
+      return;
+    }
+    // events whose last track is gone
+    std::vector<std::shared_ptr<Request>> finished;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      chunks += 1;
+      for (size_t i = 0; i < slots.size(); ++i)
+        if (slots[i] && live[i] == 0) finished.push_back(slots[i]);
+    }
+    for (const std::shared_ptr<Request>& r : finished) {
+      r->edep.resize(ctx->geo.n_slabs);
+      if (ems_read_edep(ctx, (uint32_t)r->slot, 1, r->edep.data()) ||
+          ems_read_ledger(ctx, (uint32_t)r->slot, 1, &r->ledger)) {
+        fail_all(std::string("result read-back failed: ") + ems_last_error());
+        return;
+      }
+    }
+    if (!finished.empty()) {
+      const Clock::time_point now = Clock::now();
+      std::lock_guard<std::mutex> lk(mu);
+      for (const std::shared_ptr<Request>& r : finished) {
+        slots[r->slot].reset();
+        free_slots.push_back((uint32_t)r->slot);
+        admitted_bytes -= r->bytes;
+        in_flight -= 1;
+        r->done = true;
+        completed += 1;
+        prim_completed += r->tracks.size();
+        lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+        unfinished.erase(r->ticket);
+      }
+      cv_done.notify_all();
+    }
+  }
+}
+
+extern "C" {
+
+ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws, uint64_t bytes,
+                             void* stream, uint64_t admit_cap_bytes, ems_server** out) {
+  if (!cfg || !out) return fail(EMS_E_INVALID, "null argument");
+  if (cfg->flags & (EMS_F_STEPLOG | EMS_F_PROFILE)) return fail(EMS_E_INVALID, "server: no step log or profile");
+  if (admit_cap_bytes == 0) return fail(EMS_E_INVALID, "admit_cap_bytes must be > 0");
+  ems_config c2 = *cfg;
+  c2.flags |= EMS_F_EVENT_LIVE;
+  ems_ctx* ctx = nullptr;
+  ems_status st = ems_create(&c2, geo, d_ws, bytes, stream, &ctx);
+  if (st) return st;
+  ems_server* s = new ems_server();
+  s->ctx = ctx;
+  s->cap_bytes = admit_cap_bytes;
+  s->chunk = cfg->steps_per_launch ? cfg->steps_per_launch : 8;
+  s->slots.resize(cfg->max_events);
+  for (uint32_t i = cfg->max_events; i-- > 0;) s->free_slots.push_back(i);
+  s->t0 = Clock::now();
+  s->driver = std::thread([s] { s->run(); });
+  *out = s;
+  return EMS_OK;
+}
+
+ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t n, uint32_t key, uint64_t* ticket) {
+  if (!s || !ticket || !tracks) return fail(EMS_E_INVALID, "null argument");
+  if (n < 1 || n > kMaxTracks) return fail(EMS_E_INVALID, "a request holds 1..65536 tracks");
+  auto r = std::make_shared<Request>();
+  r->tracks.assign(tracks, tracks + n);
+  double etot = 0.0;
+  const ems_geometry& g = s->ctx->geo;
+  for (uint32_t i = 0; i < n; ++i) {
+    ems_primary& q = r->tracks[i];
+    q.event = 0;
+    const double d2 = q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2];
+    const bool ok = q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && std::isfinite(q.ekin_MeV) && d2 > 0.0 &&
+                    std::isfinite(d2) && q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] &&
+                    std::fabs(q.pos_mm[0]) <= g.half_xy_mm && std::fabs(q.pos_mm[1]) <= g.half_xy_mm;
+    if (!ok) return fail(EMS_E_INVALID, "invalid track #" + std::to_string(i));
+    r->add[q.species] += 1;
+    etot += q.ekin_MeV;
+  }
+  for (int sp = 0; sp < 3; ++sp)
+    if (r->add[sp] > s->ctx->L.cap) return fail(EMS_E_CAPACITY, "request exceeds the track capacity");
+  // estimated peak tracks of the event in both queue buffers
+  r->bytes = 2 * kTrackBytes * (uint64_t)(n + 0.1 * etot + 1.0);
+  r->key = key;
+  r->t_submit = Clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->failed) return fail(EMS_E_STATE, s->fail_msg);
+  if (s->queue.size() >= kMaxQueued) return fail(EMS_E_BUSY, "request queue full");
+  r->ticket = s->next_ticket++;
+  s->tickets[r->ticket] = r;
+  s->unfinished.insert(r->ticket);
+  s->queue.push_back(r);
+  s->submitted += 1;
+  *ticket = r->ticket;
+  s->cv_work.notify_one();
+  return EMS_OK;
+}
+
+ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us, double* edep_out,
+                           ems_ledger* ledger_out) {
+  if (!s) return fail(EMS_E_INVALID, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(EMS_E_INVALID, "unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  auto ready = [&] { return r->done || s->failed; };
+  if (timeout_us < 0) s->cv_done.wait(lk, ready);
+  else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+    return fail(EMS_E_TIMEOUT, "request not finished yet");
+  if (!r->done) return fail(EMS_E_STATE, s->fail_msg);
+  if (edep_out) std::copy(r->edep.begin(), r->edep.end(), edep_out);
+  if (ledger_out) *ledger_out = r->ledger;
+  s->tickets.erase(ticket);
+  return EMS_OK;
+}
+
+ems_status ems_server_poll(ems_server* s, uint64_t ticket, int* done) {
+  if (!s || !done) return fail(EMS_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(EMS_E_INVALID, "unknown ticket");
+  if (s->failed) return fail(EMS_E_STATE, s->fail_msg);
+  *done = it->second->done ? 1 : 0;
+  return EMS_OK;
+}
+
+ems_status ems_server_flush(ems_server* s) {
+  if (!s) return fail(EMS_E_INVALID, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  const uint64_t target = s->next_ticket - 1;
+  s->cv_done.wait(lk, [&] { return s->failed || s->unfinished.empty() || *s->unfinished.begin() > target; });
+  if (s->failed) return fail(EMS_E_STATE, s->fail_msg);
+  return EMS_OK;
+}
+
+ems_status ems_server_stats(ems_server* s, ems_server_info* out) {
+  if (!s || !out) return fail(EMS_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  ems_server_info st{};
+  st.submitted = s->submitted;
+  st.completed = s->completed;
+  st.in_flight = s->in_flight;
+  st.queued = s->queue.size();
+  st.admitted_bytes = s->admitted_bytes;
+  st.admit_cap_bytes = s->cap_bytes;
+  st.peak_admitted_bytes = s->peak_bytes;
+  st.primaries_completed = s->prim_completed;
+  st.chunks = s->chunks;
+  std::vector<double> v = s->lat_ms;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
+    st.p50_ms = q(0.50);
+    st.p99_ms = q(0.99);
+    double sum = 0.0;
+    for (double x : v) sum += x;
+    st.mean_ms = sum / v.size();
+    st.max_ms = v.back();
+  }
+  st.wall_s = std::chrono::duration<double>(Clock::now() - s->t0).count();
+  st.primaries_per_s = st.wall_s > 0 ? st.primaries_completed / st.wall_s : 0.0;
+  *out = st;
+  return EMS_OK;
+}
+
+ems_status ems_server_reset_stats(ems_server* s) {
+  if (!s) return fail(EMS_E_INVALID, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->lat_ms.clear();
+  s->completed = s->prim_completed = s->submitted = s->chunks = 0;
+  s->peak_bytes = s->admitted_bytes;
+  s->t0 = Clock::now();
+  return EMS_OK;
+}
+
+ems_status ems_server_destroy(ems_server* s) {
+  if (!s) return EMS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->driver.joinable()) s->driver.join();
+  ems_destroy(s->ctx);
+  delete s;
+  return EMS_OK;
+}
+
+}  // extern "C"

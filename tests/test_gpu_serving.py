@@ -1,0 +1,104 @@
+"""GPU tests of the continuous-batching offload server: a request's result is
+the same alone and mixed with concurrent requests from many producer threads,
+equals the oracle's for the same tracks and event key, conserves energy, and
+the server drains (Flush) and respects its admission budget."""
+import threading
+
+import numpy as np
+import pytest
+
+import ems_inputs as I
+from parity_util import ME
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_15445_amd as E
+    E.lib()
+    return E
+
+
+def make_server(E, slots=64, cap_bytes=1 << 30, capacity=1 << 20, bz=3.8):
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=5, bz_tesla=bz)
+    c = E.make_config(cfg, slots, track_capacity=capacity, steps_per_launch=4)
+    return geo, cfg, E.Server(c, geo, cap_bytes)
+
+
+def residual(edep, led, tracks):
+    out = edep.sum() + led["escaped"].sum() + led["killed"] + 2 * ME * (int(led["n_pair"]) - int(led["n_annih"]))
+    return abs(out - tracks["ekin"].sum()) / tracks["ekin"].sum()
+
+
+def test_same_result_alone_and_in_the_mix(E, oracle_mod):
+    print("alone vs mix", flush=True)
+    rng = np.random.Generator(np.random.Philox(55))
+    probe = I.serving_request(rng, e_median_MeV=2000.0, max_tracks=30)
+    key = 777
+    geo, cfg, srv = make_server(E)
+    alone_edep, alone_led = srv.wait(srv.submit(probe, key), timeout_s=120)
+    srv.close()
+
+    geo, cfg, srv = make_server(E, slots=24)
+    results = {}
+    reqs = {}
+
+    def producer(p):
+        r = np.random.Generator(np.random.Philox(1000 + p))
+        mine = []
+        for i in range(12):
+            tr = I.serving_request(r, e_median_MeV=1000.0, max_tracks=40)
+            k = p * 1000 + i
+            mine.append((srv.submit(tr, k), tr, k))
+            if p == 3 and i == 5:
+                mine.append((srv.submit(probe, key), probe, key))
+        for t, tr, k in mine:
+            results[t] = srv.wait(t, timeout_s=300)
+            reqs[t] = (tr, k)
+
+    ths = [threading.Thread(target=producer, args=(p,)) for p in range(8)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    st = srv.stats()
+    srv.close()
+    assert len(results) == 8 * 12 + 1 and st["completed"] == len(results)
+    probe_t = [t for t, (tr, k) in reqs.items() if k == key][0]
+    mix_edep, mix_led = results[probe_t]
+    assert np.allclose(mix_edep, alone_edep, rtol=1e-12, atol=1e-12)
+    for f in ("n_pair", "n_annih"):
+        assert mix_led[f] == alone_led[f]
+    for t, (edep, led) in results.items():
+        assert residual(edep, led, reqs[t][0]) < 1e-9
+    # the oracle, given the same tracks and event key, gives the same deposits
+    p = probe.copy()
+    p["event"] = 0
+    r = oracle_mod.Oracle(geo, cfg).run(p, n_events=1, event_keys=[key])
+    assert np.allclose(alone_edep, r["edep"][0], rtol=1e-8, atol=1e-8)
+
+
+def test_flush_admission_and_errors(E):
+    print("flush / admission", flush=True)
+    cap = 40 << 20
+    geo, cfg, srv = make_server(E, slots=16, cap_bytes=cap)
+    rng = np.random.Generator(np.random.Philox(9))
+    tickets = [srv.submit(I.serving_request(rng, e_median_MeV=3000.0, max_tracks=50), k) for k in range(60)]
+    srv.flush()
+    assert all(srv.poll(t) for t in tickets)
+    st = srv.stats()
+    assert st["completed"] == 60 and st["in_flight"] == 0 and st["queued"] == 0
+    assert st["peak_admitted_bytes"] <= cap
+    bad = I.serving_request(rng)
+    bad["ekin"][0] = -1.0
+    with pytest.raises(E.EmsError) as ei:
+        srv.submit(bad, 1)
+    assert ei.value.code == E.E_INVALID
+    with pytest.raises(E.EmsError):
+        srv.wait(123456789, timeout_s=0.1)
+    srv.close()
