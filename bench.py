@@ -27,6 +27,7 @@ import numpy as np  # noqa: E402
 METRIC = "primaries/sec (10 GeV e-, 50-layer Pb/lAr) FP64 vs mixed; offload p99 ms"
 HBM_PEAK_GBS = 8000.0
 TRACK_BYTES = 76  # FP64 SoA record: pos 24, dir 24, E 8, id 8, event 4, step 4, slab 4
+TRACK_BYTES_MIXED = 64  # mixed form: direction in FP32
 
 
 def cpu_baseline(geo, cfg, prim, n_events, threads):
@@ -58,11 +59,14 @@ def cpu_baseline(geo, cfg, prim, n_events, threads):
                 sample=f"first {n_events} events of the workload, {len(ts)} threads, {dt:.1f} s wall")
 
 
-def serving(E, I, args):
-    """Offload-server leg: a pool of requests (1..200 tracks, lognormal total
-    energy, mixed species, Bz 3.8 T) first submitted as fast as producers can
-    (saturated throughput), then at 80% of that request rate with Poisson
-    arrivals (latency p50/p99 from submission to completion)."""
+def serving(E, I, args, precision):
+    """Offload-server leg.  Requests: U{1..200} e-/e+/gamma tracks, total
+    energy lognormal(ln 5 GeV, 1) clamped to [10 MeV, 2 TeV], Bz 3.8 T, from
+    P producer threads (a pool of distinct requests per producer, reused
+    with fresh event keys).  First the saturated closed loop (each producer
+    keeps a window of requests outstanding), then Poisson arrivals at 80% of
+    that request rate; latency is submission to completion, with the first
+    10% of the completions dropped."""
     geo = I.calorimeter()
     cfg = I.RunConfig(seed=5, bz_tesla=3.8)
     P = args.serve_producers
@@ -70,39 +74,53 @@ def serving(E, I, args):
     for p in range(P):
         rng = np.random.Generator(np.random.Philox(5 + p))
         pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
-    c = E.make_config(cfg, args.serve_slots, track_capacity=args.capacity, steps_per_launch=4,
-                      steps_per_visit=args.steps_per_visit, refill_below=args.refill_below)
+    c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity, steps_per_launch=4,
+                      steps_per_visit=args.steps_per_visit, refill_below=args.refill_below, precision=precision)
     srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
+    n_each = max(1, args.serve_requests // P)
+    total = n_each * P
 
-    def closed(p, n, out):
-        ts = [srv.submit(pools[p][i % len(pools[p])], p * 1_000_000 + i) for i in range(n)]
-        for t in ts:
+    def req(p, i):
+        return pools[p][i % len(pools[p])]
+
+    def drop_warmup(target):
+        # clear the statistics once the first 10% of the requests are done
+        t_end = time.perf_counter() + 300
+        while srv.stats()["completed"] < target and time.perf_counter() < t_end:
+            time.sleep(0.002)
+        srv.reset_stats()
+
+    def closed(p, base):
+        pending = []
+        for i in range(n_each):
+            if len(pending) >= args.serve_window:
+                srv.wait(pending.pop(0), timeout_s=300)
+            pending.append(srv.submit(req(p, i), base + p * 1_000_000 + i))
+        for t in pending:
             srv.wait(t, timeout_s=300)
-        out[p] = sum(len(pools[p][i % len(pools[p])]) for i in range(n))
 
-    # warm-up, then the saturated phase
-    out = [0] * P
-    closed(0, 16, out)
     srv.reset_stats()
+    mon = threading.Thread(target=drop_warmup, args=(total // 10,))
     t0 = time.perf_counter()
-    ths = [threading.Thread(target=closed, args=(p, args.serve_requests // P, out)) for p in range(P)]
+    mon.start()
+    ths = [threading.Thread(target=closed, args=(p, 0)) for p in range(P)]
     for t in ths:
         t.start()
     for t in ths:
         t.join()
+    mon.join()
     wall = time.perf_counter() - t0
     sat = srv.stats()
-    n_req = (args.serve_requests // P) * P
-    sat_rps = n_req / wall
+    sat_rps = total / wall
+    prims = sum(len(req(p, i)) for p in range(P) for i in range(n_each))
     res = {"workload": "serving: requests of U{1..200} e-/e+/gamma tracks, lognormal(ln 5 GeV, 1) total, Bz 3.8 T",
-           "slots": args.serve_slots, "producers": P, "admit_cap_bytes": args.serve_admit_gib << 30,
-           "saturated": {"requests": n_req, "primaries_per_s": sum(out) / wall, "requests_per_s": sat_rps,
+           "precision": "fp64" if precision == E.FP64 else "mixed",
+           "slots": args.serve_slots, "producers": P, "window": args.serve_window,
+           "admit_cap_bytes": args.serve_admit_gib << 30,
+           "saturated": {"requests": total, "primaries_per_s": prims / wall, "requests_per_s": sat_rps,
                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
                          "peak_admitted_bytes": sat["peak_admitted_bytes"]}}
-    # Poisson arrivals at 80% of the saturated request rate
     rate = 0.8 * sat_rps / P
-    n_each = max(1, int(rate * args.serve_seconds))
-    srv.reset_stats()
 
     def open_loop(p):
         rng = np.random.default_rng(100 + p)
@@ -114,73 +132,38 @@ def serving(E, I, args):
             d = t_next - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            ts.append(srv.submit(pools[p][i % len(pools[p])], 500_000 + p * 1_000_000 + i))
+            ts.append(srv.submit(req(p, i), 500_000 + p * 1_000_000 + i))
         for t in ts:
             srv.wait(t, timeout_s=300)
 
+    srv.reset_stats()
+    mon = threading.Thread(target=drop_warmup, args=(total // 10,))
     t0 = time.perf_counter()
+    mon.start()
     ths = [threading.Thread(target=open_loop, args=(p,)) for p in range(P)]
     for t in ths:
         t.start()
     for t in ths:
         t.join()
+    mon.join()
     wall = time.perf_counter() - t0
     po = srv.stats()
     srv.close()
-    res["poisson_80pct"] = {"requests": n_each * P, "offered_requests_per_s": rate * P,
-                            "achieved_requests_per_s": n_each * P / wall, "p50_ms": po["p50_ms"],
+    res["poisson_80pct"] = {"requests": total, "offered_requests_per_s": rate * P,
+                            "achieved_requests_per_s": total / wall, "p50_ms": po["p50_ms"],
                             "p99_ms": po["p99_ms"], "mean_ms": po["mean_ms"], "max_ms": po["max_ms"],
-                            "primaries_per_s": po["primaries_completed"] / wall}
+                            "primaries_per_s": prims / wall, "dropped_warmup_requests": total // 10}
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cal_10GeV_e-_x10k")
-    ap.add_argument("--capacity", type=int, default=8 << 20)
-    ap.add_argument("--blocks", type=int, default=0)
-    ap.add_argument("--steps-per-launch", type=int, default=16)
-    ap.add_argument("--steps-per-visit", type=int, default=16)
-    ap.add_argument("--refill-below", type=int, default=8)
-    ap.add_argument("--cpu-events", type=int, default=640)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-slots", type=int, default=4096)
-    ap.add_argument("--serve-producers", type=int, default=8)
-    ap.add_argument("--serve-pool", type=int, default=256, help="distinct requests per producer (reused, new keys)")
-    ap.add_argument("--serve-requests", type=int, default=16384)
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
-    ap.add_argument("--serve-admit-gib", type=int, default=16)
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
-    args = ap.parse_args()
-    if args.copy_probe:
-        import torch
-        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); events shard across GPUs with no "
-              "exchange during transport, so the one-GPU figure is the per-GPU throughput", file=sys.stderr)
-        sys.exit(2)
-
+def transport_leg(E, I, workload, precision, capacity, args):
+    """W warm-up steps, then K timed steps of one workload in one form."""
     import torch
-
-    import ems_inputs as I
-    import paper_2209_15445_amd as E
-
-    geo, cfg, prim = I.workload(args.workload)
+    geo, cfg, prim = I.workload(workload)
     n = len(prim)
-    c = E.make_config(cfg, n, track_capacity=args.capacity, steps_per_launch=args.steps_per_launch,
+    c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                       launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit,
-                      refill_below=args.refill_below)
+                      refill_below=args.refill_below, precision=precision)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -209,22 +192,115 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     eng.close()
-
-    value = n * args.steps / dt
+    tb = TRACK_BYTES if precision == E.FP64 else TRACK_BYTES_MIXED
     # each visit reads one track record and writes at most one (survivor or
     # carried track); each secondary record is written once
-    alg_bytes = TRACK_BYTES * (2 * sum(visits) + sum(created))
+    alg_bytes = tb * (2 * sum(visits) + sum(created))
     per_launch = alg_bytes / max(launches, 1)
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_visit (photon + e-/e+ launch per iteration)", "bytes_per_launch": per_launch,
+            "avg_launch_us": avg_launch_s * 1e6, "launches": launches}
+    return dict(geo=geo, cfg=cfg, prim=prim, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+                track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep)
+
+
+def layer_error(leg, n_events):
+    """Per-layer mean deposit of the mixed form against the FP64 oracle on the
+    first n_events events of the same workload (same event keys, so the pair
+    is correlated): relative error per layer, its RMS and maximum over the
+    layers holding >= 0.1% of the peak, with the statistical error."""
+    import oracle
+    geo, cfg, prim = leg["geo"], leg["cfg"], leg["prim"]
+    k = min(n_events, len(prim))
+    idx = np.arange(k)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    o = oracle.Oracle(geo, cfg)
+    parts = np.array_split(idx, threads)
+    res = [None] * len(parts)
+
+    def work(j):
+        p = prim[parts[j]].copy()
+        p["event"] = np.arange(len(parts[j]))
+        res[j] = o.run(p, n_events=len(parts[j]), event_keys=parts[j].astype(np.uint32))["edep"]
+
+    ts = [threading.Thread(target=work, args=(j,)) for j in range(len(parts)) if len(parts[j])]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    ref = np.concatenate([r for r in res if r is not None])
+    nl = geo.n_slabs // 2
+    lo = ref.reshape(k, nl, 2).sum(axis=2)
+    lm = leg["edep"][:k].reshape(k, nl, 2).sum(axis=2)
+    mo, mm = lo.mean(axis=0), lm.mean(axis=0)
+    live = mo > 1e-3 * mo.max()
+    rel = (mm - mo)[live] / mo[live]
+    stat = np.sqrt(lo.var(axis=0) / k)[live] / mo[live]
+    return {"events": int(k), "layers": int(live.sum()), "rms_rel": float(np.sqrt(np.mean(rel ** 2))),
+            "max_abs_rel": float(np.abs(rel).max()), "mean_stat_rel": float(stat.mean()),
+            "total_rel": float((lm.sum() - lo.sum()) / lo.sum())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cal_10GeV_e-_x10k")
+    ap.add_argument("--capacity", type=int, default=8 << 20)
+    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--steps-per-launch", type=int, default=16)
+    ap.add_argument("--steps-per-visit", type=int, default=16)
+    ap.add_argument("--refill-below", type=int, default=8)
+    ap.add_argument("--cpu-events", type=int, default=640)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
+    ap.add_argument("--mixed-capacity", type=int, default=1 << 25)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-producers", type=int, default=64)
+    ap.add_argument("--serve-window", type=int, default=64, help="outstanding requests per producer (closed loop)")
+    ap.add_argument("--serve-pool", type=int, default=64, help="distinct requests per producer (reused, new keys)")
+    ap.add_argument("--serve-requests", type=int, default=20480)
+    ap.add_argument("--serve-capacity", type=int, default=1 << 24)
+    ap.add_argument("--serve-admit-gib", type=int, default=8)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); events shard across GPUs with no "
+              "exchange during transport, so the one-GPU figure is the per-GPU throughput", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import ems_inputs as I
+    import paper_2209_15445_amd as E
+
+    fp = transport_leg(E, I, args.workload, E.FP64, args.capacity, args)
+    geo, cfg, prim = fp["geo"], fp["cfg"], fp["prim"]
+    n = len(prim)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": fp["value"],
         "unit": "primaries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": fp["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -232,17 +308,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "events": n, "primary": "e-", "energy_MeV": float(prim["ekin"][0]),
                    "geometry": "50 x (2.3 mm Pb + 5.7 mm lAr), 40x40 cm", "bz_tesla": cfg.bz_tesla,
-                   "precision": "fp64", "track_steps_per_step": sum(steps) // args.steps,
-                   "visits_per_step": sum(visits) // args.steps,
+                   "precision": "fp64", "track_steps_per_step": fp["track_steps"],
+                   "visits_per_step": fp["visits"],
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_visit (photon + e-/e+ launch per iteration)", "bytes_per_launch": per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6,
-                     "launches": launches},
+        "roofline": fp["roofline"],
     }
+    if not args.no_mixed:
+        mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
+        out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
+                        "unit": "primaries/s", "ms_per_step": mx["ms_per_step"], "dtype": "f32 physics / f64 state",
+                        "track_steps_per_step": mx["track_steps"], "roofline": mx["roofline"]}
+        if not args.no_cpu:
+            out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
     if not args.no_serve:
-        out["serving"] = serving(E, I, args)
+        out["serving"] = serving(E, I, args, E.FP64)
+        if not args.no_mixed:
+            out["serving_mixed"] = serving(E, I, args, E.MIXED)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(geo, cfg, prim, min(args.cpu_events, n), threads)

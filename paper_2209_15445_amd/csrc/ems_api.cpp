@@ -43,7 +43,7 @@ uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (!c || !g) return fail(EMS_E_INVALID, "null config or geometry");
   if (c->abi_version != EMS_ABI_VERSION) return fail(EMS_E_VERSION, "abi_version mismatch");
-  if (c->precision != EMS_FP64) return fail(EMS_E_INVALID, "only EMS_FP64 is available");
+  if (c->precision != EMS_FP64 && c->precision != EMS_MIXED) return fail(EMS_E_INVALID, "precision must be EMS_FP64 or EMS_MIXED");
   if (g->n_slabs < 1 || g->n_slabs > 4096 || !g->z_mm || !g->material)
     return fail(EMS_E_INVALID, "geometry needs 1..4096 slabs with planes and materials");
   if (g->n_materials < 1 || g->n_materials > 4 || !g->materials)
@@ -75,6 +75,19 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   return EMS_OK;
 }
 
+// bytes of one table value and of one queued track in the chosen form
+uint64_t real_bytes(const ems_config* c) { return c->precision == EMS_MIXED ? 4 : 8; }
+
+}  // namespace
+
+namespace ems {
+uint64_t queue_track_bytes(const ems_config* c) {
+  return c->precision == EMS_MIXED ? track_bytes<float>() : track_bytes<double>();
+}
+}  // namespace ems
+
+namespace {
+
 Layout plan(const ems_config* c, const ems_geometry* g) {
   Layout L{};
   const uint64_t nodes = c->n_bins + 1;
@@ -86,7 +99,9 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
     return at;
   };
   L.ctl = take(sizeof(Ctl));
-  L.tab = take(g->n_materials * kNumTables * nodes * 8);  // photon block, then lepton block
+  // photon block, then lepton block (8-byte aligned between them)
+  L.tab = take((g->n_materials * kGammaTables * nodes * real_bytes(c) + 7) / 8 * 8 +
+               g->n_materials * kLeptonTables * nodes * real_bytes(c));
   L.zp = take((g->n_slabs + 1) * 8ull);
   L.smat = take(g->n_slabs * 4ull);
   L.mat = take(g->n_materials * sizeof(MatRT));
@@ -97,7 +112,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
   L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
-  L.queues = take(6 * L.cap * kTrackBytes);
+  L.queues = take(6 * L.cap * queue_track_bytes(c));
   L.total = o;
   return L;
 }
@@ -118,8 +133,8 @@ TableSet tables_for(const ems_config* c, const ems_geometry* g) {
   return build_tables(p, mats);
 }
 
-StepEnv env_for(const ems_config* c, const ems_geometry* g, const TableSet& ts) {
-  StepEnv e{};
+StepEnv<double> env_for(const ems_config* c, const ems_geometry* g, const TableSet& ts) {
+  StepEnv<double> e{};
   e.nodes = ts.nodes;
   e.n_slabs = g->n_slabs;
   e.lnemin = ts.lnemin;
@@ -184,6 +199,44 @@ ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary
   return EMS_OK;
 }
 
+// The mixed form compares FP32 interpolated totals against bounds; bounds
+// are raised by 2^-20 (relative) so FP32 rounding of the interpolation (a few
+// 1e-7) never exceeds them.  A larger bound only adds null collisions.
+constexpr double kBoundInflation = 1.0 + 0x1p-20;
+
+void inflate_bounds(MatRT& m) {
+  for (int i = 0; i < 2; ++i) {
+    m.up_em[i] *= kBoundInflation;
+    m.up_ep[i] *= kBoundInflation;
+  }
+}
+
+// table blocks as laid out on the device, values of type R; the photon block
+// is padded to 8 bytes
+template <class R>
+void pack_tables(const TableSet& ts, uint32_t n_mat, std::vector<char>& out) {
+  std::vector<R> g, l;
+  const bool mixed = sizeof(R) == 4;
+  for (uint32_t m = 0; m < n_mat; ++m)
+    for (int t = 0; t < kGammaTables; ++t)
+      for (uint32_t j = 0; j < ts.nodes; ++j) g.push_back((R)ts.at(m, t, j));
+  for (uint32_t m = 0; m < n_mat; ++m)
+    for (int t = kGammaTables; t < kNumTables; ++t)
+      for (uint32_t j = 0; j < ts.nodes; ++j) {
+        const bool bound = t == tPMem || t == tPMep;
+        l.push_back((R)(mixed && bound ? ts.at(m, t, j) * kBoundInflation : ts.at(m, t, j)));
+      }
+  const size_t gb = (g.size() * sizeof(R) + 7) / 8 * 8;
+  out.assign(gb + l.size() * sizeof(R), 0);
+  memcpy(out.data(), g.data(), g.size() * sizeof(R));
+  memcpy(out.data() + gb, l.data(), l.size() * sizeof(R));
+}
+
+template <class R>
+ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const ems_primary* prim, uint64_t n,
+                          uint32_t n_events, const uint32_t* keys, double* edep, ems_ledger* ledger,
+                          ems_step_record* log, uint64_t log_cap, uint64_t* log_n);
+
 }  // namespace
 
 
@@ -247,8 +300,11 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   c->device = dev;
   const uint64_t nodes = cfg->n_bins + 1;
   const uint32_t common = (uint32_t)((geo->n_slabs + 1) * 8 + geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
-  const uint32_t lds_g = (uint32_t)(geo->n_materials * kGammaTables * nodes * 8) + common;
-  const uint32_t lds_l = (uint32_t)(geo->n_materials * kLeptonTables * nodes * 8) + common;
+  const uint64_t rb = real_bytes(cfg);
+  const uint64_t gbytes = (geo->n_materials * kGammaTables * nodes * rb + 7) / 8 * 8;
+  const uint64_t lbytes = (geo->n_materials * kLeptonTables * nodes * rb + 7) / 8 * 8;
+  const uint32_t lds_g = (uint32_t)gbytes + common;
+  const uint32_t lds_l = (uint32_t)lbytes + common;
   if (lds_l > 160u * 1024u) return bad(fail(EMS_E_INVALID, "tables exceed LDS"));
 
   KArgs& a = c->args;
@@ -257,8 +313,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.edep = reinterpret_cast<double*>(c->ws + L.edep);
   a.ledger = reinterpret_cast<LedgerDev*>(c->ws + L.ledger);
   a.keys = reinterpret_cast<const uint32_t*>(c->ws + L.keys);
-  a.tab_g = reinterpret_cast<const double*>(c->ws + L.tab);
-  a.tab_l = a.tab_g + geo->n_materials * kGammaTables * nodes;
+  a.tab_g = c->ws + L.tab;
+  a.tab_l = c->ws + L.tab + gbytes;
   a.zplane = reinterpret_cast<const double*>(c->ws + L.zp);
   a.slab_mat = reinterpret_cast<const uint32_t*>(c->ws + L.smat);
   a.mat = reinterpret_cast<const MatRT*>(c->ws + L.mat);
@@ -275,6 +331,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.lds_l = lds_l;
   a.steps_per_visit = cfg->steps_per_visit;
   a.refill_below = cfg->refill_below;
+  a.precision = cfg->precision == EMS_MIXED ? 1u : 0u;
   a.env = env_for(cfg, geo, c->ts);
   int per_g = 0, per_l = 0;
   if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
@@ -288,27 +345,28 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
       hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return bad(fail(EMS_E_DEVICE, "pinned host allocation or event creation failed"));
-  // device table layout: photon block [mat][3][nodes], then lepton block [mat][10][nodes]
-  std::vector<double> packed;
-  packed.reserve(c->ts.v.size());
-  for (uint32_t m = 0; m < geo->n_materials; ++m)
-    for (int t = 0; t < kGammaTables; ++t)
-      for (uint64_t j = 0; j < nodes; ++j) packed.push_back(c->ts.at(m, t, (uint32_t)j));
-  for (uint32_t m = 0; m < geo->n_materials; ++m)
-    for (int t = kGammaTables; t < kNumTables; ++t)
-      for (uint64_t j = 0; j < nodes; ++j) packed.push_back(c->ts.at(m, t, (uint32_t)j));
+  // device table layout: photon block [mat][3][nodes], then lepton block
+  // [mat][10][nodes], in the arithmetic type of the chosen form
+  std::vector<char> packed;
+  std::vector<MatRT> rt = c->ts.rt;
+  if (cfg->precision == EMS_MIXED) {
+    pack_tables<float>(c->ts, geo->n_materials, packed);
+    for (MatRT& m : rt) inflate_bounds(m);
+  } else {
+    pack_tables<double>(c->ts, geo->n_materials, packed);
+  }
   std::vector<uint32_t> keys(cfg->max_events);
   for (uint32_t i = 0; i < cfg->max_events; ++i) keys[i] = i;
   hipStream_t s = c->stream;
   bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
-            hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
-            hipMemcpyAsync(c->ws + L.mat, c->ts.rt.data(), c->ts.rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
+            hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
             hipMemcpyAsync(c->ws + L.keys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.edep, 0, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
-            hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * kTrackBytes, s) == hipSuccess &&
+            hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
     (void)hipHostFree(c->pin_inj);
@@ -465,29 +523,42 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
   ems_status st = check_inputs(&c2, geo);
   if (st) return st;
   if (!edep || !ledger || (n && !prim)) return fail(EMS_E_INVALID, "null buffers");
+  if (c2.precision == EMS_MIXED)
+    return host_transport<float>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+  return host_transport<double>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Breadth-first host loop over the same step code as the kernels (test hook).
+template <class R>
+ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const ems_primary* prim, uint64_t n,
+                          uint32_t n_events, const uint32_t* keys, double* edep, ems_ledger* ledger,
+                          ems_step_record* log, uint64_t log_cap, uint64_t* log_n) {
   TableSet ts = tables_for(&c2, geo);
-  StepEnv env = env_for(&c2, geo, ts);
-  std::vector<double> tg, tl;
-  for (uint32_t m = 0; m < geo->n_materials; ++m) {
-    for (int t = 0; t < kGammaTables; ++t)
-      for (uint32_t j = 0; j < ts.nodes; ++j) tg.push_back(ts.at(m, t, j));
-    for (int t = kGammaTables; t < kNumTables; ++t)
-      for (uint32_t j = 0; j < ts.nodes; ++j) tl.push_back(ts.at(m, t, j));
-  }
-  env.tg = tg.data();
-  env.tl = tl.data();
+  StepEnv<R> env = retype<R>(env_for(&c2, geo, ts));
+  std::vector<char> packed;
+  pack_tables<R>(ts, geo->n_materials, packed);
+  std::vector<MatRT> rt = ts.rt;
+  if (sizeof(R) == 4)
+    for (MatRT& m : rt) inflate_bounds(m);
+  const size_t gb = (geo->n_materials * kGammaTables * ts.nodes * sizeof(R) + 7) / 8 * 8;
+  env.tg = reinterpret_cast<const R*>(packed.data());
+  env.tl = reinterpret_cast<const R*>(packed.data() + gb);
   env.zplane = geo->z_mm;
   env.slab_mat = geo->material;
-  env.mat = ts.rt.data();
+  env.mat = rt.data();
   std::vector<uint64_t> rows(n_events, 0);
   std::vector<InjRec> recs;
-  st = prepare(*geo, n_events, prim, n, rows, recs);
+  ems_status st = prepare(*geo, n_events, prim, n, rows, recs);
   if (st) return st;
   memset(edep, 0, sizeof(double) * n_events * geo->n_slabs);
   memset(ledger, 0, sizeof(ems_ledger) * n_events);
-  std::vector<Trk> cur[3], nxt[3];
+  std::vector<Trk<R>> cur[3], nxt[3];
   for (const InjRec& r : recs) {
-    Trk t{r.x, r.y, r.z, r.ux, r.uy, r.uz, r.E, r.id, r.ev, keys ? keys[r.ev] : r.ev, 0, r.slab};
+    Trk<R> t{r.x, r.y, r.z, (R)r.ux, (R)r.uy, (R)r.uz, r.E, r.id, r.ev, keys ? keys[r.ev] : r.ev, 0, r.slab};
     cur[r.sp].push_back(t);
   }
   struct HostSink {
@@ -496,7 +567,7 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
     ems_ledger* ledger;
     ems_step_record* log;
     uint64_t log_cap, nlog;
-    void apply(int sp, const Trk& t, const StepOut& o, double e0) {
+    void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e0) {
       ems_ledger& L = ledger[t.ev];
       edep[(size_t)t.ev * geo->n_slabs + o.slab] += o.dep;
       L.escaped[sp] += o.escaped;
@@ -531,9 +602,9 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
   for (;;) {
     if (cur[0].empty() && cur[1].empty() && cur[2].empty()) break;
     for (int sp = 0; sp < 3; ++sp) {
-      for (Trk t : cur[sp]) {
-        VisitState vs;
-        StepOut o;
+      for (Trk<R> t : cur[sp]) {
+        VisitState<R> vs;
+        StepOut<R> o;
         visit_begin<2>(env, sp, t, vs);
         for (;;) {
           const double e0 = t.E;
@@ -543,8 +614,8 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
         }
         if (o.nsec > 0) {
           for (int k = 0; k < o.nsec; ++k) {
-            const Sec& s = o.sec[k];
-            nxt[s.sp].push_back(Trk{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});
+            const Sec<R>& s = o.sec[k];
+            nxt[s.sp].push_back(Trk<R>{t.x, t.y, t.z, s.ux, s.uy, s.uz, s.E, s.id, t.ev, t.key, 0, o.slab});
           }
         }
         if (t.slab >= 0) nxt[sp].push_back(t);
@@ -563,7 +634,7 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
   return EMS_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 namespace ems {
 

@@ -72,6 +72,40 @@ EMS_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// ---------------------------------------------------------------- reals
+// The step arithmetic is written once for a real type R: double for the
+// FP64 form, float for the mixed form (tables, interpolation, step lengths
+// and sampling in FP32; positions, boundary distances and energies stay FP64
+// in the callers).  These overloads pick the single- or double-precision
+// libm routine explicitly.
+EMS_HD float xlog(float v) { return logf(v); }
+EMS_HD double xlog(double v) { return log(v); }
+EMS_HD float xexp(float v) { return expf(v); }
+EMS_HD double xexp(double v) { return exp(v); }
+EMS_HD float xsqrt(float v) { return sqrtf(v); }
+EMS_HD double xsqrt(double v) { return sqrt(v); }
+EMS_HD float xsin(float v) { return sinf(v); }
+EMS_HD double xsin(double v) { return sin(v); }
+EMS_HD float xcos(float v) { return cosf(v); }
+EMS_HD double xcos(double v) { return cos(v); }
+EMS_HD float xfloor(float v) { return floorf(v); }
+EMS_HD double xfloor(double v) { return floor(v); }
+EMS_HD float xceil(float v) { return ceilf(v); }
+EMS_HD double xceil(double v) { return ceil(v); }
+
+// A uniform draw in the arithmetic type: the FP64 value itself, or that
+// value rounded to float and kept inside [2^-25, 1 - 2^-24] so that ln u is
+// finite and u < 1 (the same draws drive both forms).
+template <class R>
+EMS_HD R as_real_u(double u) {
+  return u;
+}
+template <>
+EMS_HD float as_real_u<float>(double u) {
+  const float f = (float)u;
+  return f < 0x1p-25f ? 0x1p-25f : (f > 1.0f - 0x1p-24f ? 1.0f - 0x1p-24f : f);
+}
+
 // 64 bits (hi:lo) -> (0,1): top 52 bits plus one half ulp, exactly representable
 EMS_HD double to_unit(uint32_t lo, uint32_t hi) {
   const uint64_t v = ((uint64_t)hi << 32) | lo;
@@ -105,6 +139,14 @@ struct Draws {
     return (i & 1u) ? to_unit(buf.z, buf.w) : to_unit(buf.x, buf.y);
   }
   EMS_HD double next() { return at(idx++); }
+  template <class R>
+  EMS_HD R u_at(uint32_t i) {
+    return as_real_u<R>(at(i));
+  }
+  template <class R>
+  EMS_HD R u() {
+    return as_real_u<R>(at(idx++));
+  }
   EMS_HD uint64_t child_id(uint32_t k) const {
     const U4 r = philox4x32_10(U4{id_lo, id_hi, step, kChildBit | k}, k0, k1);
     return (uint64_t)r.x | ((uint64_t)r.y << 32);
@@ -112,29 +154,33 @@ struct Draws {
 };
 
 // ---------------------------------------------------------------- vectors
-struct V3 {
-  double x, y, z;
+template <class R>
+struct V3T {
+  R x, y, z;
 };
+using V3 = V3T<double>;
 
-EMS_HD V3 unit(V3 v) {
-  const double n = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
-  return V3{v.x / n, v.y / n, v.z / n};
+template <class R>
+EMS_HD V3T<R> unit(V3T<R> v) {
+  const R n = xsqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+  return V3T<R>{v.x / n, v.y / n, v.z / n};
 }
 
 // Direction with polar angle (cos t, sin t) and azimuth p about the axis u:
 // the frame is (e1, e2, u) with e2 = z^ x u / |z^ x u| and e1 = e2 x u;
 // u = +-z^ uses e1 = (+-1, 0, 0), e2 = (0, 1, 0).
-EMS_HD V3 about_axis(V3 u, double cost, double sint, double phi) {
-  const double a = sint * cos(phi), b = sint * sin(phi);
-  const double t2 = u.x * u.x + u.y * u.y;
-  if (t2 > 0.0) {
-    const double t = sqrt(t2);
-    return V3{(u.x * u.z * a - u.y * b) / t + u.x * cost,
-              (u.y * u.z * a + u.x * b) / t + u.y * cost,
-              -t * a + u.z * cost};
+template <class R>
+EMS_HD V3T<R> about_axis(V3T<R> u, R cost, R sint, R phi) {
+  const R a = sint * xcos(phi), b = sint * xsin(phi);
+  const R t2 = u.x * u.x + u.y * u.y;
+  if (t2 > R(0)) {
+    const R t = xsqrt(t2);
+    return V3T<R>{(u.x * u.z * a - u.y * b) / t + u.x * cost,
+                  (u.y * u.z * a + u.x * b) / t + u.y * cost,
+                  -t * a + u.z * cost};
   }
-  if (u.z > 0.0) return V3{a, b, cost};
-  return V3{-a, b, -cost};
+  if (u.z > R(0)) return V3T<R>{a, b, cost};
+  return V3T<R>{-a, b, -cost};
 }
 
 }  // namespace ems

@@ -5,29 +5,36 @@
 
 namespace ems {
 
-// One species queue buffer, structure of arrays (76 bytes per track):
-// position, direction, energy in FP64; 64-bit id; event row, step, slab.
-// The six buffers (2 x 3 species) are consecutive blocks of cap * 76 bytes.
+// One species queue buffer, structure of arrays: position and energy in
+// FP64, 64-bit id, direction in the arithmetic type R, then event row, step
+// and slab (76 bytes per track in the FP64 form, 64 in the mixed form).  The
+// six buffers (2 x 3 species) are consecutive blocks of cap * track_bytes.
+template <class R>
 struct Queue {
-  double *x, *y, *z, *ux, *uy, *uz, *E;
+  double *x, *y, *z, *E;
   uint64_t* id;
+  R *ux, *uy, *uz;
   uint32_t *ev, *n;
   int32_t* slab;
 };
-constexpr size_t kTrackBytes = 7 * 8 + 8 + 3 * 4;
+template <class R>
+constexpr size_t track_bytes() {
+  return 4 * 8 + 8 + 3 * sizeof(R) + 3 * 4;
+}
 
-EMS_HD Queue queue_view(char* base, uint64_t cap, uint32_t buf, uint32_t sp) {
-  char* b = base + (size_t)(buf * 3u + sp) * cap * kTrackBytes;
-  Queue q;
+template <class R>
+EMS_HD Queue<R> queue_view(char* base, uint64_t cap, uint32_t buf, uint32_t sp) {
+  char* b = base + (size_t)(buf * 3u + sp) * cap * track_bytes<R>();
+  Queue<R> q;
   q.x = reinterpret_cast<double*>(b);
   q.y = q.x + cap;
   q.z = q.y + cap;
-  q.ux = q.z + cap;
+  q.E = q.z + cap;
+  q.id = reinterpret_cast<uint64_t*>(q.E + cap);
+  q.ux = reinterpret_cast<R*>(q.id + cap);
   q.uy = q.ux + cap;
   q.uz = q.uy + cap;
-  q.E = q.uz + cap;
-  q.id = reinterpret_cast<uint64_t*>(q.E + cap);
-  q.ev = reinterpret_cast<uint32_t*>(q.id + cap);
+  q.ev = reinterpret_cast<uint32_t*>(q.uz + cap);
   q.n = q.ev + cap;
   q.slab = reinterpret_cast<int32_t*>(q.n + cap);
   return q;
@@ -94,8 +101,8 @@ struct KArgs {
   double* edep;        // [rows][n_slabs]
   LedgerDev* ledger;   // [rows]
   const uint32_t* keys;
-  const double* tab_g;  // photon table block [mat][3][nodes]
-  const double* tab_l;  // lepton table block [mat][10][nodes]
+  const void* tab_g;   // photon table block [mat][3][nodes] (double or float)
+  const void* tab_l;   // lepton table block [mat][10][nodes]
   const double* zplane;
   const uint32_t* slab_mat;
   const MatRT* mat;
@@ -111,7 +118,8 @@ struct KArgs {
   uint32_t lds_g, lds_l;      // dynamic LDS of the photon / lepton kernels
   uint32_t steps_per_visit;   // steps a thread may take per launch
   uint32_t refill_below;      // batch commit/refill when at most this many lanes still step
-  StepEnv env;         // scalars; its pointers are set per block
+  uint32_t precision;  // 0: FP64 kernels, 1: mixed kernels
+  StepEnv<double> env;  // scalars; its pointers are set per block
 };
 
 }  // namespace ems

@@ -59,7 +59,8 @@ __device__ inline void wave_count(unsigned long long* counter, uint32_t v) {
   if (__lane_id() == 0 && s) atomicAdd(counter, (unsigned long long)s);
 }
 
-__device__ inline void store_track(const Queue& q, uint32_t i, const Trk& t) {
+template <class R>
+__device__ inline void store_track(const Queue<R>& q, uint32_t i, const Trk<R>& t) {
   q.x[i] = t.x;
   q.y[i] = t.y;
   q.z[i] = t.z;
@@ -91,7 +92,8 @@ struct DevSink {
   bool full, logging;
   uint32_t applied;  // steps applied by this lane in the current visit
 
-  __device__ void apply(int sp, const Trk& t, const StepOut& o, double e_before) {
+  template <class R>
+  __device__ void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e_before) {
     ++applied;
     if (o.dep != 0.0) atomicAdd(&edep[(size_t)t.ev * n_slabs + o.slab], o.dep);
     LedgerDev& L = ledger[t.ev];
@@ -131,19 +133,21 @@ struct DevSink {
 
 // Stage a table block, the slab planes, slab materials and material
 // constants in LDS; returns the environment pointing there.
-__device__ StepEnv stage(const KArgs& a, double* lds, bool photons) {
+template <class R>
+__device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
   const uint32_t nt = photons ? kGammaTables : kLeptonTables;
   const uint32_t ntab = a.n_mat * nt * a.env.nodes;
-  const double* src = photons ? a.tab_g : a.tab_l;
+  const R* src = static_cast<const R*>(photons ? a.tab_g : a.tab_l);
+  R* lds = reinterpret_cast<R*>(lds_bytes);
   for (uint32_t i = threadIdx.x; i < ntab; i += kBlock) lds[i] = src[i];
-  double* zp = lds + ntab;
+  double* zp = reinterpret_cast<double*>(lds_bytes + (ntab * sizeof(R) + 7) / 8 * 8);
   for (uint32_t i = threadIdx.x; i <= a.env.n_slabs; i += kBlock) zp[i] = a.zplane[i];
   MatRT* mr = reinterpret_cast<MatRT*>(zp + a.env.n_slabs + 1);
   if (threadIdx.x < a.n_mat) mr[threadIdx.x] = a.mat[threadIdx.x];
   uint32_t* sm = reinterpret_cast<uint32_t*>(mr + a.n_mat);
   for (uint32_t i = threadIdx.x; i < a.env.n_slabs; i += kBlock) sm[i] = a.slab_mat[i];
   __syncthreads();
-  StepEnv env = a.env;
+  StepEnv<R> env = retype<R>(a.env);
   env.tg = photons ? lds : nullptr;
   env.tl = photons ? nullptr : lds;
   env.zplane = zp;
@@ -169,9 +173,10 @@ __device__ StepEnv stage(const KArgs& a, double* lds, bool photons) {
 #ifndef EMS_LEPTON_WAVES
 #define EMS_LEPTON_WAVES 2
 #endif
-template <bool PHOTONS>
+template <bool PHOTONS, class R>
 __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAVES) void k_visit(KArgs a) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_words[];
+  char* lds = reinterpret_cast<char*>(lds_words);
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
   const uint32_t h0 = ctl->n_home[0], h1 = ctl->n_home[1], h2 = ctl->n_home[2];
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
   constexpr int KIND = PHOTONS ? 0 : 1;
 
   if (work) {
-    const StepEnv env = stage(a, lds, PHOTONS);
+    const StepEnv<R> env = stage<R>(a, lds, PHOTONS);
     const uint32_t nxt = cur ^ 1u;
     const int max_visit = (int)a.steps_per_visit;
     // secondary slots per species that leave room for all survivors
@@ -196,9 +201,9 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
     bool fin = false;   // its visit ended; outputs wait for the batch commit
     bool drained = false;
     int sp = PHOTONS ? 0 : 1;
-    Trk t, before;
-    VisitState vs;
-    StepOut o;
+    Trk<R> t, before;
+    VisitState<R> vs;
+    StepOut<R> o;
     o.nsec = 0;
     uint32_t visits_e = 0, visits_p = 0, steps_e = 0, steps_p = 0, carried_n = 0;
     uint32_t made0 = 0, made1 = 0, made2 = 0;
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
           for (int q = 0; q < 3; ++q) {
             if (!d[q]) continue;
             const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
-            const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+            const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
             uint32_t s = slot[q];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
               if (s < lim) {
                 const uint32_t p = (uint32_t)(a.cap - 1 - s);
                 if (commit) {
-                  Trk c;
+                  Trk<R> c;
                   c.x = t.x;
                   c.y = t.y;
                   c.z = t.z;
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
             const bool mine = keep && sp == q;
             const uint32_t hs = wave_reserve(&ctl->next_home[q], mine ? 1u : 0u);
             if (mine) {
-              const Queue dq = queue_view(a.qbase, a.cap, nxt, (uint32_t)q);
+              const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
               if (hs >= a.cap) atomicOr(&ctl->error, kErrOverflow);
               else if (carry) store_track(dq, hs, before);
               else store_track(dq, hs, t);
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
               home = h2;
             }
             const uint32_t pos = queue_pos(idx, home, a.cap);
-            const Queue src = queue_view(a.qbase, a.cap, cur, (uint32_t)sp);
+            const Queue<R> src = queue_view<R>(a.qbase, a.cap, cur, (uint32_t)sp);
             t.slab = src.slab[pos];
             t.ev = t.slab >= 0 ? src.ev[pos] : 0u;
             has = t.slab >= 0;  // slots of refused secondaries hold slab -1
@@ -421,6 +426,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
 
 // Injection: prepared tracks appended to the home regions of the current
 // queues.
+template <class R>
 __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, uint32_t n) {
   Ctl* ctl = a.ctl;
   const uint32_t cur = ctl->cur;
@@ -437,19 +443,19 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
         atomicOr(&ctl->error, kErrOverflow);
         continue;
       }
-      Trk t;
+      Trk<R> t;
       t.x = r.x;
       t.y = r.y;
       t.z = r.z;
-      t.ux = r.ux;
-      t.uy = r.uy;
-      t.uz = r.uz;
+      t.ux = (R)r.ux;
+      t.uy = (R)r.uy;
+      t.uz = (R)r.uz;
       t.E = r.E;
       t.id = r.id;
       t.ev = r.ev;
       t.n = 0;
       t.slab = r.slab;
-      store_track(queue_view(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
+      store_track(queue_view<R>(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
       if (a.flags & kFlagEventLive) atomicAdd(&a.live_ev[r.ev], 1);
     }
   }
@@ -469,15 +475,21 @@ __global__ void k_census(KArgs a) {
   }
 }
 
-hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
-  hipLaunchKernelGGL(k_visit<true>, dim3(blocks_g), dim3(kBlock), a.lds_g, s, a);
-  hipLaunchKernelGGL(k_visit<false>, dim3(blocks_l), dim3(kBlock), a.lds_l, s, a);
+template <class R>
+hipError_t launch_iteration_r(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
+  hipLaunchKernelGGL((k_visit<true, R>), dim3(blocks_g), dim3(kBlock), a.lds_g, s, a);
+  hipLaunchKernelGGL((k_visit<false, R>), dim3(blocks_l), dim3(kBlock), a.lds_l, s, a);
   return hipGetLastError();
+}
+hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
+  return a.precision ? launch_iteration_r<float>(a, blocks_g, blocks_l, s)
+                     : launch_iteration_r<double>(a, blocks_g, blocks_l, s);
 }
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
   const uint32_t want = (n + kBlock - 1) / kBlock;
   const uint32_t blocks = n == 0 ? 1 : (want < 4096 ? want : 4096);
-  hipLaunchKernelGGL(k_inject, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
+  if (a.precision) hipLaunchKernelGGL(k_inject<float>, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
+  else hipLaunchKernelGGL(k_inject<double>, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
   return hipGetLastError();
 }
 hipError_t launch_census(const KArgs& a, hipStream_t s) {
@@ -485,16 +497,21 @@ hipError_t launch_census(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 // blocks of each visit kernel that fit on one CU (registers and LDS)
-hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true>),
+template <class R>
+hipError_t visit_occupancy_r(const KArgs& a, int* per_cu_g, int* per_cu_l) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true, R>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false, R>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true>, kBlock, a.lds_g);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true, R>, kBlock, a.lds_g);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false>, kBlock, a.lds_l);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false, R>, kBlock, a.lds_l);
+}
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
+  return a.precision ? visit_occupancy_r<float>(a, per_cu_g, per_cu_l)
+                     : visit_occupancy_r<double>(a, per_cu_g, per_cu_l);
 }
 
 }  // namespace ems

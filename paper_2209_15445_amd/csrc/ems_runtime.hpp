@@ -22,6 +22,9 @@ struct Layout {
   uint64_t cap;
 };
 
+// bytes of one queued track in the configured form
+uint64_t queue_track_bytes(const ems_config* c);
+
 // sets the calling thread's error text and returns code
 ems_status fail(ems_status code, const std::string& msg);
 

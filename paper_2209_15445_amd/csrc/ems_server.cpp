@@ -220,7 +220,7 @@ ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t 
   for (int sp = 0; sp < 3; ++sp)
     if (r->add[sp] > s->ctx->L.cap) return fail(EMS_E_CAPACITY, "request exceeds the track capacity");
   // estimated peak tracks of the event in both queue buffers
-  r->bytes = 2 * kTrackBytes * (uint64_t)(n + 0.1 * etot + 1.0);
+  r->bytes = 2 * queue_track_bytes(&s->ctx->cfg) * (uint64_t)(n + 0.1 * etot + 1.0);
   r->key = key;
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);

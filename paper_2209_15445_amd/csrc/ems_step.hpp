@@ -7,6 +7,12 @@
 // secondaries, which the caller appends to the next arrays.  The function is
 // pure: every random number comes from the (seed, event key, id, step) Philox
 // stream, so results do not depend on which thread or iteration runs it.
+//
+// The step is written for a real type R.  R = double is the FP64 form.
+// R = float is the mixed form: tables, interpolation, step lengths, loss
+// and sampling in FP32, while positions, boundary and safety distances, the
+// helix and every energy (track, deposit, secondaries) stay FP64, so energy
+// bookkeeping is exact in both forms.
 #pragma once
 #include "ems_models.hpp"
 #include "ems_tables.hpp"
@@ -20,41 +26,77 @@ constexpr double kInf = __builtin_huge_val();
 // [mat][10][nodes] (tables 3..12).
 constexpr int kGammaTables = 3, kLeptonTables = kNumTables - kGammaTables;
 
+template <class R>
 struct StepEnv {
-  const double* tg;          // photon table block
-  const double* tl;          // lepton table block
+  const R* tg;               // photon table block
+  const R* tl;               // lepton table block
   const double* zplane;      // n_slabs + 1
   const uint32_t* slab_mat;  // n_slabs
   const MatRT* mat;
   uint32_t nodes, n_slabs;
-  double lnemin, dlog, inv_dlog;
+  R lnemin, dlog, inv_dlog;
   double half_xy, bz;
   double ecut, tcut, kcut;
   double alpha, rho, lin;
   uint32_t mask, seed, max_steps;
 
-  EMS_HD const double* T(uint32_t m, int t) const {
+  EMS_HD const R* T(uint32_t m, int t) const {
     return t < kGammaTables ? tg + ((size_t)m * kGammaTables + t) * nodes
                             : tl + ((size_t)m * kLeptonTables + (t - kGammaTables)) * nodes;
   }
 };
 
+// the scalars of an environment in another arithmetic type (table pointers
+// are left null)
+template <class R, class S>
+EMS_HD StepEnv<R> retype(const StepEnv<S>& a) {
+  StepEnv<R> e;
+  e.tg = nullptr;
+  e.tl = nullptr;
+  e.zplane = a.zplane;
+  e.slab_mat = a.slab_mat;
+  e.mat = a.mat;
+  e.nodes = a.nodes;
+  e.n_slabs = a.n_slabs;
+  e.lnemin = (R)a.lnemin;
+  e.dlog = (R)a.dlog;
+  e.inv_dlog = (R)a.inv_dlog;
+  e.half_xy = a.half_xy;
+  e.bz = a.bz;
+  e.ecut = a.ecut;
+  e.tcut = a.tcut;
+  e.kcut = a.kcut;
+  e.alpha = a.alpha;
+  e.rho = a.rho;
+  e.lin = a.lin;
+  e.mask = a.mask;
+  e.seed = a.seed;
+  e.max_steps = a.max_steps;
+  return e;
+}
+
+template <class R>
 struct Trk {
-  double x, y, z, ux, uy, uz, E;
+  double x, y, z;
+  R ux, uy, uz;
+  double E;
   uint64_t id;
   uint32_t ev, key, n;
   int32_t slab;  // < 0: track has ended
 };
 
+template <class R>
 struct Sec {
   int sp;
-  double E, ux, uy, uz;
+  double E;
+  R ux, uy, uz;
   uint64_t id;
 };
 
+template <class R>
 struct StepOut {
   int nsec;
-  Sec sec[2];
+  Sec<R> sec[2];
   int slab;        // slab the step was taken in (deposits, secondaries)
   double dep;      // energy deposited in that slab
   double escaped;  // kinetic energy of the track leaving the stack
@@ -65,45 +107,55 @@ struct StepOut {
   double step_len;
 };
 
+template <class R>
 struct Bin {
   int j;
-  double u;
+  R u;
 };
 
-EMS_HD Bin bin_of(const StepEnv& e, double lnE) {
-  const double x = (lnE - e.lnemin) * e.inv_dlog;
-  double f = floor(x);
-  const double top = (double)(e.nodes - 2);
-  f = f < 0.0 ? 0.0 : (f > top ? top : f);
+template <class R>
+EMS_HD Bin<R> bin_of(const StepEnv<R>& e, R lnE) {
+  const R x = (lnE - e.lnemin) * e.inv_dlog;
+  R f = xfloor(x);
+  const R top = (R)(e.nodes - 2);
+  f = f < R(0) ? R(0) : (f > top ? top : f);
   int j = (int)f;  // clamped again as an integer: a NaN never indexes outside
   j = j < 0 ? 0 : (j > (int)e.nodes - 2 ? (int)e.nodes - 2 : j);
-  double u = x - (double)j;
-  u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-  return Bin{j, u};
+  R u = x - (R)j;
+  u = u < R(0) ? R(0) : (u > R(1) ? R(1) : u);
+  return Bin<R>{j, u};
 }
-EMS_HD double lerp(const double* f, Bin b) { return f[b.j] + b.u * (f[b.j + 1] - f[b.j]); }
+template <class R>
+EMS_HD R lerp(const R* f, Bin<R> b) {
+  return f[b.j] + b.u * (f[b.j + 1] - f[b.j]);
+}
 
 // largest node j <= jhi with R_j <= r (0 if none; clamped to the last bin),
 // then the exact inverse of the range interpolant.  The loss over one step
 // spans few bins, so the scan starts at the track's own bin and walks down.
-EMS_HD double inverse_range(const StepEnv& e, const double* R, double r, int jhi) {
+template <class R>
+EMS_HD R inverse_range(const StepEnv<R>& e, const R* Rt, R r, int jhi) {
   int lo = jhi > (int)e.nodes - 1 ? (int)e.nodes - 1 : jhi;
-  while (lo > 0 && R[lo] > r) --lo;
+  while (lo > 0 && Rt[lo] > r) --lo;
   if (lo > (int)e.nodes - 2) lo = (int)e.nodes - 2;
-  return exp(e.lnemin + lo * e.dlog + e.dlog * (r - R[lo]) / (R[lo + 1] - R[lo]));
+  return xexp(e.lnemin + (R)lo * e.dlog + e.dlog * (r - Rt[lo]) / (Rt[lo + 1] - Rt[lo]));
 }
 
-// energy lost over path s by a charged track of kinetic energy T
-EMS_HD double cont_loss(const StepEnv& e, const double* R, int jT, double T, double S, double Rt, double s) {
+// energy lost over path s by a charged track of kinetic energy T (stopping
+// power S and range Rv at T); FP64 result
+template <class R>
+EMS_HD double cont_loss(const StepEnv<R>& e, const R* Rt, int jT, double T, R S, R Rv, double s) {
   double L;
-  if (s >= Rt) L = T;
-  else if (s < e.lin * Rt) L = s * S;
-  else L = T - inverse_range(e, R, Rt - s, jT + 1);
+  if (s >= (double)Rv) L = T;
+  else if (s < (double)(R(e.lin) * Rv)) L = (double)((R)s * S);
+  else L = T - (double)inverse_range(e, Rt, Rv - (R)s, jT + 1);
+  L = L < 0.0 ? 0.0 : L;
   return (T - L < e.ecut) ? T : L;
 }
 
-EMS_HD void land_on_plane(const StepEnv& e, Trk& t, StepOut& o) {
-  if (t.uz > 0.0) {
+template <class R>
+EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
+  if (t.uz > R(0)) {
     t.z = e.zplane[t.slab + 1];
     t.slab += 1;
   } else {
@@ -117,21 +169,25 @@ EMS_HD void land_on_plane(const StepEnv& e, Trk& t, StepOut& o) {
   }
 }
 
-EMS_HD double dist_to_planes(const StepEnv& e, const Trk& t) {
-  if (t.uz > 0.0) return (e.zplane[t.slab + 1] - t.z) / t.uz;
-  if (t.uz < 0.0) return (e.zplane[t.slab] - t.z) / t.uz;
+template <class R>
+EMS_HD double dist_to_planes(const StepEnv<R>& e, const Trk<R>& t) {
+  const double uz = t.uz;
+  if (uz > 0.0) return (e.zplane[t.slab + 1] - t.z) / uz;
+  if (uz < 0.0) return (e.zplane[t.slab] - t.z) / uz;
   return kInf;
 }
-EMS_HD double dist_to_walls(const StepEnv& e, const Trk& t) {
-  const double h = e.half_xy;
-  const double sx = t.ux > 0.0 ? (h - t.x) / t.ux : (t.ux < 0.0 ? (-h - t.x) / t.ux : kInf);
-  const double sy = t.uy > 0.0 ? (h - t.y) / t.uy : (t.uy < 0.0 ? (-h - t.y) / t.uy : kInf);
+template <class R>
+EMS_HD double dist_to_walls(const StepEnv<R>& e, const Trk<R>& t) {
+  const double h = e.half_xy, ux = t.ux, uy = t.uy;
+  const double sx = ux > 0.0 ? (h - t.x) / ux : (ux < 0.0 ? (-h - t.x) / ux : kInf);
+  const double sy = uy > 0.0 ? (h - t.y) / uy : (uy < 0.0 ? (-h - t.y) / uy : kInf);
   return sx < sy ? sx : sy;
 }
 
 // hand the interaction outcome to the caller: secondaries below the tracking
 // cut (gamma, e-) are deposited where they are born, the rest are pushed
-EMS_HD void put_sec(Sec& s, const Outcome& oc, int k, Draws& r) {
+template <class R>
+EMS_HD void put_sec(Sec<R>& s, const Outcome<R>& oc, int k, Draws& r) {
   s.sp = oc.sp[k];
   s.E = oc.e[k];
   s.ux = oc.u[k].x;
@@ -139,7 +195,8 @@ EMS_HD void put_sec(Sec& s, const Outcome& oc, int k, Draws& r) {
   s.uz = oc.u[k].z;
   s.id = r.child_id((uint32_t)k);
 }
-EMS_HD void settle(const StepEnv& e, Trk& t, const Outcome& oc, Draws& r, StepOut& o) {
+template <class R>
+EMS_HD void settle(const StepEnv<R>& e, Trk<R>& t, const Outcome<R>& oc, Draws& r, StepOut<R>& o) {
   // (constant indices only: keeps the small arrays in registers)
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -163,50 +220,14 @@ EMS_HD void settle(const StepEnv& e, Trk& t, const Outcome& oc, Draws& r, StepOu
   }
 }
 
-EMS_HD void gamma_step(const StepEnv& e, Trk& t, StepOut& o) {
-  if (t.E < e.ecut) {
-    o.dep += t.E;
-    t.E = 0.0;
-    t.slab = -1;
-    o.limiter = kLimSubcut;
-    return;
-  }
-  const uint32_t m = e.slab_mat[t.slab];
+// the discrete interaction of a photon at the end of a physics-limited step
+template <class R>
+EMS_HD void gamma_interact(const StepEnv<R>& e, uint32_t m, R sc, R sp, R sig, Trk<R>& t, Draws& r,
+                           StepOut<R>& o) {
   const double E = t.E;
-  const Bin b = bin_of(e, log(E));
-  const double sc = lerp(e.T(m, tCompt), b);
-  const double sp = lerp(e.T(m, tPhot), b);
-  const double sv = E > 2.0 * kMe ? lerp(e.T(m, tConv), b) : 0.0;
-  const double sig = sc + sp + sv;
-  const double sz = dist_to_planes(e, t), sw = dist_to_walls(e, t);
-  const double sg = sz <= sw ? sz : sw;
-  Draws r;
-  r.init(e.seed, t.key, t.id, t.n);
-  const double sphys = sig > 0.0 ? -log(r.at(0)) / sig : kInf;
-  if (sg <= sphys) {
-    t.x += sg * t.ux;
-    t.y += sg * t.uy;
-    t.z += sg * t.uz;
-    o.step_len = sg;
-    if (sz <= sw) {
-      o.limiter = kLimZ;
-      land_on_plane(e, t, o);
-    } else {
-      o.limiter = kLimWall;
-      o.escaped += t.E;
-      t.E = 0.0;
-      t.slab = -1;
-    }
-    return;
-  }
-  t.x += sphys * t.ux;
-  t.y += sphys * t.uy;
-  t.z += sphys * t.uz;
-  o.step_len = sphys;
-  o.limiter = kLimDiscrete;
-  const double pick = r.at(1) * sig;
-  const V3 u{t.ux, t.uy, t.uz};
-  Outcome oc;
+  const R pick = r.u_at<R>(1) * sig;
+  const V3T<R> u{t.ux, t.uy, t.uz};
+  Outcome<R> oc;
   if (pick < sc) {
     o.process = kXCompton;
     compton(E, u, r, oc);
@@ -221,6 +242,51 @@ EMS_HD void gamma_step(const StepEnv& e, Trk& t, StepOut& o) {
   settle(e, t, oc, r, o);
 }
 
+template <class R>
+EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
+  if (t.E < e.ecut) {
+    o.dep += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+    o.limiter = kLimSubcut;
+    return;
+  }
+  const uint32_t m = e.slab_mat[t.slab];
+  const double E = t.E;
+  const Bin<R> b = bin_of(e, xlog((R)E));
+  const R sc = lerp(e.T(m, tCompt), b);
+  const R sp = lerp(e.T(m, tPhot), b);
+  const R sv = E > 2.0 * kMe ? lerp(e.T(m, tConv), b) : R(0);
+  const R sig = sc + sp + sv;
+  const double sz = dist_to_planes(e, t), sw = dist_to_walls(e, t);
+  const double sg = sz <= sw ? sz : sw;
+  Draws r;
+  r.init(e.seed, t.key, t.id, t.n);
+  const double sphys = sig > R(0) ? (double)(-xlog(r.u_at<R>(0)) / sig) : kInf;
+  if (sg <= sphys) {
+    t.x += sg * (double)t.ux;
+    t.y += sg * (double)t.uy;
+    t.z += sg * (double)t.uz;
+    o.step_len = sg;
+    if (sz <= sw) {
+      o.limiter = kLimZ;
+      land_on_plane(e, t, o);
+    } else {
+      o.limiter = kLimWall;
+      o.escaped += t.E;
+      t.E = 0.0;
+      t.slab = -1;
+    }
+    return;
+  }
+  t.x += sphys * (double)t.ux;
+  t.y += sphys * (double)t.uy;
+  t.z += sphys * (double)t.uz;
+  o.step_len = sphys;
+  o.limiter = kLimDiscrete;
+  gamma_interact(e, m, sc, sp, sig, t, r, o);
+}
+
 // discrete e-/e+ processes: table id and threshold (cross section is zero at
 // and below it), in selection order
 struct LeptonProcs {
@@ -229,7 +295,8 @@ struct LeptonProcs {
   double th[3];
   uint32_t code[3];
 };
-EMS_HD LeptonProcs lepton_procs(const StepEnv& e, bool positron) {
+template <class R>
+EMS_HD LeptonProcs lepton_procs(const StepEnv<R>& e, bool positron) {
   LeptonProcs p;
   if (positron) {
     p.n = 3;
@@ -246,8 +313,9 @@ EMS_HD LeptonProcs lepton_procs(const StepEnv& e, bool positron) {
 }
 
 // right-continuous discrete total (process counted at its threshold)
-EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, double E, Bin b) {
-  double s = 0.0;
+template <class R>
+EMS_HD R total_upper(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, double E, Bin<R> b) {
+  R s = R(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     if (i < p.n && E >= p.th[i]) s += lerp(e.T(m, p.tab[i]), b);
@@ -257,27 +325,28 @@ EMS_HD double total_upper(const StepEnv& e, uint32_t m, const LeptonProcs& p, do
 // maximum of the discrete total over [a, b]: endpoints, grid nodes and
 // thresholds inside; when a is the tracking cut the nodes below b come from
 // the running-maximum table; the values at the thresholds are precomputed
-EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p, bool positron, double a,
-                             double b, Bin bb, double lnb, bool from_cut) {
-  double best = total_upper(e, m, p, b, bb);
-  const double xb = (lnb - e.lnemin) * e.inv_dlog;
-  int jb = (int)ceil(xb) - 1;
+template <class R>
+EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, bool positron, double a, double b,
+                        Bin<R> bb, R lnb, bool from_cut) {
+  R best = total_upper(e, m, p, b, bb);
+  const R xb = (lnb - e.lnemin) * e.inv_dlog;
+  int jb = (int)xceil(xb) - 1;
   jb = jb > (int)e.nodes - 1 ? (int)e.nodes - 1 : jb;
   if (from_cut && jb >= 0) {
     // a is the tracking cut = node 0: the running maximum covers a and the
     // nodes below b
-    const double v = e.T(m, positron ? tPMep : tPMem)[jb];
+    const R v = e.T(m, positron ? tPMep : tPMem)[jb];
     best = v > best ? v : best;
   } else {
-    const double lna = log(a);
-    const double va = total_upper(e, m, p, a, bin_of(e, lna));
+    const R lna = xlog((R)a);
+    const R va = total_upper(e, m, p, a, bin_of(e, lna));
     best = va > best ? va : best;
     if (jb >= 0) {
-      const double xa = (lna - e.lnemin) * e.inv_dlog;
-      int j = (int)floor(xa) + 1;
+      const R xa = (lna - e.lnemin) * e.inv_dlog;
+      int j = (int)xfloor(xa) + 1;
       j = j < 0 ? 0 : j;
       for (; j <= jb; ++j) {
-        double s = 0.0;
+        R s = R(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
           if (i < p.n) s += e.T(m, p.tab[i])[j];
@@ -289,17 +358,18 @@ EMS_HD double thinning_bound(const StepEnv& e, uint32_t m, const LeptonProcs& p,
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     if (p.th[i] > a && p.th[i] < b) {
-      const double v = positron ? mr.up_ep[i] : mr.up_em[i];
+      const R v = (R)(positron ? mr.up_ep[i] : mr.up_em[i]);
       best = v > best ? v : best;
     }
   }
   return best;
 }
 
-EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
+template <class R>
+EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
-  Outcome oc;
+  Outcome<R> oc;
   const double T = t.E;
   if (T < e.ecut) {
     o.dep += T;
@@ -337,44 +407,46 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
   }
   const uint32_t m = e.slab_mat[t.slab];
   const bool cont = (e.mask & kPCont) != 0;
-  const double lnT = log(T);
-  const Bin b = bin_of(e, lnT);
-  const double* Rt = e.T(m, positron ? tRep : tRem);
-  double S = 0.0, R = kInf, scont = kInf;
+  const R lnT = xlog((R)T);
+  const Bin<R> b = bin_of(e, lnT);
+  const R* Rt = e.T(m, positron ? tRep : tRem);
+  R S = R(0), Rv = (R)kInf, scont = (R)kInf;
   if (cont) {
     S = lerp(e.T(m, positron ? tSep : tSem), b);
-    R = lerp(Rt, b);
-    scont = R <= e.rho ? R : e.alpha * R + e.rho * (1.0 - e.alpha) * (2.0 - e.rho / R);
+    Rv = lerp(Rt, b);
+    const R al = (R)e.alpha, rh = (R)e.rho;
+    scont = Rv <= rh ? Rv : al * Rv + rh * (R(1) - al) * (R(2) - rh / Rv);
   }
-  const double smax = scont <= sg ? scont : sg;
+  const double smax = (double)scont <= sg ? (double)scont : sg;
   double elo = T, loss_max = 0.0;
   if (cont) {
-    loss_max = cont_loss(e, Rt, b.j, T, S, R, smax);
+    loss_max = cont_loss(e, Rt, b.j, T, S, Rv, smax);
     elo = T - loss_max;
-    const double lin = e.lin * R;
-    if (smax >= lin) {
-      const double e2 = T - lin * S;
+    const R lin = (R)e.lin * Rv;
+    if (smax >= (double)lin) {
+      const double e2 = T - (double)(lin * S);
       elo = e2 < elo ? e2 : elo;
     }
   }
   const bool from_cut = !(elo > e.ecut);
   const double a = from_cut ? e.ecut : elo;
   const LeptonProcs pl = lepton_procs(e, positron);
-  const double bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
-  const double sphys = bound > 0.0 ? -log(r.at(0)) / bound : kInf;
+  const R bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
+  const double sphys = bound > R(0) ? (double)(-xlog(r.u_at<R>(0)) / bound) : kInf;
   double s;
   uint32_t lim;
   if (sphys < smax) {
     s = sphys;
     lim = kLimDiscrete;
-  } else if (sg <= scont) {
+  } else if (sg <= (double)scont) {
     s = sg;
     lim = zlim ? kLimZ : (field ? kLimSafety : kLimWall);
   } else {
-    s = scont;
+    s = (double)scont;
     lim = kLimCont;
   }
   if (field) {
+    // exact helix about z (FP64 in both forms)
     const double p = sqrt(T * (T + 2.0 * kMe));
     const double kap = (positron ? kKB : -kKB) * e.bz / p;
     const double ph = kap * s;
@@ -383,18 +455,18 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
     const double ux = t.ux, uy = t.uy;
     t.x += (ux * sp + uy * omc) / kap;
     t.y += (uy * sp - ux * omc) / kap;
-    t.z += t.uz * s;
-    t.ux = ux * cp + uy * sp;
-    t.uy = -ux * sp + uy * cp;
+    t.z += (double)t.uz * s;
+    t.ux = (R)(ux * cp + uy * sp);
+    t.uy = (R)(-ux * sp + uy * cp);
   } else {
-    t.x += s * t.ux;
-    t.y += s * t.uy;
-    t.z += s * t.uz;
+    t.x += s * (double)t.ux;
+    t.y += s * (double)t.uy;
+    t.z += s * (double)t.uz;
   }
   o.step_len = s;
   o.clen += s;
   // the step ends at s_max unless a discrete interaction came first
-  const double dE = !cont ? 0.0 : (lim == kLimDiscrete ? cont_loss(e, Rt, b.j, T, S, R, s) : loss_max);
+  const double dE = !cont ? 0.0 : (lim == kLimDiscrete ? cont_loss(e, Rt, b.j, T, S, Rv, s) : loss_max);
   o.dep += dE;
   const double Tp = T - dE;
   t.E = Tp;
@@ -421,9 +493,9 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
     return;
   }
   if (lim != kLimDiscrete) return;
-  const double pick = r.at(1) * bound;
-  const Bin bp = bin_of(e, log(Tp));
-  double cum = 0.0;
+  const R pick = r.u_at<R>(1) * bound;
+  const Bin<R> bp = bin_of(e, xlog((R)Tp));
+  R cum = R(0);
   uint32_t code = kXNull;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -437,7 +509,7 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
     return;
   }
   o.process = code;
-  const V3 u{t.ux, t.uy, t.uz};
+  const V3T<R> u{t.ux, t.uy, t.uz};
   switch (code) {
     case kXMoller: moller(Tp, e.tcut, u, r, oc); break;
     case kXBhabha: bhabha(Tp, e.tcut, u, r, oc); break;
@@ -450,18 +522,18 @@ EMS_HD void lepton_step(const StepEnv& e, bool positron, Trk& t, StepOut& o) {
   settle(e, t, oc, r, o);
 }
 
-// One full step of a track of species sp: dispatch, step counter, watchdog.
-// KIND: 0 = photons only, 1 = e-/e+ only, 2 = any species (host use).
-template <int KIND>
-EMS_HD void take_step_k(const StepEnv& e, int sp, Trk& t, StepOut& o) {
+template <class R>
+EMS_HD void clear_out(const Trk<R>& t, StepOut<R>& o) {
   o.nsec = 0;
   o.slab = t.slab;
   o.dep = o.escaped = o.killed = o.clen = o.step_len = 0.0;
   o.pair = o.annih = o.null = 0;
   o.limiter = 0;
   o.process = kXNone;
-  if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step(e, t, o);
-  else lepton_step(e, sp == kPositron, t, o);
+}
+
+template <class R>
+EMS_HD void watchdog(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   t.n += 1;
   if (t.slab >= 0 && t.n >= e.max_steps) {
     o.killed += t.E;
@@ -469,45 +541,47 @@ EMS_HD void take_step_k(const StepEnv& e, int sp, Trk& t, StepOut& o) {
     t.slab = -1;
   }
 }
-EMS_HD void take_step(const StepEnv& e, int sp, Trk& t, StepOut& o) { take_step_k<2>(e, sp, t, o); }
 
-// A visit: consecutive steps of one track by one thread, until a step
-// produces secondaries, the track ends, or max_steps steps were taken.  The
-// sequence of steps is exactly the one-step-at-a-time sequence (every step
-// draws from its own (id, step) stream); only the queue round trips between
-// them are saved.  Steps without secondaries are handed to sink.apply() as
-// they happen.  If the last step produced secondaries it is NOT applied: `o`
-// holds it, `before` holds the track as it was before that step, and the
-// caller either commits it (sink.apply + push) or carries `before`.
-// Returns the number of steps taken.
+// One full step of a track of species sp: dispatch, step counter, watchdog.
+// KIND: 0 = photons only, 1 = e-/e+ only, 2 = any species (host use).
+template <int KIND, class R>
+EMS_HD void take_step_k(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
+  clear_out(t, o);
+  if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step(e, t, o);
+  else lepton_step(e, sp == kPositron, t, o);
+  watchdog(e, t, o);
+}
+template <class R>
+EMS_HD void take_step(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
+  take_step_k<2>(e, sp, t, o);
+}
+
 // Photon visit state: between interactions a photon keeps its energy and
 // direction, so ln E, its table bin and the inverse direction are computed
 // once per visit; each crossing then costs one Philox block, one log and the
 // geometry.
+template <class R>
 struct PhotonCache {
-  Bin b;
+  Bin<R> b;
   bool conv;
   double iux, iuy, iuz;
 };
 
-EMS_HD void photon_begin(const StepEnv& e, const Trk& t, PhotonCache& pc) {
-  pc.b = bin_of(e, log(t.E > e.ecut ? t.E : e.ecut));
+template <class R>
+EMS_HD void photon_begin(const StepEnv<R>& e, const Trk<R>& t, PhotonCache<R>& pc) {
+  pc.b = bin_of(e, xlog((R)(t.E > e.ecut ? t.E : e.ecut)));
   pc.conv = t.E > 2.0 * kMe;
-  pc.iux = 1.0 / t.ux;
-  pc.iuy = 1.0 / t.uy;
-  pc.iuz = 1.0 / t.uz;
+  pc.iux = 1.0 / (double)t.ux;
+  pc.iuy = 1.0 / (double)t.uy;
+  pc.iuz = 1.0 / (double)t.uz;
 }
 
 // One photon step with the visit cache: exactly gamma_step followed by the
 // step count and watchdog of take_step.  Returns true when the visit must
 // end after it (the photon interacted or is gone).
-EMS_HD bool photon_substep(const StepEnv& e, const PhotonCache& pc, Trk& t, StepOut& o) {
-  o.nsec = 0;
-  o.slab = t.slab;
-  o.dep = o.escaped = o.killed = o.clen = o.step_len = 0.0;
-  o.pair = o.annih = o.null = 0;
-  o.limiter = 0;
-  o.process = kXNone;
+template <class R>
+EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>& t, StepOut<R>& o) {
+  clear_out(t, o);
   const double E = t.E;
   if (E < e.ecut) {
     o.dep += E;
@@ -516,24 +590,25 @@ EMS_HD bool photon_substep(const StepEnv& e, const PhotonCache& pc, Trk& t, Step
     o.limiter = kLimSubcut;
   } else {
     const uint32_t m = e.slab_mat[t.slab];
-    const double sc = lerp(e.T(m, tCompt), pc.b);
-    const double sp = lerp(e.T(m, tPhot), pc.b);
-    const double sv = pc.conv ? lerp(e.T(m, tConv), pc.b) : 0.0;
-    const double sig = sc + sp + sv;
+    const R sc = lerp(e.T(m, tCompt), pc.b);
+    const R sp = lerp(e.T(m, tPhot), pc.b);
+    const R sv = pc.conv ? lerp(e.T(m, tConv), pc.b) : R(0);
+    const R sig = sc + sp + sv;
     const double h = e.half_xy;
-    const double sz = t.uz > 0.0 ? (e.zplane[t.slab + 1] - t.z) * pc.iuz
-                                 : (t.uz < 0.0 ? (e.zplane[t.slab] - t.z) * pc.iuz : kInf);
-    const double sx = t.ux > 0.0 ? (h - t.x) * pc.iux : (t.ux < 0.0 ? (-h - t.x) * pc.iux : kInf);
-    const double sy = t.uy > 0.0 ? (h - t.y) * pc.iuy : (t.uy < 0.0 ? (-h - t.y) * pc.iuy : kInf);
+    const double ux = t.ux, uy = t.uy, uz = t.uz;
+    const double sz = uz > 0.0 ? (e.zplane[t.slab + 1] - t.z) * pc.iuz
+                               : (uz < 0.0 ? (e.zplane[t.slab] - t.z) * pc.iuz : kInf);
+    const double sx = ux > 0.0 ? (h - t.x) * pc.iux : (ux < 0.0 ? (-h - t.x) * pc.iux : kInf);
+    const double sy = uy > 0.0 ? (h - t.y) * pc.iuy : (uy < 0.0 ? (-h - t.y) * pc.iuy : kInf);
     const double sw = sx < sy ? sx : sy;
     const double sg = sz <= sw ? sz : sw;
     Draws r;
     r.init(e.seed, t.key, t.id, t.n);
-    const double sphys = sig > 0.0 ? -log(r.at(0)) / sig : kInf;
+    const double sphys = sig > R(0) ? (double)(-xlog(r.u_at<R>(0)) / sig) : kInf;
     if (sg <= sphys) {
-      t.x += sg * t.ux;
-      t.y += sg * t.uy;
-      t.z += sg * t.uz;
+      t.x += sg * ux;
+      t.y += sg * uy;
+      t.z += sg * uz;
       o.step_len = sg;
       if (sz <= sw) {
         o.limiter = kLimZ;
@@ -545,47 +620,29 @@ EMS_HD bool photon_substep(const StepEnv& e, const PhotonCache& pc, Trk& t, Step
         t.slab = -1;
       }
     } else {
-      t.x += sphys * t.ux;
-      t.y += sphys * t.uy;
-      t.z += sphys * t.uz;
+      t.x += sphys * ux;
+      t.y += sphys * uy;
+      t.z += sphys * uz;
       o.step_len = sphys;
       o.limiter = kLimDiscrete;
-      const double pick = r.at(1) * sig;
-      const V3 u{t.ux, t.uy, t.uz};
-      Outcome oc;
-      if (pick < sc) {
-        o.process = kXCompton;
-        compton(E, u, r, oc);
-      } else if (pick < sc + sp) {
-        o.process = kXPhot;
-        photo(E, u, oc);
-      } else {
-        o.process = kXConv;
-        pair(e.mat[m], E, u, r, oc);
-        o.pair += 1;
-      }
-      settle(e, t, oc, r, o);
+      gamma_interact(e, m, sc, sp, sig, t, r, o);
     }
   }
-  t.n += 1;
-  if (t.slab >= 0 && t.n >= e.max_steps) {
-    o.killed += t.E;
-    t.E = 0.0;
-    t.slab = -1;
-  }
+  watchdog(e, t, o);
   // any interaction changes E and u (even one whose electron was deposited
   // on the spot), so the visit ends there
   return t.slab < 0 || o.limiter == kLimDiscrete;
 }
 
 // Per-lane state of a visit.  KIND: 0 = photons, 1 = e-/e+, 2 = any (host).
+template <class R>
 struct VisitState {
-  PhotonCache pc;
+  PhotonCache<R> pc;
   int steps;  // steps taken in this visit
 };
 
-template <int KIND>
-EMS_HD void visit_begin(const StepEnv& e, int sp, const Trk& t, VisitState& vs) {
+template <int KIND, class R>
+EMS_HD void visit_begin(const StepEnv<R>& e, int sp, const Trk<R>& t, VisitState<R>& vs) {
   vs.steps = 0;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) photon_begin(e, t, vs.pc);
 }
@@ -595,8 +652,8 @@ EMS_HD void visit_begin(const StepEnv& e, int sp, const Trk& t, VisitState& vs) 
 // step that creates secondaries, when the track ends, or after max_steps
 // steps.  Every step draws from its own (id, step) stream, so a run of
 // visits is step for step the one-step-at-a-time loop.
-template <int KIND>
-EMS_HD bool visit_step(const StepEnv& e, int sp, VisitState& vs, Trk& t, StepOut& o, int max_steps) {
+template <int KIND, class R>
+EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps) {
   bool end;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
     end = photon_substep(e, vs.pc, t, o);

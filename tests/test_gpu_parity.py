@@ -27,10 +27,10 @@ def E():
 
 
 def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
-            blocks=0, visit=16, refill=8):
+            blocks=0, visit=16, refill=8, precision=0):
     c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
                       profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit,
-                      refill_below=refill)
+                      refill_below=refill, precision=precision)
     t = E.Transport(c, geo)
     if keys is not None:
         t.set_event_keys(keys)
@@ -213,3 +213,51 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     mg, mo = gl.mean(axis=0), ol.mean(axis=0)
     sig = np.sqrt(gl.var(axis=0) / n + ol.var(axis=0) / len(sample))
     assert np.all(np.abs(mg - mo) <= 3 * sig + 0.005 * np.abs(mo) + 1e-9)
+
+
+@pytest.mark.parametrize("case", ["1GeV_e-", "mixed_species_bz3.8"])
+def test_mixed_precision_against_fp64_oracle(E, oracle_mod, case):
+    """Mixed form on the GPU: conservation 1e-5, secondary counts per-mil,
+    per-layer means within 3 sigma + 0.5% of the FP64 oracle on the same
+    events; also within per-mil of the host run of the same mixed step code."""
+    from parity_util import mixed_precision_check
+    print(f"mixed precision {case}", flush=True)
+    if case == "1GeV_e-":
+        geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    else:
+        geo = I.calorimeter()
+        cfg = I.RunConfig(seed=3, bz_tesla=3.8)
+        prim = I.mixed_species(24, 1e3, 5e3, seed=3)
+    n = len(prim)
+    g = run_gpu(E, geo, cfg, prim, n, flags=E.F_FULL_LEDGER, precision=E.MIXED)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=n)
+    rep = mixed_precision_check(g["edep"], g["ledger"], r["edep"], r["ledger"], prim)
+    print("per-layer rms rel error", rep["rms"], flush=True)
+    h = E.debug_host_transport(E.make_config(cfg, n, precision=E.MIXED), geo, prim, n)
+    a = np.asarray(g["ledger"]["n_steps"], dtype=np.float64).sum()
+    b = np.asarray(h["ledger"]["n_steps"], dtype=np.float64).sum()
+    assert abs(a - b) <= 1e-3 * b
+
+
+def test_full_size_mixed_workload(E, oracle_mod):
+    """10^5 x 10 GeV e- in the mixed form, as the benchmark runs it: every
+    event conserves energy to 1e-5 and the per-layer means agree with a
+    24-event FP64 oracle sample within 3 sigma + 0.5%."""
+    print("full size mixed cal_10GeV_e-_x100k", flush=True)
+    geo, cfg, prim = I.workload("cal_10GeV_e-_x100k")
+    n = len(prim)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 25, precision=E.MIXED)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(n, 24, replace=False))
+    p = prim[sample].copy()
+    p["event"] = np.arange(len(sample))
+    r = oracle_mod.Oracle(geo, cfg).run(p, n_events=len(sample), event_keys=sample.astype(np.uint32))
+    gl = g["edep"].reshape(n, 50, 2).sum(axis=2)
+    ol = r["edep"].reshape(len(sample), 50, 2).sum(axis=2)
+    mg, mo = gl.mean(axis=0), ol.mean(axis=0)
+    sig = np.sqrt(gl.var(axis=0) / n + ol.var(axis=0) / len(sample))
+    assert np.all(np.abs(mg - mo) <= 3 * sig + 0.005 * np.abs(mo) + 1e-9)
+    # the sampled events mostly keep their FP64 histories (same draws)
+    close = np.isclose(g["edep"][sample].sum(axis=1), r["edep"].sum(axis=1), rtol=1e-2)
+    assert close.sum() >= 20

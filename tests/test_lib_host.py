@@ -138,3 +138,22 @@ def test_host_step_code_event_keys(E, oracle_mod):
     h = E.debug_host_transport(E.make_config(cfg, 2), geo, p, 2, keys=keys)
     r = oracle_mod.Oracle(geo, cfg).run(p, n_events=2, event_keys=keys)
     assert np.allclose(h["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("case", ["1GeV_e-", "mixed_species_bz3.8"])
+def test_host_mixed_precision_against_fp64_oracle(E, oracle_mod, case):
+    """The mixed form (FP32 tables, step lengths and sampling; FP64 positions,
+    boundaries and energies) on the host: conservation 1e-5, secondary counts
+    per-mil, per-layer means within 3 sigma + 0.5% of the FP64 oracle."""
+    from parity_util import mixed_precision_check
+    if case == "1GeV_e-":
+        geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    else:
+        geo = I.calorimeter()
+        cfg = I.RunConfig(seed=3, bz_tesla=3.8)
+        prim = I.mixed_species(24, 1e3, 5e3, seed=3)
+    n = len(prim)
+    h = E.debug_host_transport(E.make_config(cfg, n, precision=E.MIXED), geo, prim, n)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=n)
+    rep = mixed_precision_check(h["edep"], h["ledger"], r["edep"], r["ledger"], prim)
+    assert rep["rms"] < 0.01
