@@ -64,8 +64,10 @@ enum {
                                   charged path length (one more atomic per
                                   step); energy terms are always kept       */
   EMS_F_PROFILE = 1u << 2,     /* live tracks per species per iteration     */
-  EMS_F_EVENT_LIVE = 1u << 3   /* per-event live-track counters (set by the
+  EMS_F_EVENT_LIVE = 1u << 3,  /* per-event live-track counters (set by the
                                   offload server to detect finished events) */
+  EMS_F_KERNEL_TIMING = 1u << 4 /* a HIP event after every launch: per-kernel
+                                  device time in ems_run_stats.kernel_ms   */
 };
 
 typedef struct {
@@ -166,6 +168,11 @@ typedef struct {
                                     on the bound stream (gaps included)     */
   uint64_t visits[3];            /* track records loaded per species (one
                                     per visit of a thread to a track)       */
+  uint64_t made_by[2];           /* secondary records written by the photon
+                                    launches and by the e-/e+ launches      */
+  double kernel_ms[2];           /* with EMS_F_KERNEL_TIMING: device time of
+                                    the photon and of the e-/e+ launches,
+                                    event to event on the bound stream      */
 } ems_run_stats;
 
 typedef struct ems_ctx ems_ctx;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libems.so")
 ABI_VERSION = 1
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
-F_STEPLOG, F_FULL_LEDGER, F_PROFILE = 1, 2, 4
+F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING = 1, 2, 4, 8, 16
 
 
 class EmsError(RuntimeError):
@@ -51,7 +51,7 @@ class RunStats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("steps", C.c_uint64 * 3), ("created", C.c_uint64 * 3),
                 ("deferred", C.c_uint64), ("launches", C.c_uint64), ("peak_live", C.c_uint32 * 3),
                 ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double),
-                ("visits", C.c_uint64 * 3)]
+                ("visits", C.c_uint64 * 3), ("made_by", C.c_uint64 * 2), ("kernel_ms", C.c_double * 2)]
 
 
 class ServerInfo(C.Structure):
@@ -294,7 +294,8 @@ class Transport:
         _check(lib().ems_stats(self._h, C.byref(s)))
         return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
-                    run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits))
+                    run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits),
+                    made_by=list(s.made_by), kernel_ms=list(s.kernel_ms))
 
 
 class Server:

@@ -384,6 +384,7 @@ ems_status ems_destroy(ems_ctx* c) {
   if (c->pin_ctl) (void)hipHostFree(c->pin_ctl);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->evk) (void)hipEventDestroy(e);
   delete c;
   return EMS_OK;
 }
@@ -664,9 +665,21 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
 }
 
 ems_status rt_chunk(ems_ctx* c, uint32_t K) {
+  const bool timing = (c->cfg.flags & EMS_F_KERNEL_TIMING) != 0;
+  while (timing && c->evk.size() < 2 * (size_t)K + 1) {
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipEventCreate(&e));
+    c->evk.push_back(e);
+  }
   HIPCHK(c, launch_census(c->args, c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-  for (uint32_t k = 0; k < K; ++k) HIPCHK(c, launch_iteration(c->args, c->blocks_g, c->blocks_l, c->stream));
+  if (timing) HIPCHK(c, hipEventRecord(c->evk[0], c->stream));
+  for (uint32_t k = 0; k < K; ++k) {
+    HIPCHK(c, launch_visit(c->args, true, c->blocks_g, c->stream));
+    if (timing) HIPCHK(c, hipEventRecord(c->evk[2 * k + 1], c->stream));
+    HIPCHK(c, launch_visit(c->args, false, c->blocks_l, c->stream));
+    if (timing) HIPCHK(c, hipEventRecord(c->evk[2 * k + 2], c->stream));
+  }
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -675,6 +688,15 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
   const Ctl& s = *c->pin_ctl;
   ems_run_stats& st = c->stats;
   st.step_kernel_ms += ms;
+  for (uint32_t k = 0; timing && k < K; ++k) {
+    float a = 0.0f, b = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&a, c->evk[2 * k], c->evk[2 * k + 1]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->evk[2 * k + 1], c->evk[2 * k + 2]));
+    st.kernel_ms[0] += a;
+    st.kernel_ms[1] += b;
+  }
+  st.made_by[0] = s.made_by[0];
+  st.made_by[1] = s.made_by[1];
   st.launches += K;
   st.iterations = s.iteration;
   for (int i = 0; i < 3; ++i) {

@@ -65,6 +65,7 @@ struct Ctl {
   uint32_t cursor[2];     // next queue index handed out (photon, e-/e+ launch)
   unsigned long long steps[3], created[3], deferred, log_n;
   unsigned long long visits[3];  // track records loaded (one per visit)
+  unsigned long long made_by[2];  // secondary records written (photon, e-/e+ launches)
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
@@ -93,7 +94,7 @@ struct StepRec {
   double e_before, e_after, pos[3], step_len, edep;
 };
 
-enum : uint32_t { kFlagSteplog = 1u, kFlagFullLedger = 2u, kFlagProfile = 4u, kFlagEventLive = 8u };
+enum : uint32_t { kFlagSteplog = 1u, kFlagFullLedger = 2u, kFlagProfile = 4u, kFlagEventLive = 8u, kFlagTiming = 16u };
 
 struct KArgs {
   char* qbase;         // six queue buffers, see queue_view

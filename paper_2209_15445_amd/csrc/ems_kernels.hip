@@ -167,14 +167,27 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 // the queue from a per-launch cursor.  Lanes thus stay busy instead of
 // waiting for the wave's longest visit, without paying one atomic per track.
 // The order in which tracks are visited does not change any result.
-#ifndef EMS_PHOTON_WAVES
-#define EMS_PHOTON_WAVES 2
+// Minimum resident waves per SIMD the register allocation must allow, per
+// kernel and arithmetic type.
+#ifndef EMS_WAVES_F64_PHOTON
+#define EMS_WAVES_F64_PHOTON 2
 #endif
-#ifndef EMS_LEPTON_WAVES
-#define EMS_LEPTON_WAVES 2
+#ifndef EMS_WAVES_F64_LEPTON
+#define EMS_WAVES_F64_LEPTON 2
+#endif
+#ifndef EMS_WAVES_F32_PHOTON
+#define EMS_WAVES_F32_PHOTON 2
+#endif
+#ifndef EMS_WAVES_F32_LEPTON
+#define EMS_WAVES_F32_LEPTON 2
 #endif
 template <bool PHOTONS, class R>
-__global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAVES) void k_visit(KArgs a) {
+constexpr int visit_waves() {
+  return sizeof(R) == 8 ? (PHOTONS ? EMS_WAVES_F64_PHOTON : EMS_WAVES_F64_LEPTON)
+                        : (PHOTONS ? EMS_WAVES_F32_PHOTON : EMS_WAVES_F32_LEPTON);
+}
+template <bool PHOTONS, class R>
+__global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(KArgs a) {
   extern __shared__ double lds_words[];
   char* lds = reinterpret_cast<char*>(lds_words);
   Ctl* ctl = a.ctl;
@@ -370,6 +383,7 @@ __global__ __launch_bounds__(kBlock, PHOTONS ? EMS_PHOTON_WAVES : EMS_LEPTON_WAV
     wave_count(&ctl->created[0], made0);
     wave_count(&ctl->created[1], made1);
     wave_count(&ctl->created[2], made2);
+    wave_count(&ctl->made_by[PHOTONS ? 0 : 1], made0 + made1 + made2);
     const uint32_t c = wave_sum(steps_e + steps_p), k = wave_sum(carried_n);
     if (__lane_id() == 0) {
       if (c) atomicAdd(&ctl->commits, c);
@@ -475,15 +489,16 @@ __global__ void k_census(KArgs a) {
   }
 }
 
-template <class R>
-hipError_t launch_iteration_r(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
-  hipLaunchKernelGGL((k_visit<true, R>), dim3(blocks_g), dim3(kBlock), a.lds_g, s, a);
-  hipLaunchKernelGGL((k_visit<false, R>), dim3(blocks_l), dim3(kBlock), a.lds_l, s, a);
+// one iteration is the photon launch followed by the e-/e+ launch
+hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
+  if (photons) {
+    if (a.precision) hipLaunchKernelGGL((k_visit<true, float>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
+    else hipLaunchKernelGGL((k_visit<true, double>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
+  } else {
+    if (a.precision) hipLaunchKernelGGL((k_visit<false, float>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
+    else hipLaunchKernelGGL((k_visit<false, double>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
+  }
   return hipGetLastError();
-}
-hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s) {
-  return a.precision ? launch_iteration_r<float>(a, blocks_g, blocks_l, s)
-                     : launch_iteration_r<double>(a, blocks_g, blocks_l, s);
 }
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
   const uint32_t want = (n + kBlock - 1) / kBlock;

@@ -11,7 +11,7 @@
 
 namespace ems {
 
-hipError_t launch_iteration(const KArgs& a, uint32_t blocks_g, uint32_t blocks_l, hipStream_t s);
+hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s);
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
 hipError_t launch_census(const KArgs& a, hipStream_t s);
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
@@ -53,6 +53,7 @@ struct ems_ctx {
   InjRec* pin_inj = nullptr;
   Ctl* pin_ctl = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> evk;  // per-launch events (EMS_F_KERNEL_TIMING)
   bool failed = false;
   ems_run_stats stats{};
 };
