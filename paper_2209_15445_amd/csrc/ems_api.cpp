@@ -610,6 +610,7 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
         for (;;) {
           const double e0 = t.E;
           const bool end = visit_step<2>(env, sp, vs, t, o, max_visit);
+          if (o.pending) interact<2>(env, t, o);
           sink.apply(sp, t, o, e0);
           if (end) break;
         }

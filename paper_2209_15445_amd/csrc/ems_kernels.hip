@@ -212,6 +212,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
 
     bool has = false;   // lane holds a track (inside a visit or waiting to commit)
     bool fin = false;   // its visit ended; outputs wait for the batch commit
+    bool held = false;  // the visit's last step is not yet applied to the tallies
     bool drained = false;
     int sp = PHOTONS ? 0 : 1;
     Trk<R> t, before;
@@ -226,6 +227,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       // batch point: few lanes still stepping (or none, once the queue is drained)
       if (stepping <= (drained ? 0u : a.refill_below)) {
         if (any_fin) {
+          // the interactions selected by the lanes' last steps, sampled
+          // together (one pass through each sampler the wave needs)
+          if (fin && o.pending) interact<KIND>(env, t, o);
           // secondaries into the top regions (a step commits only if all of
           // its secondaries fit), then survivors or carried tracks
           uint32_t d[3];
@@ -242,6 +246,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           }
           const bool pending = fin && o.nsec > 0;
           const bool commit = pending && fits;
+          const bool apply_now = commit || (fin && held && o.nsec == 0);
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
             if (!d[q]) continue;
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
               ++s;
             }
           }
-          if (commit) {
+          if (apply_now) {
             sink.apply(sp, t, o, before.E);
             if (sp == 2) ++steps_p;
             else ++steps_e;
@@ -306,7 +311,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           if (fin) {
             has = false;
             fin = false;
+            held = false;
             o.nsec = 0;
+            o.pending = false;
           }
         }
         // refill empty lanes
@@ -361,7 +368,8 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
         before = t;
         const double e0 = t.E;
         fin = visit_step<KIND>(env, sp, vs, t, o, max_visit);
-        if (o.nsec == 0) {
+        held = o.pending;
+        if (!held) {
           sink.apply(sp, t, o, e0);
           if (sp == 2) ++steps_p;
           else ++steps_e;

@@ -104,6 +104,7 @@ struct StepOut {
   double clen;     // charged path length
   int pair, annih, null;
   uint32_t limiter, process;
+  bool pending;    // a discrete interaction `process` is selected but not yet sampled
   double step_len;
 };
 
@@ -151,6 +152,23 @@ EMS_HD double cont_loss(const StepEnv<R>& e, const R* Rt, int jT, double T, R S,
   else L = T - (double)inverse_range(e, Rt, Rv - (R)s, jT + 1);
   L = L < 0.0 ? 0.0 : L;
   return (T - L < e.ecut) ? T : L;
+}
+
+// Distance to the next discrete interaction, -ln(U0)/sigma, or kInf when it
+// certainly lies beyond `reach` so that its value is not needed: from
+// ln(1 - y) <= -y, u <= (1 - y)(1 - m) with y = sigma * reach gives
+// -ln(u)/sigma >= reach (1 + m/y) >= reach (1 + m), and the margin m (1e-9
+// in FP64, 1e-5 in FP32) is far above the rounding of the logarithm and the
+// division, so every comparison of the result with `reach` comes out as it
+// would with the exact value.
+template <class R>
+EMS_HD double phys_distance(Draws& r, R sig, double reach) {
+  if (!(sig > R(0))) return kInf;
+  const R u = r.u_at<R>(0);
+  const double y = (double)sig * reach;
+  const double m = sizeof(R) == 8 ? 1e-9 : 1e-5;
+  if ((double)u <= (1.0 - y) * (1.0 - m)) return kInf;
+  return (double)(-xlog(u) / sig);
 }
 
 template <class R>
@@ -220,26 +238,12 @@ EMS_HD void settle(const StepEnv<R>& e, Trk<R>& t, const Outcome<R>& oc, Draws& 
   }
 }
 
-// the discrete interaction of a photon at the end of a physics-limited step
+// process of a photon's discrete interaction (U1 against the partial sums)
 template <class R>
-EMS_HD void gamma_interact(const StepEnv<R>& e, uint32_t m, R sc, R sp, R sig, Trk<R>& t, Draws& r,
-                           StepOut<R>& o) {
-  const double E = t.E;
+EMS_HD void gamma_select(R sc, R sp, R sig, Draws& r, StepOut<R>& o) {
   const R pick = r.u_at<R>(1) * sig;
-  const V3T<R> u{t.ux, t.uy, t.uz};
-  Outcome<R> oc;
-  if (pick < sc) {
-    o.process = kXCompton;
-    compton(E, u, r, oc);
-  } else if (pick < sc + sp) {
-    o.process = kXPhot;
-    photo(E, u, oc);
-  } else {
-    o.process = kXConv;
-    pair(e.mat[m], E, u, r, oc);
-    o.pair += 1;
-  }
-  settle(e, t, oc, r, o);
+  o.process = pick < sc ? kXCompton : (pick < sc + sp ? kXPhot : kXConv);
+  o.pending = true;
 }
 
 template <class R>
@@ -262,7 +266,7 @@ EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   const double sg = sz <= sw ? sz : sw;
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
-  const double sphys = sig > R(0) ? (double)(-xlog(r.u_at<R>(0)) / sig) : kInf;
+  const double sphys = phys_distance(r, sig, sg);
   if (sg <= sphys) {
     t.x += sg * (double)t.ux;
     t.y += sg * (double)t.uy;
@@ -284,7 +288,7 @@ EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   t.z += sphys * (double)t.uz;
   o.step_len = sphys;
   o.limiter = kLimDiscrete;
-  gamma_interact(e, m, sc, sp, sig, t, r, o);
+  gamma_select(sc, sp, sig, r, o);
 }
 
 // discrete e-/e+ processes: table id and threshold (cross section is zero at
@@ -369,19 +373,17 @@ template <class R>
 EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
-  Outcome<R> oc;
   const double T = t.E;
   if (T < e.ecut) {
     o.dep += T;
     o.limiter = kLimSubcut;
     t.E = 0.0;
     if (positron) {
-      o.process = kXAnnihRest;
-      annihilate_at_rest(r, oc);
-      o.annih += 1;
-      settle(e, t, oc, r, o);
+      o.process = kXAnnihRest;  // the track ends with the interaction
+      o.pending = true;
+    } else {
+      t.slab = -1;
     }
-    t.slab = -1;
     return;
   }
   const bool field = e.bz != 0.0;
@@ -432,7 +434,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   const double a = from_cut ? e.ecut : elo;
   const LeptonProcs pl = lepton_procs(e, positron);
   const R bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
-  const double sphys = bound > R(0) ? (double)(-xlog(r.u_at<R>(0)) / bound) : kInf;
+  const double sphys = phys_distance(r, bound, smax);
   double s;
   uint32_t lim;
   if (sphys < smax) {
@@ -475,11 +477,10 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     o.limiter = kLimStopped;
     if (positron) {
       o.process = kXAnnihRest;
-      annihilate_at_rest(r, oc);
-      o.annih += 1;
-      settle(e, t, oc, r, o);
+      o.pending = true;
+    } else {
+      t.slab = -1;
     }
-    t.slab = -1;
     return;
   }
   if (lim == kLimZ) {
@@ -509,17 +510,52 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     return;
   }
   o.process = code;
+  o.pending = true;
+}
+
+// The discrete interaction selected by the step (o.process, o.pending):
+// sampling from the step's draws U2, U3, ... (U1, U2 for annihilation at
+// rest), secondaries handed out, parent updated, then the step counter and
+// watchdog.  Running it right after the step or later in a batch with other
+// tracks gives the same result.  KIND: 0 = photon processes only, 1 = e-/e+
+// processes only, 2 = any.
+template <int KIND, class R>
+EMS_HD void interact(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
+  Draws r;
+  r.init(e.seed, t.key, t.id, t.n);
+  Outcome<R> oc;
+  const double E = t.E;
   const V3T<R> u{t.ux, t.uy, t.uz};
-  switch (code) {
-    case kXMoller: moller(Tp, e.tcut, u, r, oc); break;
-    case kXBhabha: bhabha(Tp, e.tcut, u, r, oc); break;
-    case kXBrem: brem(e.mat[m], Tp, e.kcut, u, r, oc); break;
-    default:
-      annihilate(Tp, u, r, oc);
-      o.annih += 1;
-      break;
+  const MatRT& mr = e.mat[e.slab_mat[t.slab]];
+  const uint32_t p = o.process;
+  if (KIND != 1 && p == kXCompton) {
+    compton(E, u, r, oc);
+  } else if (KIND != 1 && p == kXPhot) {
+    photo(E, u, oc);
+  } else if (KIND != 1 && p == kXConv) {
+    pair(mr, E, u, r, oc);
+    o.pair += 1;
+  } else if (KIND != 0 && p == kXMoller) {
+    moller(E, e.tcut, u, r, oc);
+  } else if (KIND != 0 && p == kXBhabha) {
+    bhabha(E, e.tcut, u, r, oc);
+  } else if (KIND != 0 && p == kXBrem) {
+    brem(mr, E, e.kcut, u, r, oc);
+  } else if (KIND != 0 && p == kXAnnih) {
+    annihilate(E, u, r, oc);
+    o.annih += 1;
+  } else if (KIND != 0) {  // kXAnnihRest
+    annihilate_at_rest(r, oc);
+    o.annih += 1;
+  } else {
+    oc.survives = true;  // not reached: photon steps select only the three above
+    oc.e_parent = E;
+    oc.u_parent = u;
+    oc.n = 0;
   }
   settle(e, t, oc, r, o);
+  o.pending = false;
+  watchdog(e, t, o);
 }
 
 template <class R>
@@ -530,6 +566,7 @@ EMS_HD void clear_out(const Trk<R>& t, StepOut<R>& o) {
   o.pair = o.annih = o.null = 0;
   o.limiter = 0;
   o.process = kXNone;
+  o.pending = false;
 }
 
 template <class R>
@@ -549,7 +586,8 @@ EMS_HD void take_step_k(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
   clear_out(t, o);
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step(e, t, o);
   else lepton_step(e, sp == kPositron, t, o);
-  watchdog(e, t, o);
+  if (o.pending) interact<KIND>(e, t, o);
+  else watchdog(e, t, o);
 }
 template <class R>
 EMS_HD void take_step(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
@@ -604,7 +642,7 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
     const double sg = sz <= sw ? sz : sw;
     Draws r;
     r.init(e.seed, t.key, t.id, t.n);
-    const double sphys = sig > R(0) ? (double)(-xlog(r.u_at<R>(0)) / sig) : kInf;
+    const double sphys = phys_distance(r, sig, sg);
     if (sg <= sphys) {
       t.x += sg * ux;
       t.y += sg * uy;
@@ -625,10 +663,10 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
       t.z += sphys * uz;
       o.step_len = sphys;
       o.limiter = kLimDiscrete;
-      gamma_interact(e, m, sc, sp, sig, t, r, o);
+      gamma_select(sc, sp, sig, r, o);
     }
   }
-  watchdog(e, t, o);
+  if (!o.pending) watchdog(e, t, o);
   // any interaction changes E and u (even one whose electron was deposited
   // on the spot), so the visit ends there
   return t.slab < 0 || o.limiter == kLimDiscrete;
@@ -649,20 +687,25 @@ EMS_HD void visit_begin(const StepEnv<R>& e, int sp, const Trk<R>& t, VisitState
 
 // One step of a visit; returns true when the visit ends after it.  A visit
 // is a run of consecutive steps of one track by one thread; it ends at a
-// step that creates secondaries, when the track ends, or after max_steps
-// steps.  Every step draws from its own (id, step) stream, so a run of
-// visits is step for step the one-step-at-a-time loop.
+// step with a discrete interaction (every real one changes the track and
+// all but a few create secondaries), when the track ends, or after
+// max_steps steps.  Every step draws from its own (id, step) stream, so a
+// run of visits is step for step the one-step-at-a-time loop.  The step's
+// interaction is left pending (o.pending) for the caller to run with
+// interact(), so that a wave samples its interactions together.
 template <int KIND, class R>
 EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps) {
   bool end;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
     end = photon_substep(e, vs.pc, t, o);
   } else {
-    take_step_k<1>(e, sp, t, o);
-    end = t.slab < 0;
+    clear_out(t, o);
+    lepton_step(e, sp == kPositron, t, o);
+    if (!o.pending) watchdog(e, t, o);
+    end = t.slab < 0 || o.pending;
   }
   vs.steps += 1;
-  return end || o.nsec > 0 || vs.steps >= max_steps;
+  return end || vs.steps >= max_steps;
 }
 
 }  // namespace ems
