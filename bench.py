@@ -193,17 +193,20 @@ def transport_leg(E, I, workload, precision, capacity, args):
     dt = time.perf_counter() - t0
     eng.close()
     tb = TRACK_BYTES if precision == E.FP64 else TRACK_BYTES_MIXED
-    # per launch of each kernel: every visit reads one track record and
-    # writes at most one (survivor or carried track); every secondary record
-    # is written once
+    # algorithmic bytes of the method: every track-step reads the track's
+    # record and writes the survivor (2 records), every secondary adds one
+    # record.  Multi-step visits move fewer: one read and at most one write
+    # per visit ("record_bytes_per_launch").
     names = ["k_visit<photons>", "k_visit<e-/e+>"]
-    alg = [tb * (2 * visits[0] + made_by[0]), tb * (2 * (visits[1] + visits[2]) + made_by[1])]
+    alg = [tb * (2 * steps[0] + made_by[0]), tb * (2 * (steps[1] + steps[2]) + made_by[1])]
+    rec = [tb * (2 * visits[0] + made_by[0]), tb * (2 * (visits[1] + visits[2]) + made_by[1])]
     kern = {}
     for i in range(2):
         per_launch = alg[i] / max(launches, 1)
         avg_s = kms[i] / 1e3 / max(launches, 1)
         ach = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
         kern[names[i]] = {"achieved": ach, "frac": ach / HBM_PEAK_GBS, "bytes_per_launch": per_launch,
+                          "record_bytes_per_launch": rec[i] / max(launches, 1),
                           "avg_launch_us": avg_s * 1e6, "launches": launches, "share_of_kernel_time":
                           kms[i] / max(sum(kms), 1e-12)}
     dom = names[1] if kms[1] >= kms[0] else names[0]
