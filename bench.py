@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
     ap.add_argument("--mixed-capacity", type=int, default=1 << 25)
+    ap.add_argument("--extra-workload", default="cal_mixed_1-100GeV_bz3.8_x10k",
+                    help="also time this workload in both forms ('' to skip)")
     ap.add_argument("--serve-slots", type=int, default=4096)
     ap.add_argument("--serve-producers", type=int, default=64)
     ap.add_argument("--serve-window", type=int, default=64, help="outstanding requests per producer (closed loop)")
@@ -364,6 +366,14 @@ def main():
                         "track_steps_per_step": mx["track_steps"], "roofline": mx["roofline"]}
         if not args.no_cpu:
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
+    if args.extra_workload:
+        out["other_workloads"] = {}
+        for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
+            leg = transport_leg(E, I, args.extra_workload, prec, args.mixed_capacity, args)
+            out["other_workloads"][f"{args.extra_workload}/{tag}"] = {
+                "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
+                "track_steps_per_step": leg["track_steps"],
+                "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in leg["roofline"]["kernels"].items()}}
     if not args.no_serve:
         out["serving"] = serving(E, I, args, E.FP64)
         if not args.no_mixed:

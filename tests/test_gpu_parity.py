@@ -191,9 +191,9 @@ def test_empty_run_and_edges(E):
     assert L["n_annih"][1] == 1 and abs(e[1].sum() + L["escaped"][1].sum() - (5e-4 + 2 * 0.51099895)) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k"])
+@pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k", "cal_mixed_1-100GeV_bz3.8_x10k"])
 def test_full_size_workload_sampled(E, oracle_mod, name):
-    """The benchmark workload in the benchmark's launch configuration: every
+    """Full-size workloads in the benchmark's launch configuration: every
     event conserves energy, oracle-sampled events agree exactly, per-layer
     means agree with the oracle sample within 3 sigma + 0.5%."""
     print(f"full size {name}", flush=True)
@@ -207,6 +207,8 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     p["event"] = np.arange(len(sample))
     r = oracle_mod.Oracle(geo, cfg).run(p, n_events=len(sample), event_keys=sample.astype(np.uint32))
     assert np.allclose(g["edep"][sample], r["edep"], rtol=1e-8, atol=1e-8)
+    for f in ("n_pair", "n_annih"):
+        assert np.array_equal(g["ledger"][f][sample], r["ledger"][f]), f
     # per-layer statistics
     gl = g["edep"].reshape(n, 50, 2).sum(axis=2)
     ol = r["edep"].reshape(len(sample), 50, 2).sum(axis=2)
@@ -261,3 +263,23 @@ def test_full_size_mixed_workload(E, oracle_mod):
     # the sampled events mostly keep their FP64 histories (same draws)
     close = np.isclose(g["edep"][sample].sum(axis=1), r["edep"].sum(axis=1), rtol=1e-2)
     assert close.sum() >= 20
+
+
+def test_full_size_mixed_species_workload_mixed_form(E, oracle_mod):
+    """10^4 mixed-species 1-100 GeV events in Bz = 3.8 T in the mixed form:
+    conservation 1e-5, per-layer means within 3 sigma + 0.5% of a 24-event
+    FP64 oracle sample (same events, same keys)."""
+    print("full size mixed form cal_mixed_1-100GeV_bz3.8_x10k", flush=True)
+    geo, cfg, prim = I.workload("cal_mixed_1-100GeV_bz3.8_x10k")
+    n = len(prim)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=8 << 20, precision=E.MIXED)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(n, 24, replace=False))
+    p = prim[sample].copy()
+    p["event"] = np.arange(len(sample))
+    r = oracle_mod.Oracle(geo, cfg).run(p, n_events=len(sample), event_keys=sample.astype(np.uint32))
+    gl = g["edep"][sample].reshape(24, 50, 2).sum(axis=2)
+    ol = r["edep"].reshape(24, 50, 2).sum(axis=2)
+    sig = np.sqrt(gl.var(axis=0) / 24 + ol.var(axis=0) / 24)
+    assert np.all(np.abs(gl.mean(axis=0) - ol.mean(axis=0)) <= 3 * sig + 0.005 * ol.mean(axis=0) + 1e-9)
