@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
     ap.add_argument("--steps-per-visit", type=int, default=16)
-    ap.add_argument("--refill-below", type=int, default=8)
+    ap.add_argument("--refill-below", type=int, default=16)
     ap.add_argument("--cpu-events", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")

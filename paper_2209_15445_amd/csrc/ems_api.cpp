@@ -340,6 +340,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   const uint32_t cus = (uint32_t)prop.multiProcessorCount;
   c->blocks_g = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_g;
   c->blocks_l = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_l;
+  a.waves_g = c->blocks_g * 4;  // 256-thread blocks of 64-lane waves
+  a.waves_l = c->blocks_l * 4;
 
   if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_inj), kInjectChunk * sizeof(InjRec)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
@@ -470,6 +472,7 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   for (int s = 0; s < 3; ++s) {
     fresh.n_home[s] = c->pin_ctl->n_home[s];
     fresh.n_sec[s] = c->pin_ctl->n_sec[s];
+    fresh.n_real[s] = c->pin_ctl->n_real[s];
   }
   *c->pin_ctl = fresh;
   HIPCHK(c, hipMemcpyAsync(c->ws + L.ctl, c->pin_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));

@@ -66,6 +66,11 @@ struct Ctl {
   unsigned long long steps[3], created[3], deferred, log_n;
   unsigned long long visits[3];  // track records loaded (one per visit)
   unsigned long long made_by[2];  // secondary records written (photon, e-/e+ launches)
+  // Live records: the extents n_home + n_sec may include dead slots (unused
+  // ends of wave-private append chunks); n_real counts the live tracks of
+  // the current queues, next_real those written to the next queues.
+  uint32_t n_real[3];
+  uint32_t next_real[3];
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
@@ -120,6 +125,7 @@ struct KArgs {
   uint32_t steps_per_visit;   // steps a thread may take per launch
   uint32_t refill_below;      // batch commit/refill when at most this many lanes still step
   uint32_t precision;  // 0: FP64 kernels, 1: mixed kernels
+  uint32_t waves_g, waves_l;  // waves of the photon and of the e-/e+ launch
   StepEnv<double> env;  // scalars; its pointers are set per block
 };
 

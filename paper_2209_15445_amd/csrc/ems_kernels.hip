@@ -48,6 +48,106 @@ __device__ inline uint32_t wave_reserve(uint32_t* counter, uint32_t count) {
   return base + prefix;
 }
 
+// Next queue index for every lane with `want`: taken from the wave's own
+// range [lo, hi), which is refilled EMS_CURSOR_CHUNK indices at a time from
+// the launch's global cursor, so a wave pays one global atomic per chunk
+// instead of one per refill.  Every index below the cursor's final value is
+// handed out exactly once (ranges are disjoint and none is dropped).
+#ifndef EMS_CURSOR_CHUNK
+#define EMS_CURSOR_CHUNK 64
+#endif
+static_assert(EMS_CURSOR_CHUNK <= 1 || EMS_CURSOR_CHUNK >= 64, "a chunk must cover a whole wave's request");
+__device__ inline uint32_t take_next(uint32_t* cursor, bool want, uint32_t& lo, uint32_t& hi) {
+  if (EMS_CURSOR_CHUNK <= 1) return wave_reserve(cursor, want ? 1u : 0u);
+  const uint64_t m = __ballot(want);
+  const uint32_t n = (uint32_t)__popcll(m);
+  const uint32_t rank = (uint32_t)__popcll(m & __lanemask_lt());
+  const uint32_t avail = hi - lo;
+  uint32_t i = lo + rank;
+  if (n > avail) {
+    // the rest of the old range, then a fresh chunk (n <= 64 <= chunk size)
+    uint32_t base = 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    if ((int)__lane_id() == leader) base = atomicAdd(cursor, (uint32_t)EMS_CURSOR_CHUNK);
+    base = __shfl(base, leader);
+    if (rank >= avail) i = base + (rank - avail);
+    lo = base + (n - avail);
+    hi = base + EMS_CURSOR_CHUNK;
+  } else {
+    lo += n;
+  }
+  return i;
+}
+
+// Append slots in wave-private chunks.  A wave holds a range [lo, hi) of an
+// append counter and refills it `chunk` slots at a time (one global atomic
+// per chunk instead of one per batch: thousands of waves appending to the
+// same few counters otherwise serialise on them).  take_slots reserves cnt
+// (0..3) slots per lane and returns the lane's first position x in the
+// wave's request; its k-th slot is slot_of(tk, x + k).  Unused ends of the
+// ranges are marked dead when the wave exits.  chunk = 1 is exact
+// reservation (no unused slots).
+struct Take {
+  uint32_t lo, avail, base;
+};
+__device__ inline uint32_t take_slots(uint32_t* counter, uint32_t cnt, uint32_t chunk, uint32_t& lo, uint32_t& hi,
+                                      Take& tk) {
+  const uint64_t b0 = __ballot(cnt & 1u);
+  const uint64_t b1 = __ballot((cnt >> 1) & 1u);
+  const uint32_t total = (uint32_t)(__popcll(b0) + 2 * __popcll(b1));
+  const uint64_t lt = __lanemask_lt();
+  const uint32_t prefix = (uint32_t)(__popcll(b0 & lt) + 2 * __popcll(b1 & lt));
+  tk.lo = lo;
+  tk.avail = hi - lo;
+  tk.base = 0;
+  if (total > tk.avail) {
+    const uint32_t need = total - tk.avail;
+    const uint32_t grab = need > chunk ? need : chunk;
+    const int leader = __ffsll((unsigned long long)(b0 | b1)) - 1;
+    uint32_t base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(counter, grab);
+    base = __builtin_amdgcn_readfirstlane(__shfl(base, leader));
+    tk.base = base;
+    lo = base + need;
+    hi = base + grab;
+  } else {
+    lo += total;
+  }
+  return prefix;
+}
+__device__ inline uint32_t slot_of(const Take& tk, uint32_t x) {
+  return x < tk.avail ? tk.lo + x : tk.base + (x - tk.avail);
+}
+
+// Per-iteration append plan of species q (the same in both launches of an
+// iteration, computed from the current queue sizes).  The chunk is the
+// largest power of two up to EMS_APPEND_CHUNK for which all waves together
+// leave unused at most a quarter of the current population and of the free
+// room (so small populations append exactly); the secondary limit leaves
+// room for every survivor plus the unused chunk ends of the home region.
+#ifndef EMS_APPEND_CHUNK
+#define EMS_APPEND_CHUNK 256
+#endif
+struct Plan {
+  uint32_t lim[3], chunk[3];
+};
+__device__ inline Plan append_plan(const KArgs& a, uint32_t n0, uint32_t n1, uint32_t n2) {
+  Plan p;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint64_t n = q == 0 ? n0 : (q == 1 ? n1 : n2);
+    const uint64_t room = a.cap - n;
+    const uint64_t waves = (uint64_t)a.waves_g + a.waves_l;
+    const uint64_t budget = (n < room ? n : room) / 4;
+    uint32_t chunk = EMS_APPEND_CHUNK;
+    while (chunk > 1 && waves * chunk > budget) chunk >>= 1;
+    const uint64_t home_waves = q == 0 ? a.waves_g : a.waves_l;
+    p.chunk[q] = chunk;
+    p.lim[q] = (uint32_t)(room - (chunk > 1 ? home_waves * chunk : 0));
+  }
+  return p;
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
@@ -57,6 +157,10 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
 __device__ inline void wave_count(unsigned long long* counter, uint32_t v) {
   const uint32_t s = wave_sum(v);
   if (__lane_id() == 0 && s) atomicAdd(counter, (unsigned long long)s);
+}
+__device__ inline void wave_count(uint32_t* counter, uint32_t v) {
+  const uint32_t s = wave_sum(v);
+  if (__lane_id() == 0 && s) atomicAdd(counter, s);
 }
 
 template <class R>
@@ -204,7 +308,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     const uint32_t nxt = cur ^ 1u;
     const int max_visit = (int)a.steps_per_visit;
     // secondary slots per species that leave room for all survivors
-    const uint32_t lim0 = (uint32_t)(a.cap - n0), lim1 = (uint32_t)(a.cap - n1), lim2 = (uint32_t)(a.cap - n2);
+    const Plan plan = append_plan(a, n0, n1, n2);
+    const uint32_t lim0 = plan.lim[0], lim1 = plan.lim[1], lim2 = plan.lim[2];
+    // wave-private append ranges (uniform): secondaries and home, per species
+    uint32_t slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, hlo[3] = {0, 0, 0}, hhi[3] = {0, 0, 0};
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
                  (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
@@ -214,6 +321,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     bool fin = false;   // its visit ended; outputs wait for the batch commit
     bool held = false;  // the visit's last step is not yet applied to the tallies
     bool drained = false;
+    uint32_t chunk_lo = 0, chunk_hi = 0;  // queue indices held by this wave (uniform)
     int sp = PHOTONS ? 0 : 1;
     Trk<R> t, before;
     VisitState<R> vs;
@@ -221,6 +329,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     o.nsec = 0;
     uint32_t visits_e = 0, visits_p = 0, steps_e = 0, steps_p = 0, carried_n = 0;
     uint32_t made0 = 0, made1 = 0, made2 = 0;
+    uint32_t kept_a = 0, kept_b = 0;  // home records written (own species; e+)
     for (;;) {
       const uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin));
       const bool any_fin = __ballot(fin) != 0;
@@ -237,12 +346,14 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           for (int q = 0; q < 3; ++q)
             d[q] = (fin && o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (fin && o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
           uint32_t slot[3];
+          Take tk[3];
           bool fits = true;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            slot[q] = wave_reserve(&ctl->next_sec[q], d[q]);
+            slot[q] = take_slots(&ctl->next_sec[q], d[q], plan.chunk[q], slo[q], shi[q], tk[q]);
             const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
-            if (d[q] && slot[q] + d[q] > lim) fits = false;
+            if (d[q] && slot_of(tk[q], slot[q] + d[q] - 1) >= lim) fits = false;
+            if (d[q] > 1 && slot_of(tk[q], slot[q]) >= lim) fits = false;
           }
           const bool pending = fin && o.nsec > 0;
           const bool commit = pending && fits;
@@ -252,10 +363,11 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
             if (!d[q]) continue;
             const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
             const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
-            uint32_t s = slot[q];
+            uint32_t x = slot[q];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
               if (!(k < o.nsec && o.sec[k].sp == q)) continue;
+              const uint32_t s = slot_of(tk[q], x);
               if (s < lim) {
                 const uint32_t p = (uint32_t)(a.cap - 1 - s);
                 if (commit) {
@@ -276,7 +388,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
                   dq.slab[p] = -1;  // refused: the next iteration skips this slot
                 }
               }
-              ++s;
+              ++x;
             }
           }
           if (apply_now) {
@@ -294,12 +406,19 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
 #pragma unroll
           for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
             const bool mine = keep && sp == q;
-            const uint32_t hs = wave_reserve(&ctl->next_home[q], mine ? 1u : 0u);
+            Take th;
+            const uint32_t hx = take_slots(&ctl->next_home[q], mine ? 1u : 0u, plan.chunk[q], hlo[q], hhi[q], th);
+            const uint32_t hs = slot_of(th, hx);
             if (mine) {
               const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
-              if (hs >= a.cap) atomicOr(&ctl->error, kErrOverflow);
-              else if (carry) store_track(dq, hs, before);
-              else store_track(dq, hs, t);
+              if (hs >= a.cap) {
+                atomicOr(&ctl->error, kErrOverflow);
+              } else {
+                if (carry) store_track(dq, hs, before);
+                else store_track(dq, hs, t);
+                if (q == 2) ++kept_b;
+                else ++kept_a;
+              }
             }
           }
           if (fin && track_live) {
@@ -316,10 +435,12 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
             o.pending = false;
           }
         }
-        // refill empty lanes
-        if (!drained) {
+        // refill empty lanes; a lane that drew a dead slot (a refused
+        // secondary or an unused chunk end) draws again, a few times
+        for (int round = 0; round < 4 && !drained; ++round) {
           const bool want = !has;
-          const uint32_t i = wave_reserve(cursor, want ? 1u : 0u);
+          if (__ballot(want) == 0) break;
+          const uint32_t i = take_next(cursor, want, chunk_lo, chunk_hi);
           if (want && i < nmine) {
             sp = PHOTONS ? 0 : 1;
             uint32_t idx = i, home = PHOTONS ? h0 : h1;
@@ -377,6 +498,17 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       }
     }
 
+    // unused ends of the wave's append ranges hold no track
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
+      const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
+      const uint32_t send = shi[q] < lim ? shi[q] : lim;
+      for (uint32_t x = slo[q] + __lane_id(); x < send; x += 64) dq.slab[a.cap - 1 - x] = -1;
+      for (uint32_t x = hlo[q] + __lane_id(); x < hhi[q]; x += 64) {
+        if (x < a.cap) dq.slab[x] = -1;
+      }
+    }
     // statistics and per-launch progress
     if (PHOTONS) {
       wave_count(&ctl->steps[0], steps_e);
@@ -392,6 +524,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     wave_count(&ctl->created[1], made1);
     wave_count(&ctl->created[2], made2);
     wave_count(&ctl->made_by[PHOTONS ? 0 : 1], made0 + made1 + made2);
+    wave_count(&ctl->next_real[0], made0 + (PHOTONS ? kept_a : 0u));
+    wave_count(&ctl->next_real[1], made1 + (PHOTONS ? 0u : kept_a));
+    wave_count(&ctl->next_real[2], made2 + kept_b);
     const uint32_t c = wave_sum(steps_e + steps_p), k = wave_sum(carried_n);
     if (__lane_id() == 0) {
       if (c) atomicAdd(&ctl->commits, c);
@@ -412,28 +547,34 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
   __syncthreads();
   if (last && threadIdx.x == 0) {
     __threadfence();
+    const uint32_t r0 = ctl->n_real[0], r1 = ctl->n_real[1], r2 = ctl->n_real[2];
     if (a.flags & kFlagProfile) {
       if (ctl->iteration < a.profile_cap) {
-        a.profile[(size_t)ctl->iteration * 3 + 0] = n0;
-        a.profile[(size_t)ctl->iteration * 3 + 1] = n1;
-        a.profile[(size_t)ctl->iteration * 3 + 2] = n2;
+        a.profile[(size_t)ctl->iteration * 3 + 0] = r0;
+        a.profile[(size_t)ctl->iteration * 3 + 1] = r1;
+        a.profile[(size_t)ctl->iteration * 3 + 2] = r2;
       }
     }
-    if (n0 + n1 + n2 > 0) ctl->iteration += 1;
+    if (r0 + r1 + r2 > 0) ctl->iteration += 1;
     const uint32_t commits = atomicAdd(&ctl->commits, 0u), carried = atomicAdd(&ctl->carried, 0u);
     if (carried > 0 && commits == 0) ctl->error |= kErrStall;  // nothing can move: queues too small
     uint32_t live = 0;
+    for (int q = 0; q < 3; ++q) live += atomicAdd(&ctl->next_real[q], 0u);
+    const Plan plan = append_plan(a, n0, n1, n2);
     for (int q = 0; q < 3; ++q) {
-      const uint32_t lim = (uint32_t)(a.cap - (q == 0 ? n0 : (q == 1 ? n1 : n2)));
+      const uint32_t lim = plan.lim[q];
       const uint32_t hv = atomicAdd(&ctl->next_home[q], 0u);
       uint32_t sv = atomicAdd(&ctl->next_sec[q], 0u);
       sv = sv < lim ? sv : lim;
-      ctl->n_home[q] = hv;
-      ctl->n_sec[q] = sv;
+      const uint32_t rv = atomicAdd(&ctl->next_real[q], 0u);
+      // with no live track left the dead slots need no visit
+      ctl->n_home[q] = live ? hv : 0u;
+      ctl->n_sec[q] = live ? sv : 0u;
+      ctl->n_real[q] = rv;
       ctl->next_home[q] = 0;
       ctl->next_sec[q] = 0;
-      ctl->peak[q] = hv + sv > ctl->peak[q] ? hv + sv : ctl->peak[q];
-      live += hv + sv;
+      ctl->next_real[q] = 0;
+      ctl->peak[q] = rv > ctl->peak[q] ? rv : ctl->peak[q];
     }
     ctl->live = live;
     ctl->commits = 0;
@@ -460,8 +601,10 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
     for (int qs = 0; qs < 3; ++qs) {
       const uint32_t cnt = (active && (int)r.sp == qs) ? 1u : 0u;
       const uint32_t slot = wave_reserve(&ctl->n_home[qs], cnt);
+      const bool fits = cnt && slot + ctl->n_sec[qs] < a.cap;
+      wave_count(&ctl->n_real[qs], fits ? 1u : 0u);
       if (!cnt) continue;
-      if (slot + ctl->n_sec[qs] >= a.cap) {
+      if (!fits) {
         atomicOr(&ctl->error, kErrOverflow);
         continue;
       }
@@ -489,7 +632,7 @@ __global__ void k_census(KArgs a) {
     Ctl* c = a.ctl;
     uint32_t live = 0;
     for (int q = 0; q < 3; ++q) {
-      const uint32_t n = c->n_home[q] + c->n_sec[q];
+      const uint32_t n = c->n_real[q];
       c->peak[q] = n > c->peak[q] ? n : c->peak[q];
       live += n;
     }
