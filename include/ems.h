@@ -77,7 +77,7 @@ typedef struct {
 /* Slab stack along z (the paper's 50-layer sampling calorimeter, section
  * 2.2): slab k spans [z_mm[k], z_mm[k+1]) and is made of material[k]. */
 typedef struct {
-  uint32_t n_slabs;              /* 1 .. 4096                               */
+  uint32_t n_slabs;              /* 1 .. 4095                               */
   const double* z_mm;            /* host, n_slabs + 1 strictly increasing   */
   const uint32_t* material;      /* host, n_slabs indices < n_materials     */
   uint32_t n_materials;          /* 1 .. 4                                  */
@@ -98,7 +98,7 @@ typedef struct {
   double lin_loss_limit;         /* linear-loss limit (fraction of range)    */
   uint32_t process_mask;         /* EMS_P_* bits                             */
   uint32_t flags;                /* EMS_F_* bits                             */
-  uint32_t max_steps_per_track;  /* watchdog (>= 1)                          */
+  uint32_t max_steps_per_track;  /* watchdog, 1 .. 2^20 - 1                  */
   uint32_t seed;                 /* Philox key word 0                        */
   uint32_t max_events;           /* tally rows (>= 1)                        */
   uint64_t track_capacity;       /* tracks per species per queue, 64..2^28 */

@@ -150,7 +150,7 @@ class _GeoHolder:
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
-                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=8):
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=16):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
     c = Config()

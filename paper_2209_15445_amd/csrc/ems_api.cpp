@@ -44,8 +44,8 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (!c || !g) return fail(EMS_E_INVALID, "null config or geometry");
   if (c->abi_version != EMS_ABI_VERSION) return fail(EMS_E_VERSION, "abi_version mismatch");
   if (c->precision != EMS_FP64 && c->precision != EMS_MIXED) return fail(EMS_E_INVALID, "precision must be EMS_FP64 or EMS_MIXED");
-  if (g->n_slabs < 1 || g->n_slabs > 4096 || !g->z_mm || !g->material)
-    return fail(EMS_E_INVALID, "geometry needs 1..4096 slabs with planes and materials");
+  if (g->n_slabs < 1 || g->n_slabs > kMaxSlabs || !g->z_mm || !g->material)
+    return fail(EMS_E_INVALID, "geometry needs 1..4095 slabs with planes and materials");
   if (g->n_materials < 1 || g->n_materials > 4 || !g->materials)
     return fail(EMS_E_INVALID, "geometry needs 1..4 materials");
   if (!(g->half_xy_mm > 0.0) || !isfinite(g->half_xy_mm)) return fail(EMS_E_INVALID, "half_xy_mm must be > 0");
@@ -67,7 +67,8 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
       !(c->lin_loss_limit > 0.0 && c->lin_loss_limit < 1.0))
     return fail(EMS_E_INVALID, "bad step-function parameters");
   if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
-  if (c->max_steps_per_track < 1 || c->max_events < 1) return fail(EMS_E_INVALID, "max_steps and max_events >= 1");
+  if (c->max_steps_per_track < 1 || c->max_steps_per_track > kMaxStepsPerTrack || c->max_events < 1)
+    return fail(EMS_E_INVALID, "max_steps_per_track in [1, 2^20 - 1] and max_events >= 1");
   if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");
   if (c->refill_below > 63) return fail(EMS_E_INVALID, "refill_below in [0, 63]");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))

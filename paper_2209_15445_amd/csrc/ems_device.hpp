@@ -6,16 +6,21 @@
 namespace ems {
 
 // One species queue buffer, structure of arrays: position and energy in
-// FP64, 64-bit id, direction in the arithmetic type R, then event row, step
-// and slab (76 bytes per track in the FP64 form, 64 in the mixed form).  The
-// six buffers (2 x 3 species) are consecutive blocks of cap * track_bytes.
+// FP64, 64-bit id, direction in the arithmetic type R, then event row, RNG
+// event key, and step count and slab packed in one word (n << 12 | slab;
+// all ones marks a dead slot).  76 bytes per track in the FP64 form, 64 in
+// the mixed form.  The six buffers (2 x 3 species) are consecutive blocks of
+// cap * track_bytes.
+constexpr uint32_t kSlabBits = 12, kSlabMask = (1u << kSlabBits) - 1;
+constexpr uint32_t kMaxSlabs = kSlabMask;                 // slab indices 0..4094
+constexpr uint32_t kMaxStepsPerTrack = (1u << 20) - 1;    // step counts fit 20 bits
+constexpr uint32_t kDeadRecord = 0xFFFFFFFFu;
 template <class R>
 struct Queue {
   double *x, *y, *z, *E;
   uint64_t* id;
   R *ux, *uy, *uz;
-  uint32_t *ev, *n;
-  int32_t* slab;
+  uint32_t *ev, *key, *ns;
 };
 template <class R>
 constexpr size_t track_bytes() {
@@ -35,8 +40,8 @@ EMS_HD Queue<R> queue_view(char* base, uint64_t cap, uint32_t buf, uint32_t sp) 
   q.uy = q.ux + cap;
   q.uz = q.uy + cap;
   q.ev = reinterpret_cast<uint32_t*>(q.uz + cap);
-  q.n = q.ev + cap;
-  q.slab = reinterpret_cast<int32_t*>(q.n + cap);
+  q.key = q.ev + cap;
+  q.ns = q.key + cap;
   return q;
 }
 

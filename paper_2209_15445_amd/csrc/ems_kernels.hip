@@ -30,6 +30,9 @@ namespace ems {
 namespace {
 
 constexpr int kBlock = 256;
+// s_waitcnt immediate for "all vector memory operations done" (vmcnt 0,
+// expcnt and lgkmcnt at their maxima: not waited on)
+constexpr int kWaitVmem = 0x0F70;
 
 // Reserve `count` (0..3) consecutive slots per lane in an append counter with
 // one atomic per wave; returns this lane's first slot.  Every lane of the wave
@@ -174,8 +177,8 @@ __device__ inline void store_track(const Queue<R>& q, uint32_t i, const Trk<R>& 
   q.E[i] = t.E;
   q.id[i] = t.id;
   q.ev[i] = t.ev;
-  q.n[i] = t.n;
-  q.slab[i] = t.slab;
+  q.key[i] = t.key;
+  q.ns[i] = (t.n << kSlabBits) | (uint32_t)t.slab;
 }
 
 // position of the idx-th track of a queue with `home` tracks in the bottom
@@ -335,10 +338,57 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       const bool any_fin = __ballot(fin) != 0;
       // batch point: few lanes still stepping (or none, once the queue is drained)
       if (stepping <= (drained ? 0u : a.refill_below)) {
+        // (1) prefetch the records of the tracks that the lanes free after
+        // this batch will take; the loads are in flight during (2)
+        const bool want = (!has || fin) && !drained;
+        bool got = false;
+        int nsp = PHOTONS ? 0 : 1;
+        uint32_t nw = kDeadRecord;
+        Trk<R> nt;
+        if (__ballot(want) != 0) {
+          const uint32_t i = take_next(cursor, want, chunk_lo, chunk_hi);
+          got = want && i < nmine;
+          drained = __ballot(want && i >= nmine) != 0;
+          if (got) {
+            uint32_t idx = i, home = PHOTONS ? h0 : h1;
+            if (!PHOTONS && i >= n1) {
+              nsp = 2;
+              idx = i - n1;
+              home = h2;
+            }
+            const uint32_t pos = queue_pos(idx, home, a.cap);
+            const Queue<R> src = queue_view<R>(a.qbase, a.cap, cur, (uint32_t)nsp);
+            nw = src.ns[pos];
+            nt.ev = src.ev[pos];
+            nt.key = src.key[pos];
+            nt.x = src.x[pos];
+            nt.y = src.y[pos];
+            nt.z = src.z[pos];
+            nt.ux = src.ux[pos];
+            nt.uy = src.uy[pos];
+            nt.uz = src.uz[pos];
+            nt.E = src.E[pos];
+            nt.id = src.id[pos];
+          }
+        }
+        // (2) the interactions selected by the lanes' last steps, sampled
+        // together (one pass through each sampler the wave needs)
+        if (fin && o.pending) interact<KIND>(env, t, o);
+        // (3) the prefetched records have arrived; waiting here, before any
+        // store of this batch is issued, keeps later uses of their fields
+        // from waiting on those stores (vector memory completes in order)
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
+        bool take = got && nw != kDeadRecord;  // dead: refused secondary or unused chunk end
+        nt.slab = (int32_t)(nw & kSlabMask);
+        nt.n = nw >> kSlabBits;
+        // a record that would index outside the tallies or the slab stack
+        // is reported, never used
+        if (take && (nt.slab >= (int32_t)a.env.n_slabs || nt.ev >= a.max_events)) {
+          atomicOr(&ctl->error, kErrCorrupt);
+          take = false;
+        }
+        // (4) commit the finished visits: reserve first, then write
         if (any_fin) {
-          // the interactions selected by the lanes' last steps, sampled
-          // together (one pass through each sampler the wave needs)
-          if (fin && o.pending) interact<KIND>(env, t, o);
           // secondaries into the top regions (a step commits only if all of
           // its secondaries fit), then survivors or carried tracks
           uint32_t d[3];
@@ -358,6 +408,32 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           const bool pending = fin && o.nsec > 0;
           const bool commit = pending && fits;
           const bool apply_now = commit || (fin && held && o.nsec == 0);
+          const bool carry = pending && !commit;  // back to the state before the last step
+          const bool keep = fin && (carry ? before.slab >= 0 : t.slab >= 0);
+          // home slots (one counter per call: a wave may hold e- and e+)
+          uint32_t hs = 0;
+#pragma unroll
+          for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
+            const bool mine = keep && sp == q;
+            Take th;
+            const uint32_t hx = take_slots(&ctl->next_home[q], mine ? 1u : 0u, plan.chunk[q], hlo[q], hhi[q], th);
+            if (mine) hs = slot_of(th, hx);
+          }
+          if (apply_now) {
+            sink.apply(sp, t, o, before.E);
+            if (sp == 2) ++steps_p;
+            else ++steps_e;
+            made0 += d[0];
+            made1 += d[1];
+            made2 += d[2];
+          }
+          if (carry) ++carried_n;
+          if (fin && track_live) {
+            // net change of the event's live tracks: the visited track ends
+            // or stays, committed secondaries join
+            const int delta = (keep ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
+            if (delta != 0) atomicAdd(&a.live_ev[t.ev], delta);
+          }
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
             if (!d[q]) continue;
@@ -367,9 +443,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
               if (!(k < o.nsec && o.sec[k].sp == q)) continue;
-              const uint32_t s = slot_of(tk[q], x);
-              if (s < lim) {
-                const uint32_t p = (uint32_t)(a.cap - 1 - s);
+              const uint32_t sl = slot_of(tk[q], x);
+              if (sl < lim) {
+                const uint32_t ps = (uint32_t)(a.cap - 1 - sl);
                 if (commit) {
                   Trk<R> c;
                   c.x = t.x;
@@ -381,51 +457,27 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
                   c.E = o.sec[k].E;
                   c.id = o.sec[k].id;
                   c.ev = t.ev;
+                  c.key = t.key;
                   c.n = 0;
                   c.slab = o.slab;
-                  store_track(dq, p, c);
+                  store_track(dq, ps, c);
                 } else {
-                  dq.slab[p] = -1;  // refused: the next iteration skips this slot
+                  dq.ns[ps] = kDeadRecord;  // refused: the next iteration skips this slot
                 }
               }
               ++x;
             }
           }
-          if (apply_now) {
-            sink.apply(sp, t, o, before.E);
-            if (sp == 2) ++steps_p;
-            else ++steps_e;
-            made0 += d[0];
-            made1 += d[1];
-            made2 += d[2];
-          }
-          const bool carry = pending && !commit;  // back to the state before the last step
-          if (carry) ++carried_n;
-          const bool keep = fin && (carry ? before.slab >= 0 : t.slab >= 0);
-          // (one counter per wave_reserve call: a wave may hold e- and e+)
-#pragma unroll
-          for (int q = PHOTONS ? 0 : 1; q < (PHOTONS ? 1 : 3); ++q) {
-            const bool mine = keep && sp == q;
-            Take th;
-            const uint32_t hx = take_slots(&ctl->next_home[q], mine ? 1u : 0u, plan.chunk[q], hlo[q], hhi[q], th);
-            const uint32_t hs = slot_of(th, hx);
-            if (mine) {
-              const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
-              if (hs >= a.cap) {
-                atomicOr(&ctl->error, kErrOverflow);
-              } else {
-                if (carry) store_track(dq, hs, before);
-                else store_track(dq, hs, t);
-                if (q == 2) ++kept_b;
-                else ++kept_a;
-              }
+          if (keep) {
+            const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)sp);
+            if (hs >= a.cap) {
+              atomicOr(&ctl->error, kErrOverflow);
+            } else {
+              if (carry) store_track(dq, hs, before);
+              else store_track(dq, hs, t);
+              if (sp == 2) ++kept_b;
+              else ++kept_a;
             }
-          }
-          if (fin && track_live) {
-            // net change of the event's live tracks: the visited track ends
-            // or stays, committed secondaries join
-            const int delta = (keep ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
-            if (delta != 0) atomicAdd(&a.live_ev[t.ev], delta);
           }
           if (fin) {
             has = false;
@@ -435,48 +487,25 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
             o.pending = false;
           }
         }
-        // refill empty lanes; a lane that drew a dead slot (a refused
-        // secondary or an unused chunk end) draws again, a few times
-        for (int round = 0; round < 4 && !drained; ++round) {
-          const bool want = !has;
-          if (__ballot(want) == 0) break;
-          const uint32_t i = take_next(cursor, want, chunk_lo, chunk_hi);
-          if (want && i < nmine) {
-            sp = PHOTONS ? 0 : 1;
-            uint32_t idx = i, home = PHOTONS ? h0 : h1;
-            if (!PHOTONS && i >= n1) {
-              sp = 2;
-              idx = i - n1;
-              home = h2;
-            }
-            const uint32_t pos = queue_pos(idx, home, a.cap);
-            const Queue<R> src = queue_view<R>(a.qbase, a.cap, cur, (uint32_t)sp);
-            t.slab = src.slab[pos];
-            t.ev = t.slab >= 0 ? src.ev[pos] : 0u;
-            has = t.slab >= 0;  // slots of refused secondaries hold slab -1
-            // a record that would index outside the tallies or the slab
-            // stack is reported, never used
-            if (has && (t.slab >= (int32_t)a.env.n_slabs || t.ev >= a.max_events)) {
-              atomicOr(&ctl->error, kErrCorrupt);
-              has = false;
-            }
-            if (has) {
-              t.x = src.x[pos];
-              t.y = src.y[pos];
-              t.z = src.z[pos];
-              t.ux = src.ux[pos];
-              t.uy = src.uy[pos];
-              t.uz = src.uz[pos];
-              t.E = src.E[pos];
-              t.id = src.id[pos];
-              t.n = src.n[pos];
-              t.key = a.keys[t.ev];
-              visit_begin<KIND>(env, sp, t, vs);
-              if (sp == 2) ++visits_p;
-              else ++visits_e;
-            }
-          }
-          drained = __ballot(want && i >= nmine) != 0;
+        // (5) the freed lanes take their prefetched tracks
+        if (take) {
+          t.x = nt.x;
+          t.y = nt.y;
+          t.z = nt.z;
+          t.ux = nt.ux;
+          t.uy = nt.uy;
+          t.uz = nt.uz;
+          t.E = nt.E;
+          t.id = nt.id;
+          t.ev = nt.ev;
+          t.key = nt.key;
+          t.n = nt.n;
+          t.slab = nt.slab;
+          sp = nsp;
+          has = true;
+          visit_begin<KIND>(env, sp, t, vs);
+          if (sp == 2) ++visits_p;
+          else ++visits_e;
         }
         if (__ballot(has) == 0) {
           if (drained) break;
@@ -504,9 +533,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       const Queue<R> dq = queue_view<R>(a.qbase, a.cap, nxt, (uint32_t)q);
       const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
       const uint32_t send = shi[q] < lim ? shi[q] : lim;
-      for (uint32_t x = slo[q] + __lane_id(); x < send; x += 64) dq.slab[a.cap - 1 - x] = -1;
+      for (uint32_t x = slo[q] + __lane_id(); x < send; x += 64) dq.ns[a.cap - 1 - x] = kDeadRecord;
       for (uint32_t x = hlo[q] + __lane_id(); x < hhi[q]; x += 64) {
-        if (x < a.cap) dq.slab[x] = -1;
+        if (x < a.cap) dq.ns[x] = kDeadRecord;
       }
     }
     // statistics and per-launch progress
@@ -618,6 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
       t.E = r.E;
       t.id = r.id;
       t.ev = r.ev;
+      t.key = a.keys[r.ev];
       t.n = 0;
       t.slab = r.slab;
       store_track(queue_view<R>(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
