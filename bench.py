@@ -216,7 +216,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
             "launches": launches, "kernels": kern}
     return dict(geo=geo, cfg=cfg, prim=prim, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
-                track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep)
+                track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
+                deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
 
 
 def kernel_source_digest():
@@ -294,7 +295,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cal_10GeV_e-_x10k")
-    ap.add_argument("--capacity", type=int, default=8 << 20)
+    ap.add_argument("--capacity", type=int, default=1 << 25)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
     ap.add_argument("--steps-per-visit", type=int, default=16)
@@ -304,7 +305,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
-    ap.add_argument("--mixed-capacity", type=int, default=1 << 25)
+    ap.add_argument("--mixed-capacity", type=int, default=1 << 28)
+    ap.add_argument("--extra-capacity", type=int, default=1 << 26)
     ap.add_argument("--extra-workload", default="cal_mixed_1-100GeV_bz3.8_x10k",
                     help="also time this workload in both forms ('' to skip)")
     ap.add_argument("--serve-slots", type=int, default=4096)
@@ -355,7 +357,8 @@ def main():
         "config": {"workload": args.workload, "events": n, "primary": "e-", "energy_MeV": float(prim["ekin"][0]),
                    "geometry": "50 x (2.3 mm Pb + 5.7 mm lAr), 40x40 cm", "bz_tesla": cfg.bz_tesla,
                    "precision": "fp64", "track_steps_per_step": fp["track_steps"],
-                   "visits_per_step": fp["visits"],
+                   "visits_per_step": fp["visits"], "iterations": fp["iterations"],
+                   "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below},
         "roofline": fp["roofline"],
     }
@@ -363,13 +366,15 @@ def main():
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
                         "unit": "primaries/s", "ms_per_step": mx["ms_per_step"], "dtype": "f32 physics / f64 state",
-                        "track_steps_per_step": mx["track_steps"], "roofline": mx["roofline"]}
+                        "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
+                        "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
+                        "capacity": args.mixed_capacity, "roofline": mx["roofline"]}
         if not args.no_cpu:
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
     if args.extra_workload:
         out["other_workloads"] = {}
         for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
-            leg = transport_leg(E, I, args.extra_workload, prec, args.mixed_capacity, args)
+            leg = transport_leg(E, I, args.extra_workload, prec, args.extra_capacity, args)
             out["other_workloads"][f"{args.extra_workload}/{tag}"] = {
                 "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
                 "track_steps_per_step": leg["track_steps"],

@@ -151,6 +151,11 @@ __device__ inline Plan append_plan(const KArgs& a, uint32_t n0, uint32_t n1, uin
   return p;
 }
 
+// the interactions after which the parent track goes on
+__device__ inline bool parent_survives(uint32_t process) {
+  return process == kXCompton || process == kXMoller || process == kXBhabha || process == kXBrem;
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
@@ -340,7 +345,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       if (stepping <= (drained ? 0u : a.refill_below)) {
         // (1) prefetch the records of the tracks that the lanes free after
         // this batch will take; the loads are in flight during (2)
-        const bool want = (!has || fin) && !drained;
+        // a parent that survives its interaction keeps its lane and goes on
+        // stepping in this launch while it has steps left
+        const bool will_continue = fin && o.pending && parent_survives(o.process) && vs.steps < max_visit;
+        const bool want = (!has || (fin && !will_continue)) && !drained;
         bool got = false;
         int nsp = PHOTONS ? 0 : 1;
         uint32_t nw = kDeadRecord;
@@ -409,7 +417,9 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           const bool commit = pending && fits;
           const bool apply_now = commit || (fin && held && o.nsec == 0);
           const bool carry = pending && !commit;  // back to the state before the last step
-          const bool keep = fin && (carry ? before.slab >= 0 : t.slab >= 0);
+          const bool alive = fin && (carry ? before.slab >= 0 : t.slab >= 0);
+          const bool cont = alive && !carry && will_continue;  // stays in the lane
+          const bool keep = alive && !cont;                    // written to the next queue
           // home slots (one counter per call: a wave may hold e- and e+)
           uint32_t hs = 0;
 #pragma unroll
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
           if (fin && track_live) {
             // net change of the event's live tracks: the visited track ends
             // or stays, committed secondaries join
-            const int delta = (keep ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
+            const int delta = (alive ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
             if (delta != 0) atomicAdd(&a.live_ev[t.ev], delta);
           }
 #pragma unroll
@@ -480,12 +490,14 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
             }
           }
           if (fin) {
-            has = false;
+            has = cont;
             fin = false;
             held = false;
             o.nsec = 0;
             o.pending = false;
           }
+          // a continuing photon has a new energy and direction
+          if (PHOTONS && cont) photon_begin(env, t, vs.pc);
         }
         // (5) the freed lanes take their prefetched tracks
         if (take) {

@@ -199,7 +199,8 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     print(f"full size {name}", flush=True)
     geo, cfg, prim = I.workload(name)
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=8 << 20)  # as bench.py
+    # the capacities bench.py uses for these workloads
+    g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 25) if name == "cal_10GeV_e-_x10k" else (1 << 26))
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -248,7 +249,7 @@ def test_full_size_mixed_workload(E, oracle_mod):
     print("full size mixed cal_10GeV_e-_x100k", flush=True)
     geo, cfg, prim = I.workload("cal_10GeV_e-_x100k")
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 25, precision=E.MIXED)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 28, precision=E.MIXED)  # as bench.py
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -272,7 +273,7 @@ def test_full_size_mixed_species_workload_mixed_form(E, oracle_mod):
     print("full size mixed form cal_mixed_1-100GeV_bz3.8_x10k", flush=True)
     geo, cfg, prim = I.workload("cal_mixed_1-100GeV_bz3.8_x10k")
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=8 << 20, precision=E.MIXED)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 26, precision=E.MIXED)  # as bench.py
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(2)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -283,3 +284,16 @@ def test_full_size_mixed_species_workload_mixed_form(E, oracle_mod):
     ol = r["edep"].reshape(24, 50, 2).sum(axis=2)
     sig = np.sqrt(gl.var(axis=0) / 24 + ol.var(axis=0) / 24)
     assert np.all(np.abs(gl.mean(axis=0) - ol.mean(axis=0)) <= 3 * sig + 0.005 * ol.mean(axis=0) + 1e-9)
+
+
+def test_deferral_at_scale_gives_identical_results(E):
+    """Full-size showers through queues far too small for them (heavy
+    capacity deferral) give the same deposits as roomy queues."""
+    print("deferral at scale", flush=True)
+    geo, cfg, prim = I.workload("cal_10GeV_e-_x10k")
+    p = prim[:2000].copy()
+    a = run_gpu(E, geo, cfg, p, 2000, capacity=1 << 24)
+    b = run_gpu(E, geo, cfg, p, 2000, capacity=1 << 18)
+    assert b["stats"]["deferred"] > 0 and a["stats"]["deferred"] == 0
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    assert a["stats"]["steps"] == b["stats"]["steps"]
