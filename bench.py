@@ -74,8 +74,9 @@ def serving(E, I, args, precision):
     for p in range(P):
         rng = np.random.Generator(np.random.Philox(5 + p))
         pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
-    c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity, steps_per_launch=4,
-                      steps_per_visit=args.steps_per_visit, refill_below=args.refill_below, precision=precision)
+    c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity,
+                      steps_per_launch=args.serve_steps_per_launch, steps_per_visit=args.serve_steps_per_visit,
+                      refill_below=args.refill_below, precision=precision)
     srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
     n_each = max(1, args.serve_requests // P)
     total = n_each * P
@@ -116,6 +117,7 @@ def serving(E, I, args, precision):
     res = {"workload": "serving: requests of U{1..200} e-/e+/gamma tracks, lognormal(ln 5 GeV, 1) total, Bz 3.8 T",
            "precision": "fp64" if precision == E.FP64 else "mixed",
            "slots": args.serve_slots, "producers": P, "window": args.serve_window,
+           "iterations_per_poll": args.serve_steps_per_launch, "steps_per_visit": args.serve_steps_per_visit,
            "admit_cap_bytes": args.serve_admit_gib << 30,
            "saturated": {"requests": total, "primaries_per_s": prims / wall, "requests_per_s": sat_rps,
                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
@@ -309,13 +311,16 @@ def main():
     ap.add_argument("--extra-capacity", type=int, default=1 << 26)
     ap.add_argument("--extra-workload", default="cal_mixed_1-100GeV_bz3.8_x10k",
                     help="also time this workload in both forms ('' to skip)")
-    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=16384)
     ap.add_argument("--serve-producers", type=int, default=64)
     ap.add_argument("--serve-window", type=int, default=64, help="outstanding requests per producer (closed loop)")
     ap.add_argument("--serve-pool", type=int, default=64, help="distinct requests per producer (reused, new keys)")
-    ap.add_argument("--serve-requests", type=int, default=20480)
+    ap.add_argument("--serve-requests", type=int, default=40960)
     ap.add_argument("--serve-capacity", type=int, default=1 << 24)
     ap.add_argument("--serve-admit-gib", type=int, default=8)
+    ap.add_argument("--serve-steps-per-launch", type=int, default=1, help="iterations between host polls")
+    ap.add_argument("--serve-steps-per-visit", type=int, default=16)
+    ap.add_argument("--no-fp64-serve", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
@@ -379,8 +384,9 @@ def main():
                 "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
                 "track_steps_per_step": leg["track_steps"],
                 "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in leg["roofline"]["kernels"].items()}}
-    if not args.no_serve:
+    if not args.no_serve and not args.no_fp64_serve:
         out["serving"] = serving(E, I, args, E.FP64)
+    if not args.no_serve:
         if not args.no_mixed:
             out["serving_mixed"] = serving(E, I, args, E.MIXED)
     if not args.no_cpu:

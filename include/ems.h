@@ -190,8 +190,10 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo,
                       void* d_workspace, uint64_t bytes, void* hip_stream,
                       ems_ctx** out);
 
-/* Sets the RNG event key of tally rows [first_row, first_row + n). Results of
- * a row depend only on (seed, key, its primaries), never on the row. */
+/* Sets the RNG event key of tally rows [first_row, first_row + n) for the
+ * primaries enqueued from now on (each track carries its key). Results of a
+ * row depend only on (seed, key, its primaries), never on the row. Host
+ * only: no device work, no synchronisation. */
 ems_status ems_set_event_keys(ems_ctx* ctx, uint32_t first_row, uint32_t n,
                               const uint32_t* host_keys);
 
@@ -253,11 +255,14 @@ typedef struct {
 } ems_server_info;
 
 /* cfg->max_events is the number of tally slots (events in flight);
- * EMS_F_STEPLOG and EMS_F_PROFILE are not available in a server.  Workspace
- * and stream as for ems_create; the stream is used by the driver thread
- * only.  admit_cap_bytes bounds the estimated track-buffer bytes of admitted
- * requests (estimate: 152 B x (tracks + 0.1 per MeV of request energy)); a
- * request larger than the cap is admitted alone. */
+ * EMS_F_STEPLOG and EMS_F_PROFILE are not available in a server.  The
+ * server runs its context with EMS_F_EVENT_LIVE set: the workspace must hold
+ * ems_workspace_bytes of cfg with that flag (it adds the row lists and the
+ * result staging area); EMS_E_CAPACITY otherwise.  Stream as for
+ * ems_create; it is used by the driver thread only.  admit_cap_bytes bounds
+ * the estimated track-buffer bytes of admitted requests (estimate: 2 x
+ * record bytes x (tracks + 0.1 per MeV of request energy + 1)); a request
+ * larger than the cap is admitted alone. */
 ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, void* d_workspace,
                              uint64_t bytes, void* hip_stream, uint64_t admit_cap_bytes,
                              ems_server** out);

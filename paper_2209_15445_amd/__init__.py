@@ -311,7 +311,9 @@ class Server:
         self.config = config
         self._gh = _GeoHolder(geometry)
         self.n_slabs = self._gh.n_slabs
-        nbytes = workspace_bytes(config, geometry)
+        sized = Config.from_buffer_copy(config)
+        sized.flags |= F_EVENT_LIVE  # the server's context keeps per-event live counters
+        nbytes = workspace_bytes(sized, geometry)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         ptr = (self.workspace.data_ptr() + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.Stream()

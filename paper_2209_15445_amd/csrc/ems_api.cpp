@@ -106,10 +106,12 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.zp = take((g->n_slabs + 1) * 8ull);
   L.smat = take(g->n_slabs * 4ull);
   L.mat = take(g->n_materials * sizeof(MatRT));
-  L.keys = take(c->max_events * 4ull);
   L.edep = take((uint64_t)c->max_events * g->n_slabs * 8);
   L.ledger = take((uint64_t)c->max_events * sizeof(LedgerDev));
   L.live = take((uint64_t)c->max_events * 4);
+  const bool server = (c->flags & EMS_F_EVENT_LIVE) != 0;
+  L.rows = take(server ? (uint64_t)c->max_events * 4 : 0);
+  L.gather = take(server ? (uint64_t)c->max_events * (g->n_slabs * 8ull + sizeof(LedgerDev)) : 0);
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
   L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
@@ -168,9 +170,10 @@ int32_t locate(const double* z, uint32_t n, double zz, double uz) {
   return (int32_t)lo;
 }
 
-// validate and convert primaries; ids are running indices per row
+// validate and convert primaries; ids are running indices per row, keys
+// the rows' event keys
 ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary* p, uint64_t n,
-                   std::vector<uint64_t>& row_count, std::vector<InjRec>& out) {
+                   std::vector<uint64_t>& row_count, const std::vector<uint32_t>& keys, std::vector<InjRec>& out) {
   for (uint64_t i = 0; i < n; ++i) {
     const ems_primary& q = p[i];
     const double d2 = q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2];
@@ -195,7 +198,7 @@ ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary
     r.sp = q.species;
     r.slab = locate(g.z_mm, g.n_slabs, r.z, r.uz);
     r.id = row_count[q.event]++;
-    r.pad = 0;
+    r.key = keys[q.event];
   }
   return EMS_OK;
 }
@@ -313,7 +316,6 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.ctl = reinterpret_cast<Ctl*>(c->ws + L.ctl);
   a.edep = reinterpret_cast<double*>(c->ws + L.edep);
   a.ledger = reinterpret_cast<LedgerDev*>(c->ws + L.ledger);
-  a.keys = reinterpret_cast<const uint32_t*>(c->ws + L.keys);
   a.tab_g = c->ws + L.tab;
   a.tab_l = c->ws + L.tab + gbytes;
   a.zplane = reinterpret_cast<const double*>(c->ws + L.zp);
@@ -358,8 +360,14 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   } else {
     pack_tables<double>(c->ts, geo->n_materials, packed);
   }
-  std::vector<uint32_t> keys(cfg->max_events);
-  for (uint32_t i = 0; i < cfg->max_events; ++i) keys[i] = i;
+  c->keys.resize(cfg->max_events);
+  for (uint32_t i = 0; i < cfg->max_events; ++i) c->keys[i] = i;
+  if (cfg->flags & EMS_F_EVENT_LIVE) {
+    const uint64_t gb = (uint64_t)cfg->max_events * (geo->n_slabs * 8ull + sizeof(LedgerDev));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_rows), cfg->max_events * 4ull) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->pin_gather), gb) != hipSuccess)
+      return bad(fail(EMS_E_DEVICE, "pinned host allocation failed"));
+  }
   hipStream_t s = c->stream;
   bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
@@ -367,7 +375,6 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
-            hipMemcpyAsync(c->ws + L.keys, keys.data(), keys.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.edep, 0, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
@@ -385,6 +392,8 @@ ems_status ems_destroy(ems_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->pin_inj) (void)hipHostFree(c->pin_inj);
   if (c->pin_ctl) (void)hipHostFree(c->pin_ctl);
+  if (c->pin_rows) (void)hipHostFree(c->pin_rows);
+  if (c->pin_gather) (void)hipHostFree(c->pin_gather);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->evk) (void)hipEventDestroy(e);
@@ -396,8 +405,7 @@ ems_status ems_set_event_keys(ems_ctx* c, uint32_t first, uint32_t n, const uint
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   if (!keys || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
-  HIPCHK(c, hipMemcpyAsync(c->ws + c->L.keys + first * 4ull, keys, n * 4ull, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::copy(keys, keys + n, c->keys.begin() + first);  // applied to tracks enqueued from now on
   return EMS_OK;
 }
 
@@ -556,14 +564,16 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
   env.slab_mat = geo->material;
   env.mat = rt.data();
   std::vector<uint64_t> rows(n_events, 0);
+  std::vector<uint32_t> row_keys(n_events);
+  for (uint32_t e = 0; e < n_events; ++e) row_keys[e] = keys ? keys[e] : e;
   std::vector<InjRec> recs;
-  ems_status st = prepare(*geo, n_events, prim, n, rows, recs);
+  ems_status st = prepare(*geo, n_events, prim, n, rows, row_keys, recs);
   if (st) return st;
   memset(edep, 0, sizeof(double) * n_events * geo->n_slabs);
   memset(ledger, 0, sizeof(ems_ledger) * n_events);
   std::vector<Trk<R>> cur[3], nxt[3];
   for (const InjRec& r : recs) {
-    Trk<R> t{r.x, r.y, r.z, (R)r.ux, (R)r.uy, (R)r.uz, r.E, r.id, r.ev, keys ? keys[r.ev] : r.ev, 0, r.slab};
+    Trk<R> t{r.x, r.y, r.z, (R)r.ux, (R)r.uy, (R)r.uz, r.E, r.id, r.ev, r.key, 0, r.slab};
     cur[r.sp].push_back(t);
   }
   struct HostSink {
@@ -654,7 +664,7 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
     if (c->pending[s] + add[s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
   std::vector<uint64_t> rows = c->row_count;
   std::vector<InjRec> recs;
-  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, recs);
+  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, c->keys, recs);
   if (st) return st;
   for (uint64_t done = 0; done < n; done += kInjectChunk) {
     const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
@@ -727,12 +737,42 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
   return EMS_OK;
 }
 
-ems_status rt_zero_rows(ems_ctx* c, uint32_t first, uint32_t n) {
-  const uint64_t row = c->geo.n_slabs * 8ull;
-  HIPCHK(c, hipMemsetAsync(c->ws + c->L.edep + first * row, 0, n * row, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->ws + c->L.ledger + first * sizeof(LedgerDev), 0, n * sizeof(LedgerDev), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->ws + c->L.live + first * 4ull, 0, n * 4ull, c->stream));
-  for (uint32_t i = 0; i < n; ++i) c->row_count[first + i] = 0;
+ems_status rt_reset_rows(ems_ctx* c, const uint32_t* rows, uint32_t n) {
+  if (!c->pin_rows) return fail(EMS_E_STATE, "row lists need EMS_F_EVENT_LIVE");
+  if (n == 0) return EMS_OK;
+  for (uint32_t i = 0; i < n; ++i)
+    if (rows[i] >= c->cfg.max_events) return fail(EMS_E_INVALID, "row out of range");
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // pinned row list is free again
+  memcpy(c->pin_rows, rows, n * 4ull);
+  uint32_t* d = reinterpret_cast<uint32_t*>(c->ws + c->L.rows);
+  HIPCHK(c, hipMemcpyAsync(d, c->pin_rows, n * 4ull, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_reset_rows(c->args, d, n, c->stream));
+  for (uint32_t i = 0; i < n; ++i) c->row_count[rows[i]] = 0;
+  return EMS_OK;
+}
+
+ems_status rt_gather_rows(ems_ctx* c, const uint32_t* rows, uint32_t n, double* edep, ems_ledger* ledger) {
+  if (!c->pin_rows) return fail(EMS_E_STATE, "row lists need EMS_F_EVENT_LIVE");
+  if (n == 0) return EMS_OK;
+  for (uint32_t i = 0; i < n; ++i)
+    if (rows[i] >= c->cfg.max_events) return fail(EMS_E_INVALID, "row out of range");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(c->pin_rows, rows, n * 4ull);
+  uint32_t* d = reinterpret_cast<uint32_t*>(c->ws + c->L.rows);
+  const size_t stride = c->geo.n_slabs * 8ull + sizeof(LedgerDev);
+  HIPCHK(c, hipMemcpyAsync(d, c->pin_rows, n * 4ull, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_gather_rows(c->args, d, n, c->ws + c->L.gather, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->pin_gather, c->ws + c->L.gather, n * stride, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (uint32_t i = 0; i < n; ++i) {
+    const char* src = c->pin_gather + i * stride;
+    double* e = edep + (size_t)i * c->geo.n_slabs;
+    memcpy(e, src, c->geo.n_slabs * 8ull);
+    memcpy(&ledger[i], src + c->geo.n_slabs * 8ull, sizeof(LedgerDev));
+    double sum = 0.0;
+    for (uint32_t k = 0; k < c->geo.n_slabs; ++k) sum += e[k];
+    ledger[i].edep = sum;
+  }
   return EMS_OK;
 }
 

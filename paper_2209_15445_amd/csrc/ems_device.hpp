@@ -79,13 +79,14 @@ struct Ctl {
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
-// Track prepared on the host for injection (slab located, direction unit).
+// Track prepared on the host for injection (slab located, direction unit,
+// RNG event key of its row).
 struct InjRec {
   double x, y, z, ux, uy, uz, E;
   uint64_t id;
   uint32_t ev, sp;
   int32_t slab;
-  uint32_t pad;
+  uint32_t key;
 };
 
 // Per-event ledger as laid out in the public header.
@@ -111,7 +112,6 @@ struct KArgs {
   Ctl* ctl;
   double* edep;        // [rows][n_slabs]
   LedgerDev* ledger;   // [rows]
-  const uint32_t* keys;
   const void* tab_g;   // photon table block [mat][3][nodes] (double or float)
   const void* tab_l;   // lepton table block [mat][10][nodes]
   const double* zplane;

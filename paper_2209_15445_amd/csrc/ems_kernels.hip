@@ -659,12 +659,42 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
       t.E = r.E;
       t.id = r.id;
       t.ev = r.ev;
-      t.key = a.keys[r.ev];
+      t.key = r.key;
       t.n = 0;
       t.slab = r.slab;
       store_track(queue_view<R>(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
       if (a.flags & kFlagEventLive) atomicAdd(&a.live_ev[r.ev], 1);
     }
+  }
+}
+
+// Zero the deposits, ledger and live counter of the listed rows (one block
+// per row, grid-stride over the list).
+__global__ __launch_bounds__(kBlock) void k_reset_rows(KArgs a, const uint32_t* rows, uint32_t n) {
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint32_t r = rows[i];
+    if (r >= a.max_events) continue;
+    double* e = a.edep + (size_t)r * a.env.n_slabs;
+    for (uint32_t k = threadIdx.x; k < a.env.n_slabs; k += kBlock) e[k] = 0.0;
+    unsigned long long* l = reinterpret_cast<unsigned long long*>(a.ledger + r);
+    for (uint32_t k = threadIdx.x; k < sizeof(LedgerDev) / 8; k += kBlock) l[k] = 0ull;
+    if (threadIdx.x == 0) a.live_ev[r] = 0;
+  }
+}
+
+// Copy the deposits and ledger of the listed rows to a compact staging area:
+// entry i holds n_slabs doubles, then the row's ledger.
+__global__ __launch_bounds__(kBlock) void k_gather_rows(KArgs a, const uint32_t* rows, uint32_t n, char* out) {
+  const size_t stride = (size_t)a.env.n_slabs * 8 + sizeof(LedgerDev);
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint32_t r = rows[i];
+    if (r >= a.max_events) continue;
+    double* o = reinterpret_cast<double*>(out + i * stride);
+    const double* e = a.edep + (size_t)r * a.env.n_slabs;
+    for (uint32_t k = threadIdx.x; k < a.env.n_slabs; k += kBlock) o[k] = e[k];
+    unsigned long long* lo = reinterpret_cast<unsigned long long*>(o + a.env.n_slabs);
+    const unsigned long long* li = reinterpret_cast<const unsigned long long*>(a.ledger + r);
+    for (uint32_t k = threadIdx.x; k < sizeof(LedgerDev) / 8; k += kBlock) lo[k] = li[k];
   }
 }
 
@@ -698,6 +728,16 @@ hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStrea
   const uint32_t blocks = n == 0 ? 1 : (want < 4096 ? want : 4096);
   if (a.precision) hipLaunchKernelGGL(k_inject<float>, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
   else hipLaunchKernelGGL(k_inject<double>, dim3(blocks), dim3(kBlock), 0, s, a, rec, n);
+  return hipGetLastError();
+}
+hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s) {
+  const uint32_t blocks = n == 0 ? 1 : (n < 1024 ? n : 1024);
+  hipLaunchKernelGGL(k_reset_rows, dim3(blocks), dim3(kBlock), 0, s, a, rows, n);
+  return hipGetLastError();
+}
+hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s) {
+  const uint32_t blocks = n == 0 ? 1 : (n < 1024 ? n : 1024);
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks), dim3(kBlock), 0, s, a, rows, n, out);
   return hipGetLastError();
 }
 hipError_t launch_census(const KArgs& a, hipStream_t s) {

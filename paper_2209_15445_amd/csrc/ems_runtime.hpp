@@ -14,11 +14,13 @@ namespace ems {
 hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s);
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
 hipError_t launch_census(const KArgs& a, hipStream_t s);
+hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s);
+hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s);
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
-  uint64_t ctl, tab, zp, smat, mat, keys, edep, ledger, live, profile, log, inj, queues, total;
+  uint64_t ctl, tab, zp, smat, mat, edep, ledger, live, rows, gather, profile, log, inj, queues, total;
   uint64_t cap;
 };
 
@@ -49,9 +51,12 @@ struct ems_ctx {
   KArgs args{};
   uint32_t blocks_g = 0, blocks_l = 0;
   std::vector<uint64_t> row_count;
+  std::vector<uint32_t> keys;  // RNG event key per row (host; travels with each injected track)
   uint64_t pending[3] = {0, 0, 0};
   InjRec* pin_inj = nullptr;
   Ctl* pin_ctl = nullptr;
+  uint32_t* pin_rows = nullptr;  // row lists (server)
+  char* pin_gather = nullptr;    // gathered result rows (server)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> evk;  // per-launch events (EMS_F_KERNEL_TIMING)
   bool failed = false;
@@ -74,8 +79,12 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n);
 // K iterations (after a census of the injected tracks); the status block is
 // left in c->pin_ctl; queue errors are returned as status codes
 ems_status rt_chunk(ems_ctx* c, uint32_t K);
-// zero the deposits, ledgers and live counters of rows [first, first + n)
-ems_status rt_zero_rows(ems_ctx* c, uint32_t first, uint32_t n);
+// zero the deposits, ledgers and live counters of the listed rows and
+// restart their track ids (server; needs EMS_F_EVENT_LIVE)
+ems_status rt_reset_rows(ems_ctx* c, const uint32_t* rows, uint32_t n);
+// copy the deposits and ledgers of the listed rows to the host:
+// edep[n][n_slabs], ledger[n] (server; needs EMS_F_EVENT_LIVE)
+ems_status rt_gather_rows(ems_ctx* c, const uint32_t* rows, uint32_t n, double* edep, ems_ledger* ledger);
 // copy the live-track counters of all rows to host
 ems_status rt_read_live(ems_ctx* c, int32_t* host);
 }  // namespace ems

@@ -117,13 +117,21 @@ void ems_server::run() {
       }
       if (in_flight == 0) continue;
     }
-    // inject the admitted events into their slots (driver thread only)
-    for (const std::shared_ptr<Request>& r : admit) {
-      std::vector<ems_primary> p = r->tracks;
-      for (ems_primary& q : p) q.event = (uint32_t)r->slot;
-      ems_status st = rt_zero_rows(ctx, (uint32_t)r->slot, 1);
-      if (!st) st = ems_set_event_keys(ctx, (uint32_t)r->slot, 1, &r->key);
-      for (int s = 0; s < 3; ++s) ctx->pending[s] = 0;  // room was checked above
+    // inject all admitted events into their slots with one row reset and
+    // one enqueue (driver thread only)
+    if (!admit.empty()) {
+      std::vector<uint32_t> rows;
+      std::vector<ems_primary> p;
+      for (const std::shared_ptr<Request>& r : admit) {
+        rows.push_back((uint32_t)r->slot);
+        ctx->keys[r->slot] = r->key;
+        for (ems_primary q : r->tracks) {
+          q.event = (uint32_t)r->slot;
+          p.push_back(q);
+        }
+      }
+      ems_status st = rt_reset_rows(ctx, rows.data(), (uint32_t)rows.size());
+      for (int s2 = 0; s2 < 3; ++s2) ctx->pending[s2] = 0;  // room was checked above
       if (!st) st = rt_enqueue(ctx, p.data(), p.size());
       if (st) {
         fail_all(std::string("injection failed: ") + ems_last_error());
@@ -135,12 +143,12 @@ void ems_server::run() {
       fail_all(std::string("device loop failed: ") + ems_last_error());
       return;
     }
-    for (int s = 0; s < 3; ++s) occupied[s] = ctx->pin_ctl->n_home[s] + ctx->pin_ctl->n_sec[s];
+    for (int s2 = 0; s2 < 3; ++s2) occupied[s2] = ctx->pin_ctl->n_home[s2] + ctx->pin_ctl->n_sec[s2];
     if (rt_read_live(ctx, live.data())) {
       fail_all(std::string("live counters unreadable: ") + ems_last_error());
       return;
     }
-    // events whose last track is gone
+    // events whose last track is gone: their rows come back in one transfer
     std::vector<std::shared_ptr<Request>> finished;
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -148,12 +156,20 @@ void ems_server::run() {
       for (size_t i = 0; i < slots.size(); ++i)
         if (slots[i] && live[i] == 0) finished.push_back(slots[i]);
     }
-    for (const std::shared_ptr<Request>& r : finished) {
-      r->edep.resize(ctx->geo.n_slabs);
-      if (ems_read_edep(ctx, (uint32_t)r->slot, 1, r->edep.data()) ||
-          ems_read_ledger(ctx, (uint32_t)r->slot, 1, &r->ledger)) {
+    if (!finished.empty()) {
+      const uint32_t nf = (uint32_t)finished.size();
+      std::vector<uint32_t> rows(nf);
+      for (uint32_t i = 0; i < nf; ++i) rows[i] = (uint32_t)finished[i]->slot;
+      std::vector<double> edep((size_t)nf * ctx->geo.n_slabs);
+      std::vector<ems_ledger> led(nf);
+      if (rt_gather_rows(ctx, rows.data(), nf, edep.data(), led.data())) {
         fail_all(std::string("result read-back failed: ") + ems_last_error());
         return;
+      }
+      for (uint32_t i = 0; i < nf; ++i) {
+        finished[i]->edep.assign(edep.begin() + (size_t)i * ctx->geo.n_slabs,
+                                 edep.begin() + (size_t)(i + 1) * ctx->geo.n_slabs);
+        finished[i]->ledger = led[i];
       }
     }
     if (!finished.empty()) {
