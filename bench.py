@@ -217,7 +217,24 @@ def transport_leg(E, I, workload, precision, capacity, args):
             "frac": d["frac"], "traffic": traffic_for(dom, args.workload if precision == E.FP64 else None),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
             "launches": launches, "kernels": kern}
+    # the same steps replayed from captured graphs (no per-kernel events)
+    value_graph = None
+    if args.graph_check:
+        cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
+                           launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit,
+                           refill_below=args.refill_below, precision=precision)
+        eng = E.Transport(cg, geo)
+        one_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step()
+        torch.cuda.synchronize()
+        value_graph = n * args.steps / (time.perf_counter() - t0)
+        assert eng.stats()["graph_launches"] > 0
+        eng.close()
     return dict(geo=geo, cfg=cfg, prim=prim, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+                value_graph=value_graph,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
 
@@ -305,6 +322,8 @@ def main():
     ap.add_argument("--cpu-events", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--graph-check", type=int, default=1,
+                    help="also time the same steps replayed from captured graphs (no per-kernel events)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
     ap.add_argument("--mixed-capacity", type=int, default=1 << 28)
@@ -366,11 +385,13 @@ def main():
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below},
         "roofline": fp["roofline"],
+        "value_graph_replay": fp["value_graph"],
     }
     if not args.no_mixed:
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
                         "unit": "primaries/s", "ms_per_step": mx["ms_per_step"], "dtype": "f32 physics / f64 state",
+                        "value_graph_replay": mx["value_graph"],
                         "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
                         "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
                         "capacity": args.mixed_capacity, "roofline": mx["roofline"]}

@@ -66,8 +66,14 @@ enum {
   EMS_F_PROFILE = 1u << 2,     /* live tracks per species per iteration     */
   EMS_F_EVENT_LIVE = 1u << 3,  /* per-event live-track counters (set by the
                                   offload server to detect finished events) */
-  EMS_F_KERNEL_TIMING = 1u << 4 /* a HIP event after every launch: per-kernel
-                                  device time in ems_run_stats.kernel_ms   */
+  EMS_F_KERNEL_TIMING = 1u << 4, /* a HIP event after every launch: per-kernel
+                                  device time in ems_run_stats.kernel_ms;
+                                  the chunk's kernels are then launched
+                                  directly, not replayed from a graph      */
+  EMS_F_NO_GRAPH = 1u << 5      /* launch each chunk's kernels directly
+                                  instead of replaying a captured hipGraph
+                                  of steps_per_launch iterations (always
+                                  direct on the null stream)               */
 };
 
 typedef struct {
@@ -173,6 +179,7 @@ typedef struct {
   double kernel_ms[2];           /* with EMS_F_KERNEL_TIMING: device time of
                                     the photon and of the e-/e+ launches,
                                     event to event on the bound stream      */
+  uint64_t graph_launches;       /* chunks replayed from a captured hipGraph */
 } ems_run_stats;
 
 typedef struct ems_ctx ems_ctx;

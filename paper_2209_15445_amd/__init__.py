@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libems.so")
 ABI_VERSION = 1
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
-F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING = 1, 2, 4, 8, 16
+F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
 
 
 class EmsError(RuntimeError):
@@ -51,7 +51,8 @@ class RunStats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("steps", C.c_uint64 * 3), ("created", C.c_uint64 * 3),
                 ("deferred", C.c_uint64), ("launches", C.c_uint64), ("peak_live", C.c_uint32 * 3),
                 ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double),
-                ("visits", C.c_uint64 * 3), ("made_by", C.c_uint64 * 2), ("kernel_ms", C.c_double * 2)]
+                ("visits", C.c_uint64 * 3), ("made_by", C.c_uint64 * 2), ("kernel_ms", C.c_double * 2),
+                ("graph_launches", C.c_uint64)]
 
 
 class ServerInfo(C.Structure):
@@ -217,7 +218,9 @@ class Transport:
     """One transport context on the current HIP device.
 
     The workspace is a torch uint8 tensor on the device; the stream is the
-    given torch stream (default: the current stream)."""
+    given torch stream, by default a stream of its own (default priority):
+    chunks of iterations are replayed as captured graphs, which the null
+    stream does not allow."""
 
     def __init__(self, config, geometry, stream=None, device="cuda"):
         import torch
@@ -230,7 +233,7 @@ class Transport:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         h = C.c_void_p()
         _check(lib().ems_create(C.byref(config), C.byref(self._gh.g), C.c_void_p(self._ws_ptr), nbytes,
                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -240,6 +243,7 @@ class Transport:
         if getattr(self, "_h", None):
             lib().ems_destroy(self._h)
             self._h = None
+        self.workspace = None  # device memory back to the allocator
 
     def __del__(self):
         try:
@@ -295,7 +299,7 @@ class Transport:
         return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
                     run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits),
-                    made_by=list(s.made_by), kernel_ms=list(s.kernel_ms))
+                    made_by=list(s.made_by), kernel_ms=list(s.kernel_ms), graph_launches=s.graph_launches)
 
 
 class Server:
@@ -327,6 +331,7 @@ class Server:
         if getattr(self, "_h", None):
             lib().ems_server_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:

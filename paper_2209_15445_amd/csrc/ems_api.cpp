@@ -397,6 +397,7 @@ ems_status ems_destroy(ems_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->evk) (void)hipEventDestroy(e);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   delete c;
   return EMS_OK;
 }
@@ -679,6 +680,39 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   return EMS_OK;
 }
 
+// The kernels of one chunk: census, then K iterations (photon launch, e-/e+
+// launch), with a HIP event after every launch when timing (direct
+// launches only: events recorded inside a graph are not timeable here).
+// Returns the first error.
+static hipError_t enqueue_chunk(ems_ctx* c, uint32_t K, bool timing) {
+  hipError_t e = launch_census(c->args, c->stream);
+  if (e == hipSuccess && timing) e = hipEventRecord(c->evk[0], c->stream);
+  for (uint32_t k = 0; k < K && e == hipSuccess; ++k) {
+    e = launch_visit(c->args, true, c->blocks_g, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[2 * k + 1], c->stream);
+    if (e == hipSuccess) e = launch_visit(c->args, false, c->blocks_l, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[2 * k + 2], c->stream);
+  }
+  return e;
+}
+
+// Capture one chunk of K iterations as a graph.  The kernels read every
+// changing quantity from the device control block, so one graph serves all
+// chunks; it holds kernel nodes only (no memset or event nodes).
+static hipError_t capture_chunk(ems_ctx* c, uint32_t K) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  const hipError_t el = enqueue_chunk(c, K, false);
+  e = hipStreamEndCapture(c->stream, &g);
+  if (el != hipSuccess) e = el;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e == hipSuccess) c->graph_k = K;
+  else c->graph = nullptr;
+  return e;
+}
+
 ems_status rt_chunk(ems_ctx* c, uint32_t K) {
   const bool timing = (c->cfg.flags & EMS_F_KERNEL_TIMING) != 0;
   while (timing && c->evk.size() < 2 * (size_t)K + 1) {
@@ -686,14 +720,23 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
     HIPCHK(c, hipEventCreate(&e));
     c->evk.push_back(e);
   }
-  HIPCHK(c, launch_census(c->args, c->stream));
+  bool graph = !timing && !(c->cfg.flags & EMS_F_NO_GRAPH) && c->stream != nullptr && !c->graph_off;
+  if (graph && c->graph && c->graph_k != K) {
+    HIPCHK(c, hipGraphExecDestroy(c->graph));
+    c->graph = nullptr;
+  }
+  if (graph && !c->graph && capture_chunk(c, K) != hipSuccess) {
+    // capture not available here: launch directly from now on
+    (void)hipGetLastError();
+    c->graph_off = true;
+    graph = false;
+  }
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-  if (timing) HIPCHK(c, hipEventRecord(c->evk[0], c->stream));
-  for (uint32_t k = 0; k < K; ++k) {
-    HIPCHK(c, launch_visit(c->args, true, c->blocks_g, c->stream));
-    if (timing) HIPCHK(c, hipEventRecord(c->evk[2 * k + 1], c->stream));
-    HIPCHK(c, launch_visit(c->args, false, c->blocks_l, c->stream));
-    if (timing) HIPCHK(c, hipEventRecord(c->evk[2 * k + 2], c->stream));
+  if (graph) {
+    HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    c->stats.graph_launches += 1;
+  } else {
+    HIPCHK(c, enqueue_chunk(c, K, timing));
   }
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));

@@ -59,6 +59,9 @@ struct ems_ctx {
   char* pin_gather = nullptr;    // gathered result rows (server)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> evk;  // per-launch events (EMS_F_KERNEL_TIMING)
+  hipGraphExec_t graph = nullptr;  // captured chunk of graph_k iterations
+  uint32_t graph_k = 0;
+  bool graph_off = false;  // capture failed once: direct launches
   bool failed = false;
   ems_run_stats stats{};
 };

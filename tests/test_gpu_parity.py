@@ -297,3 +297,28 @@ def test_deferral_at_scale_gives_identical_results(E):
     assert b["stats"]["deferred"] > 0 and a["stats"]["deferred"] == 0
     assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
     assert a["stats"]["steps"] == b["stats"]["steps"]
+
+
+def test_graph_replays_match_direct_launches(E):
+    """Chunks replayed from a captured hipGraph give the direct launches'
+    results on every replay, with eager work between the replays."""
+    print("graph replays", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    ref = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER | E.F_NO_GRAPH)
+    assert ref["stats"]["graph_launches"] == 0
+    c = E.make_config(cfg, 32, track_capacity=1 << 20, flags=E.F_FULL_LEDGER, steps_per_launch=4)
+    t = E.Transport(c, geo)
+    for rep in range(3):
+        t.reset()
+        t.enqueue(prim)
+        t.run()
+        s = t.stats()
+        assert s["graph_launches"] > 0 and s["step_kernel_ms"] > 0.0
+        assert np.allclose(t.edep(), ref["edep"], rtol=1e-12, atol=1e-12), rep
+        L = t.ledger()
+        for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+            assert np.array_equal(L[f], ref["ledger"][f]), (rep, f)
+        # eager device work between replays
+        import torch
+        torch.ones(1 << 20, device="cuda").sum().item()
+    t.close()
