@@ -203,11 +203,28 @@ struct DevSink {
   uint32_t n_slabs;
   bool full, logging;
   uint32_t applied;  // steps applied by this lane in the current visit
+  // deposits of consecutive steps into the same (event, slab) add up in the
+  // lane and reach the tally with one atomic when the cell changes or the
+  // lane finishes (summation order of FP64 atomics is unordered anyway)
+  size_t acc_cell;
+  double acc_dep;
+
+  __device__ void flush() {
+    if (acc_dep != 0.0) atomicAdd(&edep[acc_cell], acc_dep);
+    acc_dep = 0.0;
+  }
 
   template <class R>
   __device__ void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e_before) {
     ++applied;
-    if (o.dep != 0.0) atomicAdd(&edep[(size_t)t.ev * n_slabs + o.slab], o.dep);
+    if (o.dep != 0.0) {
+      const size_t cell = (size_t)t.ev * n_slabs + o.slab;
+      if (cell != acc_cell) {
+        flush();
+        acc_cell = cell;
+      }
+      acc_dep += o.dep;
+    }
     LedgerDev& L = ledger[t.ev];
     if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
     if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
@@ -321,7 +338,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     // wave-private append ranges (uniform): secondaries and home, per species
     uint32_t slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, hlo[3] = {0, 0, 0}, hhi[3] = {0, 0, 0};
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
-                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u};
+                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u, 0, 0.0};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
     const bool track_live = (a.flags & kFlagEventLive) != 0;
 
@@ -539,6 +556,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       }
     }
 
+    sink.flush();
     // unused ends of the wave's append ranges hold no track
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
