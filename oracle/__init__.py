@@ -94,6 +94,8 @@ def lib():
         L.or_run.argtypes = [vp, vp, C.c_uint64, C.c_uint32, vp, vp, vp, vp, C.c_uint64,
                              C.POINTER(C.c_uint64), vp, C.c_uint32, C.POINTER(C.c_uint32), C.c_int]
         L.or_run.restype = C.c_int
+        L.or_run_exits.argtypes = list(L.or_run.argtypes) + [vp, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.or_run_exits.restype = C.c_int
         L.or_table_count.argtypes = [vp]
         L.or_table_count.restype = C.c_uint64
         L.or_export_tables.argtypes = [vp, vp, C.c_uint64]
@@ -205,9 +207,10 @@ class Oracle:
 
     # -- transport ------------------------------------------------------
     def run(self, prim: np.ndarray, n_events: int | None = None, event_keys=None,
-            log_cap: int = 0, profile_cap: int = 0, stack_order: int = 0):
+            log_cap: int = 0, profile_cap: int = 0, stack_order: int = 0, exit_cap: int = 0):
         """Transport the primaries; returns a dict with edep [n_events, n_slabs],
-        ledger (structured array), and optionally the step log / profile."""
+        ledger (structured array), and optionally the step log / profile and
+        the tracks leaving the stack (primary-record layout)."""
         prim = np.ascontiguousarray(prim)
         if n_events is None:
             n_events = int(prim["event"].max()) + 1 if len(prim) else 0
@@ -220,16 +223,23 @@ class Oracle:
         log_n = C.c_uint64(0)
         prof = np.zeros((profile_cap, 3), dtype=np.uint64) if profile_cap else None
         prof_len = C.c_uint32(0)
-        rc = lib().or_run(self._h, prim.ctypes.data_as(C.c_void_p), len(prim), n_events,
-                          None if keys is None else keys.ctypes.data_as(C.c_void_p),
-                          edep.ctypes.data_as(C.c_void_p), ledger.ctypes.data_as(C.c_void_p),
-                          None if log is None else log.ctypes.data_as(C.c_void_p), log_cap,
-                          C.byref(log_n),
-                          None if prof is None else prof.ctypes.data_as(C.c_void_p), profile_cap,
-                          C.byref(prof_len), stack_order)
+        exits = np.zeros(exit_cap, dtype=prim.dtype) if exit_cap else None
+        exits_n = C.c_uint64(0)
+        rc = lib().or_run_exits(self._h, prim.ctypes.data_as(C.c_void_p), len(prim), n_events,
+                                None if keys is None else keys.ctypes.data_as(C.c_void_p),
+                                edep.ctypes.data_as(C.c_void_p), ledger.ctypes.data_as(C.c_void_p),
+                                None if log is None else log.ctypes.data_as(C.c_void_p), log_cap,
+                                C.byref(log_n),
+                                None if prof is None else prof.ctypes.data_as(C.c_void_p), profile_cap,
+                                C.byref(prof_len), stack_order,
+                                None if exits is None else exits.ctypes.data_as(C.c_void_p), exit_cap,
+                                C.byref(exits_n) if exit_cap else None)
         if rc != 0:
             raise ValueError(f"or_run failed ({rc})")
         out = dict(edep=edep, ledger=ledger, n_log=int(log_n.value), n_iter=int(prof_len.value))
+        if exits is not None:
+            out["n_exits"] = int(exits_n.value)
+            out["exits"] = exits[: min(exit_cap, int(exits_n.value))]
         if log is not None:
             out["log"] = log[: min(log_cap, int(log_n.value))]
         if prof is not None:

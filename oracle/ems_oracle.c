@@ -847,6 +847,9 @@ typedef struct {
   uint32_t* profile_len;
   or_stack* st;
   int err;
+  or_primary* exits;     /* outgoing tracks (NULL: not recorded)          */
+  uint64_t exits_cap;
+  uint64_t* exits_n;
 } or_event;
 
 static void deposit(or_event* ev, int slab, double e, or_step_rec* rec) {
@@ -924,6 +927,22 @@ static void move_helix(or_track* t, double kappa, double s) {
   t->dir[0] = ux * cp + uy * sp;
   t->dir[1] = -ux * sp + uy * cp;
 }
+/* a track leaving the stack: its state at the exit point, in the primary
+ * record layout (so that it can be handed back as input) */
+static void record_exit(or_event* ev, const or_track* t) {
+  if (!ev->exits_n) return;
+  uint64_t i = (*ev->exits_n)++;
+  if (i >= ev->exits_cap) return;
+  or_primary* x = &ev->exits[i];
+  x->event = ev->row;
+  x->species = (uint32_t)t->species;
+  x->ekin_MeV = t->E;
+  for (int k = 0; k < 3; ++k) {
+    x->pos_mm[k] = t->pos[k];
+    x->dir[k] = t->dir[k];
+  }
+}
+
 /* put the track on the plane it reached and change slab; escape if it
  * leaves the stack */
 static void cross_z(or_event* ev, or_track* t) {
@@ -936,12 +955,14 @@ static void cross_z(or_event* ev, or_track* t) {
     t->slab -= 1;
   }
   if (t->slab < 0 || t->slab >= (int)c->n_slabs) {
+    record_exit(ev, t);
     ev->led->escaped[t->species] += t->E;
     t->E = 0.0;
     t->slab = -1;
   }
 }
 static void escape(or_event* ev, or_track* t) {
+  record_exit(ev, t);
   ev->led->escaped[t->species] += t->E;
   t->E = 0.0;
   t->slab = -1;
@@ -1315,6 +1336,15 @@ int or_run(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_events
            const uint32_t* event_keys, double* edep, or_ledger* ledger,
            or_step_rec* log, uint64_t log_cap, uint64_t* log_n, uint64_t* profile,
            uint32_t profile_cap, uint32_t* profile_len, int stack_order) {
+  return or_run_exits(c, prim, n_prim, n_events, event_keys, edep, ledger, log, log_cap, log_n, profile,
+                      profile_cap, profile_len, stack_order, NULL, 0, NULL);
+}
+
+int or_run_exits(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_events,
+                 const uint32_t* event_keys, double* edep, or_ledger* ledger,
+                 or_step_rec* log, uint64_t log_cap, uint64_t* log_n, uint64_t* profile,
+                 uint32_t profile_cap, uint32_t* profile_len, int stack_order,
+                 or_primary* exits, uint64_t exits_cap, uint64_t* exits_n) {
   if (!c || (!prim && n_prim) || !edep || !ledger) return -1;
   uint64_t dummy_n = 0;
   uint32_t dummy_len = 0;
@@ -1358,6 +1388,9 @@ int or_run(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_events
     ev.profile = profile;
     ev.profile_cap = profile_cap;
     ev.profile_len = profile_len;
+    ev.exits = exits;
+    ev.exits_cap = exits_cap;
+    ev.exits_n = exits_n;
     ev.st = &st;
     st.n = 0;
     st.head = 0;

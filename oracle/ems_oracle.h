@@ -143,6 +143,18 @@ int or_run(or_ctx* c, const or_primary* prim, uint64_t n_prim,
            uint64_t* profile, uint32_t profile_cap, uint32_t* profile_len,
            int stack_order);
 
+/* As or_run, and records every track leaving the stack (through the first
+ * or last plane, a transverse wall, or the field-safety margin) in
+ * exits[*exits_n] with its event row, species, kinetic energy, exit point
+ * and direction; *exits_n counts all exits (records beyond exits_cap are
+ * dropped).  exits_n NULL: nothing recorded. */
+int or_run_exits(or_ctx* c, const or_primary* prim, uint64_t n_prim,
+                 uint32_t n_events, const uint32_t* event_keys,
+                 double* edep, or_ledger* ledger,
+                 or_step_rec* log, uint64_t log_cap, uint64_t* log_n,
+                 uint64_t* profile, uint32_t profile_cap, uint32_t* profile_len,
+                 int stack_order, or_primary* exits, uint64_t exits_cap, uint64_t* exits_n);
+
 /* Table export: [n_materials][OR_N_TABLES][n_bins+1]. */
 enum { OR_N_TABLES = 11 };
 uint64_t or_table_count(const or_ctx* c);

@@ -215,3 +215,56 @@ def test_event_key_not_row_decides_history(oracle_mod):
     sub = o.run(one, n_events=1, event_keys=[3])
     assert np.array_equal(sub["edep"][0], full["edep"][3])
     assert np.array_equal(sub["ledger"][0], full["ledger"][3])
+
+
+def test_exits_close_the_ledger_and_sit_on_the_boundary(oracle_mod):
+    """Outgoing tracks: their energies add up to each event's escaped energy
+    per species, every exit point lies on the stack's boundary and every
+    exit direction points out of the stack (with and without field)."""
+    geo = I.calorimeter()
+    H, z0, zN = geo.half_xy_mm, geo.z_mm[0], geo.z_mm[-1]
+    for bz in (0.0, 3.8):
+        cfg = I.RunConfig(seed=9, bz_tesla=bz)
+        prim = I.random_tracks(400, 8, geo, 1e-2, 200.0, seed=21)
+        res = oracle_mod.Oracle(geo, cfg).run(prim, n_events=8, exit_cap=100000)
+        x = res["exits"]
+        assert res["n_exits"] == len(x) > 0
+        esc = np.zeros((8, 3))
+        np.add.at(esc, (x["event"], x["species"]), x["ekin"])
+        assert np.allclose(esc, res["ledger"]["escaped"], rtol=1e-12, atol=1e-12)
+        p, d = x["pos"], x["dir"]
+        back = np.isclose(p[:, 2], zN, atol=1e-9) & (d[:, 2] > 0)
+        front = np.isclose(p[:, 2], z0, atol=1e-9) & (d[:, 2] < 0)
+        if bz == 0.0:
+            side = (np.isclose(np.abs(p[:, 0]), H, atol=1e-9) & (p[:, 0] * d[:, 0] > 0)) | \
+                   (np.isclose(np.abs(p[:, 1]), H, atol=1e-9) & (p[:, 1] * d[:, 1] > 0))
+        else:
+            # charged tracks leave through the field-safety margin, photons
+            # through the walls
+            side = (H - np.maximum(np.abs(p[:, 0]), np.abs(p[:, 1])) < 1e-6 + 1e-9)
+        assert np.all(back | front | side)
+
+
+@pytest.mark.parametrize("E", [0.3, 1.0])
+def test_uncollided_exits_follow_attenuation(oracle_mod, E):
+    """Photons leaving 2.3 mm of lead with their initial energy and
+    direction are the uncollided ones: their number is binomial with
+    p = exp(-Sigma x), Sigma from the cross-section formulas (not the
+    tables); they leave through the back plane on the beam axis."""
+    geo = I.single_slab(2.3, I.LEAD)
+    o = oracle_mod.Oracle(geo, I.RunConfig(seed=13))
+    n = 20000
+    res = o.run(I.beam(n, I.GAMMA, E), exit_cap=4 * n)
+    x = res["exits"]
+    same = (x["species"] == I.GAMMA) & (x["ekin"] == E) & (x["dir"][:, 2] == 1.0)
+    assert np.all(np.isclose(x["pos"][same][:, 2], 2.3, atol=1e-12))
+    assert np.all(x["pos"][same][:, :2] == 0.0)
+    mat = I.LEAD
+    n_at = mat[2] / mat[1] * 6.02214076e23 * 1e-3  # atoms per mm^3
+    sig = n_at * (mat[0] * oracle_mod.formula("SIGMA_KN", mat, 0.0, E) +
+                  oracle_mod.formula("SIGMA_PE", mat, 0.0, E) +
+                  (oracle_mod.formula("SIGMA_PAIR", mat, 0.0, E) if E > 2 * ME else 0.0))
+    p = math.exp(-sig * 2.3)
+    k = int(same.sum())
+    # the tables interpolate the formulas to well below the statistical error
+    assert abs(k - n * p) < 4 * math.sqrt(n * p * (1 - p)) + 1
