@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 1u
+#define EMS_ABI_VERSION 2u
 
 typedef int32_t ems_status;
 enum {
@@ -93,7 +93,7 @@ typedef struct {
 
 typedef struct {
   uint32_t abi_version;          /* EMS_ABI_VERSION                          */
-  uint32_t precision;            /* EMS_FP64 (EMS_MIXED: not yet built)      */
+  uint32_t precision;            /* EMS_FP64 or EMS_MIXED                    */
   double bz_tesla;               /* uniform field along +z                   */
   double gamma_cut_MeV;          /* bremsstrahlung production threshold      */
   double electron_cut_MeV;       /* delta-ray production threshold           */
@@ -113,14 +113,16 @@ typedef struct {
   uint64_t steplog_capacity;     /* records kept when EMS_F_STEPLOG is set   */
   uint32_t profile_capacity;     /* iterations kept when EMS_F_PROFILE       */
   uint32_t steps_per_visit;      /* steps one thread may take of one track per
-                                    launch, stopping at the first step that
-                                    creates secondaries (results do not
-                                    depend on it); 1 = strictly one step of
-                                    the whole population per iteration      */
+                                    launch, through interactions its track
+                                    survives (results do not depend on it);
+                                    1 = strictly one step of the whole
+                                    population per iteration               */
   uint32_t refill_below;         /* a wave commits the visits that ended and
                                     refills those lanes once at most this
                                     many of its 64 lanes are still stepping
                                     (0..63; results do not depend on it)    */
+  uint64_t exit_capacity;        /* outgoing-track records kept per run
+                                    (0 = none; see ems_read_exits)          */
 } ems_config;
 
 /* One primary track (64 bytes). event is the tally row (< max_events); the
@@ -224,6 +226,16 @@ ems_status ems_read_ledger(ems_ctx* ctx, uint32_t first, uint32_t n, ems_ledger*
 ems_status ems_reset_tallies(ems_ctx* ctx);
 /* Copies up to cap step records (host_out) and returns the number taken in
  * *n (may exceed cap; records beyond the configured capacity are dropped). */
+/* Tracks that left the stack since the last ems_reset_tallies (the paper's
+ * hybrid contract, section 4: particles in, hits and outgoing particles
+ * out): one record per track in the primary layout -- event row, species,
+ * kinetic energy, exit point (on the first or last plane, on a transverse
+ * wall, or within the 1e-6 mm field-safety margin of one) and direction --
+ * so that records can be enqueued elsewhere as primaries.  Copies
+ * min(cap, *n_total, exit_capacity) records in no particular order;
+ * *n_total counts every exit, including those beyond exit_capacity. */
+ems_status ems_read_exits(ems_ctx* ctx, ems_primary* host_out, uint64_t cap, uint64_t* n_total);
+
 ems_status ems_read_steplog(ems_ctx* ctx, ems_step_record* host_out, uint64_t cap,
                             uint64_t* n);
 /* Live tracks per species per iteration of the last run: host_out[cap][3]. */
@@ -259,6 +271,8 @@ typedef struct {
   double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result latency      */
   double wall_s;                /* since creation or the last stats reset   */
   double primaries_per_s;       /* completed primaries / wall_s             */
+  uint64_t exits_dropped;       /* outgoing tracks beyond the per-poll
+                                   exit_capacity (lost to their requests)   */
 } ems_server_info;
 
 /* cfg->max_events is the number of tally slots (events in flight);
@@ -281,6 +295,13 @@ ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t 
  * copies its deposits (edep_out[n_slabs], may be NULL) and ledger (may be
  * NULL); the ticket is released.  EMS_E_TIMEOUT, EMS_E_INVALID (unknown
  * ticket), EMS_E_STATE (the device loop failed). */
+/* As ems_server_wait, and also copies the request's outgoing tracks (with
+ * cfg->exit_capacity > 0: the capacity of exits gathered per poll) into
+ * exits_out (event field = 0; *n_exits = all of the request's exits, at
+ * most exits_cap copied). */
+ems_status ems_server_wait_exits(ems_server* s, uint64_t ticket, int64_t timeout_us, double* edep_out,
+                                 ems_ledger* ledger_out, ems_primary* exits_out, uint64_t exits_cap,
+                                 uint64_t* n_exits);
 ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us,
                            double* edep_out, ems_ledger* ledger_out);
 /* Thread-safe.  *done = 1 when the ticket's result is ready. */

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
@@ -44,7 +44,7 @@ class Config(C.Structure):
                 ("flags", C.c_uint32), ("max_steps_per_track", C.c_uint32), ("seed", C.c_uint32),
                 ("max_events", C.c_uint32), ("track_capacity", C.c_uint64), ("steps_per_launch", C.c_uint32),
                 ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
-                ("steps_per_visit", C.c_uint32), ("refill_below", C.c_uint32)]
+                ("steps_per_visit", C.c_uint32), ("refill_below", C.c_uint32), ("exit_capacity", C.c_uint64)]
 
 
 class RunStats(C.Structure):
@@ -60,7 +60,7 @@ class ServerInfo(C.Structure):
                 ("queued", C.c_uint64), ("admitted_bytes", C.c_uint64), ("admit_cap_bytes", C.c_uint64),
                 ("peak_admitted_bytes", C.c_uint64), ("primaries_completed", C.c_uint64), ("chunks", C.c_uint64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
-                ("wall_s", C.c_double), ("primaries_per_s", C.c_double)]
+                ("wall_s", C.c_double), ("primaries_per_s", C.c_double), ("exits_dropped", C.c_uint64)]
 
 
 LEDGER_DTYPE = np.dtype([("edep", "<f8"), ("escaped", "<f8", (3,)), ("killed", "<f8"), ("charged_len", "<f8"),
@@ -98,6 +98,7 @@ def lib():
             "ems_reset_tallies": [vp],
             "ems_read_steplog": [vp, vp, u64, C.POINTER(u64)],
             "ems_read_profile": [vp, vp, u32, C.POINTER(u32)],
+            "ems_read_exits": [vp, vp, u64, C.POINTER(u64)],
             "ems_stats": [vp, C.POINTER(RunStats)],
             "ems_destroy": [vp],
             "ems_host_tables": [C.POINTER(Config), C.POINTER(Geometry), vp, u64],
@@ -106,6 +107,7 @@ def lib():
             "ems_server_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, u64, C.POINTER(vp)],
             "ems_server_submit": [vp, vp, u32, u32, C.POINTER(u64)],
             "ems_server_wait": [vp, u64, C.c_int64, vp, vp],
+            "ems_server_wait_exits": [vp, u64, C.c_int64, vp, vp, vp, u64, C.POINTER(u64)],
             "ems_server_poll": [vp, u64, C.POINTER(C.c_int)],
             "ems_server_flush": [vp],
             "ems_server_stats": [vp, C.POINTER(ServerInfo)],
@@ -151,7 +153,8 @@ class _GeoHolder:
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
-                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=16):
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=16,
+                exit_capacity=0):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
     c = Config()
@@ -169,6 +172,7 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
     c.profile_capacity = profile_capacity
     c.steps_per_visit = steps_per_visit
     c.refill_below = refill_below
+    c.exit_capacity = exit_capacity
     return c
 
 
@@ -293,6 +297,17 @@ class Transport:
         _check(lib().ems_read_profile(self._h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return out, n.value
 
+    def exits(self):
+        """Tracks that left the stack since the last reset (primary records:
+        event row, species, kinetic energy, exit point, direction) and the
+        number of exits including those beyond exit_capacity."""
+        n = C.c_uint64()
+        _check(lib().ems_read_exits(self._h, None, 0, C.byref(n)))
+        out = np.zeros(min(n.value, self.config.exit_capacity), dtype=PRIMARY_DTYPE)
+        if len(out):
+            _check(lib().ems_read_exits(self._h, out.ctypes.data_as(C.c_void_p), len(out), C.byref(n)))
+        return out, n.value
+
     def stats(self):
         s = RunStats()
         _check(lib().ems_stats(self._h, C.byref(s)))
@@ -345,13 +360,28 @@ class Server:
         _check(lib().ems_server_submit(self._h, p.ctypes.data_as(C.c_void_p), len(p), int(key), C.byref(t)))
         return t.value
 
-    def wait(self, ticket, timeout_s=None):
+    def wait(self, ticket, timeout_s=None, exits=False):
+        """(edep, ledger) of a finished request, plus its outgoing tracks
+        (primary records, event field 0) when exits=True."""
         edep = np.empty(self.n_slabs)
         led = np.zeros(1, dtype=LEDGER_DTYPE)
         us = -1 if timeout_s is None else int(timeout_s * 1e6)
-        _check(lib().ems_server_wait(self._h, ticket, us, edep.ctypes.data_as(C.c_void_p),
-                                     led.ctypes.data_as(C.c_void_p)))
-        return edep, led[0]
+        if not exits:
+            _check(lib().ems_server_wait(self._h, ticket, us, edep.ctypes.data_as(C.c_void_p),
+                                         led.ctypes.data_as(C.c_void_p)))
+            return edep, led[0]
+        cap = 1024
+        while True:
+            buf = np.zeros(cap, dtype=PRIMARY_DTYPE)
+            n = C.c_uint64()
+            rc = lib().ems_server_wait_exits(self._h, ticket, us, edep.ctypes.data_as(C.c_void_p),
+                                             led.ctypes.data_as(C.c_void_p), buf.ctypes.data_as(C.c_void_p),
+                                             cap, C.byref(n))
+            if rc == E_CAPACITY and n.value > cap:
+                cap = int(n.value)  # the result is kept for the retry
+                continue
+            _check(rc)
+            return edep, led[0], buf[: n.value]
 
     def poll(self, ticket):
         d = C.c_int()

@@ -21,6 +21,7 @@ using namespace ems;
 static_assert(sizeof(ems_primary) == 64, "primary record is 64 bytes");
 static_assert(sizeof(LedgerDev) == sizeof(ems_ledger), "ledger layouts agree");
 static_assert(sizeof(StepRec) == sizeof(ems_step_record), "step record layouts agree");
+static_assert(sizeof(ExitRec) == sizeof(ems_primary), "exit records are primary records");
 
 namespace ems {
 namespace {
@@ -71,6 +72,7 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
     return fail(EMS_E_INVALID, "max_steps_per_track in [1, 2^20 - 1] and max_events >= 1");
   if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");
   if (c->refill_below > 63) return fail(EMS_E_INVALID, "refill_below in [0, 63]");
+  if (c->exit_capacity > (1ull << 32)) return fail(EMS_E_INVALID, "exit_capacity above 2^32");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
     return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
   return EMS_OK;
@@ -112,6 +114,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   const bool server = (c->flags & EMS_F_EVENT_LIVE) != 0;
   L.rows = take(server ? (uint64_t)c->max_events * 4 : 0);
   L.gather = take(server ? (uint64_t)c->max_events * (g->n_slabs * 8ull + sizeof(LedgerDev)) : 0);
+  L.exits = take(c->exit_capacity * sizeof(ExitRec));
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
   L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
@@ -324,6 +327,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.log = reinterpret_cast<StepRec*>(c->ws + L.log);
   a.profile = reinterpret_cast<uint32_t*>(c->ws + L.profile);
   a.live_ev = reinterpret_cast<int32_t*>(c->ws + L.live);
+  a.exits = reinterpret_cast<ExitRec*>(c->ws + L.exits);
+  a.exit_cap = cfg->exit_capacity;
   a.cap = L.cap;
   a.max_events = cfg->max_events;
   a.log_cap = (cfg->flags & EMS_F_STEPLOG) ? cfg->steplog_capacity : 0;
@@ -503,6 +508,22 @@ ems_status ems_read_steplog(ems_ctx* c, ems_step_record* out, uint64_t cap, uint
   const uint64_t k = std::min<uint64_t>(std::min<uint64_t>(total, c->args.log_cap), out ? cap : 0);
   if (k) {
     HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.log, k * sizeof(StepRec), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return EMS_OK;
+}
+
+ems_status ems_read_exits(ems_ctx* c, ems_primary* out, uint64_t cap, uint64_t* n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if (!n) return fail(EMS_E_INVALID, "null count");
+  HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const uint64_t total = c->pin_ctl->exit_n;
+  *n = total;
+  const uint64_t k = std::min<uint64_t>(std::min<uint64_t>(total, c->cfg.exit_capacity), out ? cap : 0);
+  if (k) {
+    HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.exits, k * sizeof(ExitRec), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return EMS_OK;
@@ -816,6 +837,19 @@ ems_status rt_gather_rows(ems_ctx* c, const uint32_t* rows, uint32_t n, double* 
     for (uint32_t k = 0; k < c->geo.n_slabs; ++k) sum += e[k];
     ledger[i].edep = sum;
   }
+  return EMS_OK;
+}
+
+ems_status rt_take_exits(ems_ctx* c, std::vector<ems_primary>& out, uint64_t* total) {
+  out.clear();
+  *total = c->pin_ctl->exit_n;  // as of the last chunk's status read
+  const uint64_t k = std::min<uint64_t>(*total, c->cfg.exit_capacity);
+  if (*total == 0) return EMS_OK;
+  out.resize(k);
+  if (k) HIPCHK(c, hipMemcpyAsync(out.data(), c->ws + c->L.exits, k * sizeof(ExitRec), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + c->L.ctl + offsetof(Ctl, exit_n), 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pin_ctl->exit_n = 0;
   return EMS_OK;
 }
 

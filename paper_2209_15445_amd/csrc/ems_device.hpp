@@ -76,6 +76,7 @@ struct Ctl {
   // the current queues, next_real those written to the next queues.
   uint32_t n_real[3];
   uint32_t next_real[3];
+  unsigned long long exit_n;  // outgoing tracks recorded (may exceed the capacity)
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
@@ -87,6 +88,12 @@ struct InjRec {
   uint32_t ev, sp;
   int32_t slab;
   uint32_t key;
+};
+
+// Outgoing track, laid out as a primary record of the public header.
+struct ExitRec {
+  uint32_t event, species;
+  double ekin, pos[3], dir[3];
 };
 
 // Per-event ledger as laid out in the public header.
@@ -131,6 +138,8 @@ struct KArgs {
   uint32_t refill_below;      // batch commit/refill when at most this many lanes still step
   uint32_t precision;  // 0: FP64 kernels, 1: mixed kernels
   uint32_t waves_g, waves_l;  // waves of the photon and of the e-/e+ launch
+  ExitRec* exits;             // outgoing tracks (exit_cap records)
+  uint64_t exit_cap;
   StepEnv<double> env;  // scalars; its pointers are set per block
 };
 

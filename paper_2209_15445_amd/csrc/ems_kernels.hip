@@ -156,6 +156,18 @@ __device__ inline bool parent_survives(uint32_t process) {
   return process == kXCompton || process == kXMoller || process == kXBhabha || process == kXBrem;
 }
 
+// One slot per lane with `want` among the lanes executing this call (also in
+// divergent code): one atomic per call for all of them.
+__device__ inline unsigned long long active_append(unsigned long long* counter, bool want) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(m & __lanemask_lt());
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
@@ -208,6 +220,8 @@ struct DevSink {
   // lane finishes (summation order of FP64 atomics is unordered anyway)
   size_t acc_cell;
   double acc_dep;
+  ExitRec* exits;
+  uint64_t exit_cap;
 
   __device__ void flush() {
     if (acc_dep != 0.0) atomicAdd(&edep[acc_cell], acc_dep);
@@ -227,6 +241,23 @@ struct DevSink {
     }
     LedgerDev& L = ledger[t.ev];
     if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
+    if (exit_cap) {
+      // the track left the stack: its state at the exit point
+      const bool out = o.escaped != 0.0;
+      const unsigned long long i = active_append(&ctl->exit_n, out);
+      if (out && i < exit_cap) {
+        ExitRec& x = exits[i];
+        x.event = t.ev;
+        x.species = (uint32_t)sp;
+        x.ekin = o.escaped;
+        x.pos[0] = t.x;
+        x.pos[1] = t.y;
+        x.pos[2] = t.z;
+        x.dir[0] = t.ux;
+        x.dir[1] = t.uy;
+        x.dir[2] = t.uz;
+      }
+    }
     if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
     if (o.pair) atomicAdd(&L.n_pair, (uint32_t)o.pair);
     if (o.annih) atomicAdd(&L.n_annih, (uint32_t)o.annih);
@@ -338,7 +369,8 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     // wave-private append ranges (uniform): secondaries and home, per species
     uint32_t slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, hlo[3] = {0, 0, 0}, hhi[3] = {0, 0, 0};
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
-                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u, 0, 0.0};
+                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u, 0, 0.0,
+                 a.exits, a.exit_cap};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
     const bool track_live = (a.flags & kFlagEventLive) != 0;
 

@@ -20,7 +20,7 @@ hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
-  uint64_t ctl, tab, zp, smat, mat, edep, ledger, live, rows, gather, profile, log, inj, queues, total;
+  uint64_t ctl, tab, zp, smat, mat, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t cap;
 };
 
@@ -90,4 +90,8 @@ ems_status rt_reset_rows(ems_ctx* c, const uint32_t* rows, uint32_t n);
 ems_status rt_gather_rows(ems_ctx* c, const uint32_t* rows, uint32_t n, double* edep, ems_ledger* ledger);
 // copy the live-track counters of all rows to host
 ems_status rt_read_live(ems_ctx* c, int32_t* host);
+// move the outgoing-track records gathered since the last call to the host
+// (after a chunk; *total counts all, including those beyond exit_capacity)
+// and restart the device list
+ems_status rt_take_exits(ems_ctx* c, std::vector<ems_primary>& out, uint64_t* total);
 }  // namespace ems

@@ -40,6 +40,7 @@ struct Request {
   Clock::time_point t_submit;
   std::vector<double> edep;
   ems_ledger ledger{};
+  std::vector<ems_primary> exits;  // outgoing tracks (event field 0)
 };
 
 constexpr size_t kMaxQueued = 1u << 20;
@@ -68,7 +69,7 @@ struct ems_server {
   uint64_t admitted_bytes = 0, peak_bytes = 0, in_flight = 0;
 
   // statistics (under mu)
-  uint64_t submitted = 0, completed = 0, prim_completed = 0, chunks = 0;
+  uint64_t submitted = 0, completed = 0, prim_completed = 0, chunks = 0, exits_dropped = 0;
   std::vector<double> lat_ms;
   Clock::time_point t0;
 
@@ -147,6 +148,27 @@ void ems_server::run() {
     if (rt_read_live(ctx, live.data())) {
       fail_all(std::string("live counters unreadable: ") + ems_last_error());
       return;
+    }
+    // outgoing tracks of this chunk, to their requests (slots change owner
+    // only in this thread)
+    if (ctx->cfg.exit_capacity) {
+      std::vector<ems_primary> ex;
+      uint64_t total = 0;
+      if (rt_take_exits(ctx, ex, &total)) {
+        fail_all(std::string("exit read-back failed: ") + ems_last_error());
+        return;
+      }
+      for (ems_primary q : ex) {
+        const uint32_t row = q.event;
+        if (row < slots.size() && slots[row]) {
+          q.event = 0;
+          slots[row]->exits.push_back(q);
+        }
+      }
+      if (total > ex.size()) {
+        std::lock_guard<std::mutex> lk(mu);
+        exits_dropped += total - ex.size();
+      }
     }
     // events whose last track is gone: their rows come back in one transfer
     std::vector<std::shared_ptr<Request>> finished;
@@ -254,6 +276,12 @@ ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t 
 
 ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us, double* edep_out,
                            ems_ledger* ledger_out) {
+  return ems_server_wait_exits(s, ticket, timeout_us, edep_out, ledger_out, nullptr, 0, nullptr);
+}
+
+ems_status ems_server_wait_exits(ems_server* s, uint64_t ticket, int64_t timeout_us, double* edep_out,
+                                 ems_ledger* ledger_out, ems_primary* exits_out, uint64_t exits_cap,
+                                 uint64_t* n_exits) {
   if (!s) return fail(EMS_E_INVALID, "null server");
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->tickets.find(ticket);
@@ -264,6 +292,12 @@ ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us, d
   else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
     return fail(EMS_E_TIMEOUT, "request not finished yet");
   if (!r->done) return fail(EMS_E_STATE, s->fail_msg);
+  if (n_exits) {
+    *n_exits = r->exits.size();
+    // too small a buffer: report the size and keep the result for a retry
+    if (r->exits.size() > exits_cap) return fail(EMS_E_CAPACITY, "exit buffer too small");
+    if (exits_out) std::copy(r->exits.begin(), r->exits.end(), exits_out);
+  }
   if (edep_out) std::copy(r->edep.begin(), r->edep.end(), edep_out);
   if (ledger_out) *ledger_out = r->ledger;
   s->tickets.erase(ticket);
@@ -302,6 +336,7 @@ ems_status ems_server_stats(ems_server* s, ems_server_info* out) {
   st.peak_admitted_bytes = s->peak_bytes;
   st.primaries_completed = s->prim_completed;
   st.chunks = s->chunks;
+  st.exits_dropped = s->exits_dropped;
   std::vector<double> v = s->lat_ms;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());

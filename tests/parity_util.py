@@ -64,3 +64,17 @@ def mixed_precision_check(edep_m, ledger_m, edep_o, ledger_o, prim, n_layers=50)
     rel = (mm - mo)[live] / mo[live]
     return dict(rel=rel, stat=(sig[live] / mo[live]), rms=float(np.sqrt(np.mean(rel ** 2))),
                 max=float(np.abs(rel).max()))
+
+
+def compare_exits(a, b, e_rtol=1e-9, pos_atol=1e-7, dir_atol=1e-9):
+    """Two lists of outgoing tracks (primary records) as multisets: same
+    count per (event, species) and, sorted by energy, the same energies,
+    exit points and directions within the tolerances."""
+    assert len(a) == len(b), (len(a), len(b))
+    ka = np.lexsort((a["ekin"], a["species"], a["event"]))
+    kb = np.lexsort((b["ekin"], b["species"], b["event"]))
+    a, b = a[ka], b[kb]
+    assert np.array_equal(a["event"], b["event"]) and np.array_equal(a["species"], b["species"])
+    assert np.allclose(a["ekin"], b["ekin"], rtol=e_rtol, atol=0.0)
+    assert np.allclose(a["pos"], b["pos"], rtol=0.0, atol=pos_atol)
+    assert np.allclose(a["dir"], b["dir"], rtol=0.0, atol=dir_atol)

@@ -322,3 +322,42 @@ def test_graph_replays_match_direct_launches(E):
         import torch
         torch.ones(1 << 20, device="cuda").sum().item()
     t.close()
+
+
+@pytest.mark.parametrize("bz", [0.0, 3.8])
+def test_exits_match_oracle(E, oracle_mod, bz):
+    """Outgoing tracks (the hybrid contract's particles out): the same
+    tracks as the oracle's, with their energies, exit points and directions."""
+    from parity_util import compare_exits
+    print(f"exits bz={bz}", flush=True)
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=9, bz_tesla=bz)
+    prim = I.random_tracks(400, 8, geo, 1e-2, 200.0, seed=21)
+    c = E.make_config(cfg, 8, exit_capacity=100000)
+    t = E.Transport(c, geo)
+    t.enqueue(prim)
+    t.run()
+    ex, n = t.exits()
+    led = t.ledger()
+    t.close()
+    r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=8, exit_cap=100000)
+    assert n == r["n_exits"] == len(ex)
+    compare_exits(ex, r["exits"])
+    esc = np.zeros((8, 3))
+    np.add.at(esc, (ex["event"], ex["species"]), ex["ekin"])
+    assert np.allclose(esc, led["escaped"], rtol=1e-12, atol=1e-12)
+
+
+def test_exit_capacity_overflow_counts_all(E):
+    print("exit overflow", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    c = E.make_config(cfg, 32, exit_capacity=10)
+    t = E.Transport(c, geo)
+    t.enqueue(prim)
+    t.run()
+    ex, n = t.exits()
+    t.reset()
+    t.run()
+    ex2, n2 = t.exits()
+    t.close()
+    assert len(ex) == 10 and n > 10 and n2 == 0 and len(ex2) == 0

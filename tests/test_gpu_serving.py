@@ -102,3 +102,25 @@ def test_flush_admission_and_errors(E):
     with pytest.raises(E.EmsError):
         srv.wait(123456789, timeout_s=0.1)
     srv.close()
+
+
+def test_server_returns_outgoing_tracks(E, oracle_mod):
+    """A request's outgoing tracks come back with its deposits and equal the
+    oracle's for the same tracks and event key."""
+    from parity_util import compare_exits
+    print("server exits", flush=True)
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=5, bz_tesla=3.8)
+    c = E.make_config(cfg, 32, track_capacity=1 << 20, steps_per_launch=2, exit_capacity=1 << 16)
+    srv = E.Server(c, geo, 1 << 30)
+    rng = np.random.Generator(np.random.Philox(77))
+    reqs = [I.serving_request(rng, e_median_MeV=800.0, max_tracks=20) for _ in range(6)]
+    tickets = [srv.submit(r, 300 + i) for i, r in enumerate(reqs)]
+    got = [srv.wait(tk, timeout_s=120, exits=True) for tk in tickets]
+    srv.close()
+    for i, (edep, led, ex) in enumerate(got):
+        p = reqs[i].copy()
+        p["event"] = 0
+        r = oracle_mod.Oracle(geo, cfg).run(p, n_events=1, event_keys=[300 + i], exit_cap=1 << 16)
+        compare_exits(ex, r["exits"])
+        assert abs(ex["ekin"].sum() - led["escaped"].sum()) <= 1e-9 * max(1.0, led["escaped"].sum())

@@ -29,7 +29,7 @@ def header_functions():
 
 def test_library_exports_every_declared_entry_point(E):
     names = header_functions()
-    assert len(names) >= 24
+    assert len(names) >= 26
     for n in names:
         assert hasattr(E.lib(), n), n
     assert E.lib().ems_abi_version() == E.ABI_VERSION
