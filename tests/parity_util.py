@@ -71,8 +71,14 @@ def compare_exits(a, b, e_rtol=1e-9, pos_atol=1e-7, dir_atol=1e-9):
     count per (event, species) and, sorted by energy, the same energies,
     exit points and directions within the tolerances."""
     assert len(a) == len(b), (len(a), len(b))
-    ka = np.lexsort((a["ekin"], a["species"], a["event"]))
-    kb = np.lexsort((b["ekin"], b["species"], b["event"]))
+    def order(x):
+        # equal energies occur (both photons of an annihilation at rest):
+        # ties are broken by the exit point, all coarsened far above the
+        # tolerances so that rounding differences cannot reorder
+        e = np.round(np.log(x["ekin"]) * 1e6)
+        p = np.round(x["pos"] * 1e4)
+        return np.lexsort((p[:, 2], p[:, 1], p[:, 0], e, x["species"], x["event"]))
+    ka, kb = order(a), order(b)
     a, b = a[ka], b[kb]
     assert np.array_equal(a["event"], b["event"]) and np.array_equal(a["species"], b["species"])
     assert np.allclose(a["ekin"], b["ekin"], rtol=e_rtol, atol=0.0)
