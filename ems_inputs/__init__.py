@@ -31,6 +31,21 @@ P_ALL = 0x7F
 LEAD = (82.0, 207.2, 11.35, 823.0)
 LIQUID_ARGON = (18.0, 39.948, 1.396, 188.0)
 
+
+def compound(density_g_cm3: float, I_eV: float, elements) -> tuple:
+    """A compound: (Z, A, rho, I, ((Z_i, A_i, atoms_i), ...)) with 1..4
+    elements; the leading Z and A are the atom-averaged values (informative
+    only, the elements define the material)."""
+    els = tuple((float(z), float(a), float(n)) for z, a, n in elements)
+    n = sum(e[2] for e in els)
+    return (sum(e[0] * e[2] for e in els) / n, sum(e[1] * e[2] for e in els) / n,
+            float(density_g_cm3), float(I_eV), els)
+
+
+# Lead tungstate PbWO4, the absorber of the paper's validation calorimeter:
+# PDG density and mean excitation energy, standard atomic weights.
+LEAD_TUNGSTATE = compound(8.300, 600.7, ((82, 207.2, 1), (74, 183.84, 1), (8, 15.999, 4)))
+
 # One primary record: 64 bytes, the layout both C interfaces declare.
 PRIMARY_DTYPE = np.dtype(
     [("event", "<u4"), ("species", "<u4"), ("ekin", "<f8"), ("pos", "<f8", (3,)), ("dir", "<f8", (3,))],

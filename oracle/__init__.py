@@ -45,7 +45,22 @@ def build(force: bool = True) -> str:
 
 class Material(C.Structure):
     _fields_ = [("Z", C.c_double), ("A_g_mol", C.c_double), ("density_g_cm3", C.c_double),
-                ("I_eV", C.c_double)]
+                ("I_eV", C.c_double), ("n_elements", C.c_uint32), ("el_Z", C.c_double * 4),
+                ("el_A", C.c_double * 4), ("el_atoms", C.c_double * 4)]
+
+
+def material_struct(m) -> Material:
+    """(Z, A, rho, I) for an element, (Z, A, rho, I, ((Z, A, atoms), ...))
+    for a compound."""
+    s = Material(*m[:4])
+    if len(m) > 4:
+        els = m[4]
+        if not 1 <= len(els) <= 4:
+            raise ValueError("a compound has 1..4 elements")
+        s.n_elements = len(els)
+        for i, (z, a, n) in enumerate(els):
+            s.el_Z[i], s.el_A[i], s.el_atoms[i] = z, a, n
+    return s
 
 
 class Setup(C.Structure):
@@ -138,7 +153,7 @@ def child_id(key, track_id, step, k):
 
 
 def formula(which, material, cut, E, arg2=0.0):
-    m = Material(*material)
+    m = material_struct(material)
     w = F[which] if isinstance(which, str) else which
     return lib().or_formula(w, C.byref(m), cut, E, arg2)
 
@@ -151,7 +166,7 @@ class Oracle:
         self.cfg = config
         self._z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
         self._mat = np.ascontiguousarray(geometry.material, dtype=np.uint32)
-        self._mats = (Material * len(geometry.materials))(*[Material(*m) for m in geometry.materials])
+        self._mats = (Material * len(geometry.materials))(*[material_struct(m) for m in geometry.materials])
         s = Setup()
         s.n_slabs = geometry.n_slabs
         s.z_mm = self._z.ctypes.data_as(C.POINTER(C.c_double))

@@ -51,12 +51,17 @@ typedef struct {
   double zm13, lnz, fc;  /* Z^{-1/3}, ln Z, Coulomb correction */
 } or_mat;
 
+enum { OR_MAX_EL = 4 };
+
 struct or_ctx {
   or_setup s;
   uint32_t n_slabs, n_mat, nb;       /* nb = n_bins: nodes 0..nb */
   double* z;
   uint32_t* slab_mat;
-  or_mat* mat;
+  or_mat* mat;                       /* material as a whole: electron density, I, plasma energy */
+  or_mat* el;                        /* [n_mat][OR_MAX_EL]: elements with their own atom densities */
+  uint32_t* n_el;                    /* elements per material */
+  double* eltab;                     /* [n_mat][OR_MAX_EL][2][nb+1]: per-element pair, brems Sigma */
   double lnemin, dlog, ecut, tcut, kcut;
   double* tab;                       /* [n_mat][OR_N_TABLES][nb+1] */
 };
@@ -107,23 +112,53 @@ static double integrate(or_fn f, const void* par, double a, double b, int np,
 /* ------------------------------------------------------------------ */
 /* Materials                                                           */
 /* ------------------------------------------------------------------ */
-static void derive_material(const or_material* in, or_mat* m) {
-  m->Z = in->Z;
-  m->A = in->A_g_mol;
-  m->rho = in->density_g_cm3;
-  m->I_eV = in->I_eV;
-  m->n_at = in->density_g_cm3 * NAVO / in->A_g_mol * 1e-3; /* cm^-3 -> mm^-3 */
-  m->n_el = in->Z * m->n_at;
-  m->I = in->I_eV * 1e-6;
-  /* plasma energy 28.816 eV * sqrt(rho Z / A)  (PDG RPP, passage of
-   * particles through matter) */
-  m->plasma = 28.816e-6 * sqrt(in->density_g_cm3 * in->Z / in->A_g_mol);
-  m->zm13 = pow(in->Z, -1.0 / 3.0);
-  m->lnz = log(in->Z);
+/* one element of atomic number Z and molar mass A present with n_at atoms
+ * per mm^3 */
+static void derive_element(double Z, double A, double n_at, or_mat* m) {
+  m->Z = Z;
+  m->A = A;
+  m->n_at = n_at;
+  m->n_el = Z * n_at;
+  m->zm13 = pow(Z, -1.0 / 3.0);
+  m->lnz = log(Z);
   /* Davies-Bethe-Maximon Coulomb correction (PDG RPP form) */
-  double a2 = (ALPHA * in->Z) * (ALPHA * in->Z);
+  double a2 = (ALPHA * Z) * (ALPHA * Z);
   m->fc = a2 * (1.0 / (1.0 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 * a2 -
                 0.002 * a2 * a2 * a2);
+}
+
+/* the material as a whole (m) and its elements (el[0..*n)); a single
+ * element is its own only element */
+static void derive_material_el(const or_material* in, or_mat* m, or_mat* el, uint32_t* n) {
+  double zsum = 0.0, msum = 0.0;  /* electrons and grams per formula unit (per mol) */
+  if (in->n_elements == 0) {
+    *n = 1;
+    derive_element(in->Z, in->A_g_mol, in->density_g_cm3 * NAVO / in->A_g_mol * 1e-3, &el[0]);  /* cm^-3 -> mm^-3 */
+    zsum = in->Z;
+    msum = in->A_g_mol;
+  } else {
+    *n = in->n_elements;
+    for (uint32_t i = 0; i < *n; ++i) msum += in->el_atoms[i] * in->el_A[i];
+    const double n_formula = in->density_g_cm3 * NAVO / msum * 1e-3;
+    for (uint32_t i = 0; i < *n; ++i) {
+      derive_element(in->el_Z[i], in->el_A[i], in->el_atoms[i] * n_formula, &el[i]);
+      zsum += in->el_atoms[i] * in->el_Z[i];
+    }
+  }
+  *m = el[0];
+  m->rho = in->density_g_cm3;
+  m->I_eV = in->I_eV;
+  m->n_el = 0.0;
+  for (uint32_t i = 0; i < *n; ++i) m->n_el += el[i].n_el;
+  m->I = in->I_eV * 1e-6;
+  /* plasma energy 28.816 eV * sqrt(rho <Z/A>)  (PDG RPP, passage of
+   * particles through matter) */
+  m->plasma = 28.816e-6 * sqrt(in->density_g_cm3 * zsum / msum);
+}
+static void derive_material(const or_material* in, or_mat* m) {
+  or_mat el[OR_MAX_EL];
+  uint32_t n;
+  derive_material_el(in, m, el, &n);
 }
 
 /* ------------------------------------------------------------------ */
@@ -439,20 +474,37 @@ static void build_range(const or_ctx* c, const double* S, double* R) {
   }
 }
 
+static double* eltab_ptr(const or_ctx* c, uint32_t m, uint32_t el, int brem) {
+  return c->eltab + (((size_t)m * OR_MAX_EL + el) * 2 + brem) * (c->nb + 1);
+}
+
 static void build_tables(or_ctx* c) {
   uint32_t mask = c->s.process_mask;
   for (uint32_t mi = 0; mi < c->n_mat; ++mi) {
     const or_mat* m = &c->mat[mi];
+    const or_mat* el = &c->el[(size_t)mi * OR_MAX_EL];
     for (uint32_t j = 0; j <= c->nb; ++j) {
       double E = node_energy(c, (int)j);
+      /* per-atom processes add up over the elements; per-electron ones
+       * scale with the material's electron density */
+      double sp = 0.0, sv = 0.0, sr = 0.0, sb = 0.0;
+      for (uint32_t i = 0; i < c->n_el[mi]; ++i) {
+        sp += el[i].n_at * xs_photo(&el[i], E);
+        double v = el[i].n_at * xs_pair(&el[i], E);
+        double r = el[i].n_at * xs_brem(&el[i], E, c->kcut);
+        eltab_ptr(c, mi, i, 0)[j] = (mask & OR_P_CONV) ? v : 0.0;
+        eltab_ptr(c, mi, i, 1)[j] = (mask & OR_P_EBREM) ? r : 0.0;
+        sv += v;
+        sr += r;
+        sb += sbrem(&el[i], E, c->kcut);
+      }
       tab_ptr(c, mi, T_COMPT)[j] = m->n_el * xs_compton(E);
-      tab_ptr(c, mi, T_PHOT)[j] = m->n_at * xs_photo(m, E);
-      tab_ptr(c, mi, T_CONV)[j] = m->n_at * xs_pair(m, E);
-      tab_ptr(c, mi, T_BREM)[j] = m->n_at * xs_brem(m, E, c->kcut);
+      tab_ptr(c, mi, T_PHOT)[j] = sp;
+      tab_ptr(c, mi, T_CONV)[j] = sv;
+      tab_ptr(c, mi, T_BREM)[j] = sr;
       tab_ptr(c, mi, T_MOLLER)[j] = m->n_el * xs_moller(E, c->tcut);
       tab_ptr(c, mi, T_BHABHA)[j] = m->n_el * xs_bhabha(E, c->tcut);
       tab_ptr(c, mi, T_ANNIH)[j] = m->n_el * xs_annih(E);
-      double sb = sbrem(m, E, c->kcut);
       tab_ptr(c, mi, T_S_EM)[j] = sion(m, E, c->tcut, 0) + sb;
       tab_ptr(c, mi, T_S_EP)[j] = sion(m, E, c->tcut, 1) + sb;
     }
@@ -640,6 +692,31 @@ static void sample_photo(double E, const double u[3], or_inter* o) {
 
 /* pair: uniform eps on [eps0, 1/2], rejection on F(eps)/F_max, then the
  * next draw decides which lepton takes eps; both collinear with u */
+/* target element of a pair (brem = 0) or bremsstrahlung (brem = 1)
+ * interaction at energy E in material m: with several elements, the next
+ * draw u picks the first element whose partial sum of interpolated
+ * per-element cross sections exceeds u times their total */
+static const or_mat* pick_element(const or_ctx* c, uint32_t m, int brem, double E, or_stream* rs) {
+  const or_mat* el = &c->el[(size_t)m * OR_MAX_EL];
+  uint32_t n = c->n_el[m];
+  if (n == 1) return &el[0];
+  double u = draw(rs);
+  int j;
+  double t;
+  bin_of(c, log(E), &j, &t);
+  double s[OR_MAX_EL], tot = 0.0;
+  for (uint32_t i = 0; i < n; ++i) {
+    s[i] = interp(eltab_ptr(c, m, i, brem), j, t);
+    tot += s[i];
+  }
+  double cum = 0.0;
+  for (uint32_t i = 0; i + 1 < n; ++i) {
+    cum += s[i];
+    if (u * tot < cum) return &el[i];
+  }
+  return &el[n - 1];
+}
+
 static void sample_pair(const or_mat* m, double E, const double u[3], or_stream* rs,
                         or_inter* o) {
   double eps0 = ME / E, fmax = pair_Fmax(m, E);
@@ -1014,7 +1091,7 @@ static void gamma_step(or_event* ev, or_track* t, or_step_rec* rec) {
     sample_photo(E, t->dir, &o);
   } else {
     rec->process = OR_X_CONV;
-    sample_pair(&c->mat[m], E, t->dir, &rs, &o);
+    sample_pair(pick_element(c, m, 0, E, &rs), E, t->dir, &rs, &o);
     ev->led->n_pair += 1;
   }
   apply(ev, t, &o, rec);
@@ -1233,7 +1310,7 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
   switch (pl.code[chosen]) {
     case OR_X_MOLLER: sample_moller(Tp, c->tcut, t->dir, &rs, &o); break;
     case OR_X_BHABHA: sample_bhabha(Tp, c->tcut, t->dir, &rs, &o); break;
-    case OR_X_BREM: sample_brem(&c->mat[m], Tp, c->kcut, t->dir, &rs, &o); break;
+    case OR_X_BREM: sample_brem(pick_element(c, m, 1, Tp, &rs), Tp, c->kcut, t->dir, &rs, &o); break;
     default:
       sample_annih(Tp, t->dir, &rs, &o);
       ev->led->n_annih += 1;
@@ -1302,8 +1379,11 @@ int or_create(const or_setup* s, or_ctx** out) {
   c->z = (double*)malloc(sizeof(double) * (s->n_slabs + 1));
   c->slab_mat = (uint32_t*)malloc(sizeof(uint32_t) * s->n_slabs);
   c->mat = (or_mat*)malloc(sizeof(or_mat) * s->n_materials);
+  c->el = (or_mat*)calloc((size_t)s->n_materials * OR_MAX_EL, sizeof(or_mat));
+  c->n_el = (uint32_t*)calloc(s->n_materials, sizeof(uint32_t));
   c->tab = (double*)calloc((size_t)s->n_materials * OR_N_TABLES * (s->n_bins + 1), sizeof(double));
-  if (!c->z || !c->slab_mat || !c->mat || !c->tab) {
+  c->eltab = (double*)calloc((size_t)s->n_materials * OR_MAX_EL * 2 * (s->n_bins + 1), sizeof(double));
+  if (!c->z || !c->slab_mat || !c->mat || !c->el || !c->n_el || !c->tab || !c->eltab) {
     or_destroy(c);
     return -2;
   }
@@ -1312,7 +1392,8 @@ int or_create(const or_setup* s, or_ctx** out) {
   c->s.z_mm = c->z;
   c->s.material = c->slab_mat;
   c->s.materials = NULL;
-  for (uint32_t i = 0; i < s->n_materials; ++i) derive_material(&s->materials[i], &c->mat[i]);
+  for (uint32_t i = 0; i < s->n_materials; ++i)
+    derive_material_el(&s->materials[i], &c->mat[i], &c->el[(size_t)i * OR_MAX_EL], &c->n_el[i]);
   c->lnemin = log(s->emin_MeV);
   c->dlog = (log(s->emax_MeV) - log(s->emin_MeV)) / s->n_bins;
   c->ecut = s->emin_MeV;
@@ -1328,7 +1409,10 @@ void or_destroy(or_ctx* c) {
   free(c->z);
   free(c->slab_mat);
   free(c->mat);
+  free(c->el);
+  free(c->n_el);
   free(c->tab);
+  free(c->eltab);
   free(c);
 }
 
@@ -1485,15 +1569,18 @@ int or_sample(const or_ctx* c, int which, uint32_t material, double E, const dou
   normalise(u);
   or_inter o;
   memset(&o, 0, sizeof o);
-  const or_mat* m = &c->mat[material];
+  const or_mat* el0 = &c->el[(size_t)material * OR_MAX_EL];
+  const or_mat* m = el0;
   switch (which) {
     case 0: sample_compton(E, u, &rs, &o); break;
     case 1:
       if (E <= 2.0 * ME) return -1;
+      m = pick_element(c, material, 0, E, &rs);
       sample_pair(m, E, u, &rs, &o);
       break;
     case 2:
       if (E <= c->kcut) return -1;
+      m = pick_element(c, material, 1, E, &rs);
       sample_brem(m, E, c->kcut, u, &rs, &o);
       break;
     case 3:
@@ -1516,5 +1603,6 @@ int or_sample(const or_ctx* c, int which, uint32_t material, double E, const dou
   for (int i = 0; i < 3; ++i) out[7 + i] = o.sec_dir[0][i];
   out[10] = o.n_sec > 1 ? o.sec_E[1] : -1.0;
   for (int i = 0; i < 3; ++i) out[11 + i] = o.sec_dir[1][i];
+  out[15] = (double)(m - el0);
   return 0;
 }

@@ -63,8 +63,20 @@ enum {
   OR_X_ANNIH_REST = 8, OR_X_NULL = 9
 };
 
+/* A material: one element (n_elements = 0: Z, A_g_mol) or a compound of
+ * 1..4 elements with el_atoms atoms of element i per formula unit (Z and
+ * A_g_mol are then not used); density and mean excitation energy are the
+ * material's.  In a compound, per-atom cross sections (photo-effect, pair,
+ * bremsstrahlung and its sub-cut loss) add up over the elements weighted by
+ * their atom densities, per-electron ones (Compton, Moller, Bhabha,
+ * annihilation, ionisation loss) use the total electron density, and a pair
+ * or bremsstrahlung interaction draws its target element from the partial
+ * cross sections with one extra random number (single-element materials
+ * draw none). */
 typedef struct {
   double Z, A_g_mol, density_g_cm3, I_eV;
+  uint32_t n_elements;
+  double el_Z[4], el_A[4], el_atoms[4];
 } or_material;
 
 typedef struct {
@@ -205,7 +217,8 @@ uint64_t or_child_id(const uint32_t key[2], uint64_t id, uint32_t step,
  *        4 Bhabha, 5 annihilation in flight.
  * out (<= 16 doubles): [0] = sampled fraction (eps / k / T_delta ...),
  * [1] = number of trials, then energies and unit directions of the
- * surviving parent and up to two secondaries (see ems_oracle.c).
+ * surviving parent and up to two secondaries (see ems_oracle.c), and
+ * [15] = index of the target element (pair, brems; else 0).
  */
 int or_sample(const or_ctx* c, int which, uint32_t material, double E,
               const double dir[3], const uint32_t key[2], uint64_t id,
