@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
     ap.add_argument("--steps-per-visit", type=int, default=16)
-    ap.add_argument("--refill-below", type=int, default=16)
+    ap.add_argument("--refill-below", type=int, default=32)
     ap.add_argument("--cpu-events", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -328,8 +328,8 @@ def main():
     ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
     ap.add_argument("--mixed-capacity", type=int, default=1 << 28)
     ap.add_argument("--extra-capacity", type=int, default=1 << 26)
-    ap.add_argument("--extra-workload", default="cal_mixed_1-100GeV_bz3.8_x10k",
-                    help="also time this workload in both forms ('' to skip)")
+    ap.add_argument("--extra-workload", default="cal_mixed_1-100GeV_bz3.8_x10k,calPbWO4_10GeV_e-_x10k",
+                    help="also time these workloads (comma-separated) in both forms ('' to skip)")
     ap.add_argument("--serve-slots", type=int, default=16384)
     ap.add_argument("--serve-producers", type=int, default=64)
     ap.add_argument("--serve-window", type=int, default=64, help="outstanding requests per producer (closed loop)")
@@ -399,9 +399,10 @@ def main():
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
     if args.extra_workload:
         out["other_workloads"] = {}
+    for wl in filter(None, args.extra_workload.split(",")):
         for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
-            leg = transport_leg(E, I, args.extra_workload, prec, args.extra_capacity, args)
-            out["other_workloads"][f"{args.extra_workload}/{tag}"] = {
+            leg = transport_leg(E, I, wl, prec, args.extra_capacity, args)
+            out["other_workloads"][f"{wl}/{tag}"] = {
                 "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
                 "track_steps_per_step": leg["track_steps"],
                 "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in leg["roofline"]["kernels"].items()}}

@@ -147,6 +147,12 @@ def workload(name: str):
         return geo, RunConfig(seed=3, bz_tesla=3.8), mixed_species(10_000, seed=3)
     if name == "cal_10GeV_e-_x100k":
         return geo, RunConfig(seed=4), beam(100_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=4)
+    # the same stack with the paper's lead tungstate absorber
+    pbwo4 = calorimeter(absorber=LEAD_TUNGSTATE)
+    if name == "calPbWO4_1GeV_e-_x32":
+        return pbwo4, RunConfig(seed=5), beam(32, ELECTRON, 1000.0)
+    if name == "calPbWO4_10GeV_e-_x10k":
+        return pbwo4, RunConfig(seed=6), beam(10_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=6)
     raise KeyError(name)
 
 

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 2u
+#define EMS_ABI_VERSION 3u
 
 typedef int32_t ems_status;
 enum {
@@ -76,8 +76,21 @@ enum {
                                   direct on the null stream)               */
 };
 
+/* A material: a single element (n_elements = 0: Z, A_g_mol), or a compound
+ * of 1..4 elements with el_atoms[i] atoms of element (el_Z[i], el_A[i]) per
+ * formula unit (Z and A_g_mol are then ignored), such as the lead tungstate
+ * absorber of the paper's validation calorimeter (section 2.2).  Density and
+ * mean excitation energy are the material's.  In a compound the per-atom
+ * cross sections (photo-effect, pair, bremsstrahlung and its sub-cut loss)
+ * add up over the elements at their atom densities, the per-electron ones
+ * (Compton, Moller, Bhabha, annihilation, ionisation loss) use the total
+ * electron density, and pair production and bremsstrahlung draw their target
+ * element from the partial cross sections with one extra random number of
+ * the interaction (single-element materials draw none). */
 typedef struct {
   double Z, A_g_mol, density_g_cm3, I_eV;
+  uint32_t n_elements;           /* 0: single element; 1 .. 4: compound      */
+  double el_Z[4], el_A[4], el_atoms[4];
 } ems_material;
 
 /* Slab stack along z (the paper's 50-layer sampling calorimeter, section

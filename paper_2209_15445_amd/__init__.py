@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
@@ -28,7 +28,20 @@ class EmsError(RuntimeError):
 
 
 class Material(C.Structure):
-    _fields_ = [("Z", C.c_double), ("A_g_mol", C.c_double), ("density_g_cm3", C.c_double), ("I_eV", C.c_double)]
+    _fields_ = [("Z", C.c_double), ("A_g_mol", C.c_double), ("density_g_cm3", C.c_double), ("I_eV", C.c_double),
+                ("n_elements", C.c_uint32), ("el_Z", C.c_double * 4), ("el_A", C.c_double * 4),
+                ("el_atoms", C.c_double * 4)]
+
+    @classmethod
+    def of(cls, m):
+        """(Z, A, rho, I) for an element; (Z, A, rho, I, ((Z_i, A_i, atoms_i), ...))
+        for a compound of 1..4 elements"""
+        out = cls(*m[:4])
+        if len(m) > 4:
+            out.n_elements = len(m[4])  # above 4: rejected by the library
+            for i, (z, a, n) in enumerate(m[4][:4]):
+                out.el_Z[i], out.el_A[i], out.el_atoms[i] = z, a, n
+        return out
 
 
 class Geometry(C.Structure):
@@ -140,7 +153,7 @@ class _GeoHolder:
     def __init__(self, geometry):
         self.z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
         self.mat = np.ascontiguousarray(geometry.material, dtype=np.uint32)
-        self.mats = (Material * len(geometry.materials))(*[Material(*m) for m in geometry.materials])
+        self.mats = (Material * len(geometry.materials))(*[Material.of(m) for m in geometry.materials])
         g = Geometry()
         g.n_slabs = len(self.mat)
         g.z_mm = self.z.ctypes.data_as(C.POINTER(C.c_double))
@@ -153,7 +166,7 @@ class _GeoHolder:
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
-                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=16,
+                launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=32,
                 exit_capacity=0):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""

@@ -57,8 +57,15 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   }
   for (uint32_t i = 0; i < g->n_materials; ++i) {
     const ems_material& m = g->materials[i];
-    if (!(m.Z >= 1.0) || !(m.A_g_mol > 0.0) || !(m.density_g_cm3 > 0.0) || !(m.I_eV > 0.0))
-      return fail(EMS_E_INVALID, "material constants must be positive");
+    if (!(m.density_g_cm3 > 0.0) || !(m.I_eV > 0.0) || !isfinite(m.density_g_cm3) || !isfinite(m.I_eV))
+      return fail(EMS_E_INVALID, "material density and I must be positive");
+    if (m.n_elements > (uint32_t)kMaxElements) return fail(EMS_E_INVALID, "a compound has 1..4 elements");
+    if (m.n_elements == 0 && (!(m.Z >= 1.0) || !(m.A_g_mol > 0.0) || !isfinite(m.Z) || !isfinite(m.A_g_mol)))
+      return fail(EMS_E_INVALID, "element Z >= 1 and A > 0 required");
+    for (uint32_t k = 0; k < m.n_elements; ++k)
+      if (!(m.el_Z[k] >= 1.0) || !(m.el_A[k] > 0.0) || !(m.el_atoms[k] > 0.0) || !isfinite(m.el_Z[k]) ||
+          !isfinite(m.el_A[k]) || !isfinite(m.el_atoms[k]))
+        return fail(EMS_E_INVALID, "compound elements need Z >= 1, A > 0 and atoms > 0");
   }
   if (c->n_bins < 2 || c->n_bins > 2000 || !(c->emin_MeV > 0.0) || !(c->emax_MeV > c->emin_MeV))
     return fail(EMS_E_INVALID, "bad energy grid");
@@ -80,6 +87,13 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
 
 // bytes of one table value and of one queued track in the chosen form
 uint64_t real_bytes(const ems_config* c) { return c->precision == EMS_MIXED ? 4 : 8; }
+
+// element block: screening constants [mat][4][2] (double), then the partial
+// pair / brems totals [mat][4][2][nodes] in the arithmetic type
+uint64_t elem_const_bytes(const ems_geometry* g) { return (uint64_t)g->n_materials * kMaxElements * 2 * 8; }
+uint64_t elem_bytes(const ems_config* c, const ems_geometry* g) {
+  return elem_const_bytes(g) + (uint64_t)g->n_materials * kMaxElements * 2 * (c->n_bins + 1) * real_bytes(c);
+}
 
 }  // namespace
 
@@ -108,6 +122,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.zp = take((g->n_slabs + 1) * 8ull);
   L.smat = take(g->n_slabs * 4ull);
   L.mat = take(g->n_materials * sizeof(MatRT));
+  L.elem = take(elem_bytes(c, g));
   L.edep = take((uint64_t)c->max_events * g->n_slabs * 8);
   L.ledger = take((uint64_t)c->max_events * sizeof(LedgerDev));
   L.live = take((uint64_t)c->max_events * 4);
@@ -134,7 +149,13 @@ TableSet tables_for(const ems_config* c, const ems_geometry* g) {
   std::vector<MaterialIn> mats;
   for (uint32_t i = 0; i < g->n_materials; ++i) {
     const ems_material& m = g->materials[i];
-    mats.push_back(MaterialIn{m.Z, m.A_g_mol, m.density_g_cm3, m.I_eV});
+    MaterialIn in{m.Z, m.A_g_mol, m.density_g_cm3, m.I_eV, m.n_elements, {}, {}, {}};
+    for (uint32_t k = 0; k < m.n_elements; ++k) {
+      in.el_Z[k] = m.el_Z[k];
+      in.el_A[k] = m.el_A[k];
+      in.el_atoms[k] = m.el_atoms[k];
+    }
+    mats.push_back(in);
   }
   return build_tables(p, mats);
 }
@@ -239,6 +260,17 @@ void pack_tables(const TableSet& ts, uint32_t n_mat, std::vector<char>& out) {
   memcpy(out.data() + gb, l.data(), l.size() * sizeof(R));
 }
 
+// element block as laid out on the device: constants (double), then the
+// partial totals in type R
+template <class R>
+void pack_elements(const TableSet& ts, std::vector<char>& out) {
+  const size_t cb = ts.elc.size() * sizeof(double);
+  out.assign(cb + ts.el.size() * sizeof(R), 0);
+  memcpy(out.data(), ts.elc.data(), cb);
+  R* t = reinterpret_cast<R*>(out.data() + cb);
+  for (size_t i = 0; i < ts.el.size(); ++i) t[i] = (R)ts.el[i];
+}
+
 template <class R>
 ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const ems_primary* prim, uint64_t n,
                           uint32_t n_events, const uint32_t* keys, double* edep, ems_ledger* ledger,
@@ -324,6 +356,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.zplane = reinterpret_cast<const double*>(c->ws + L.zp);
   a.slab_mat = reinterpret_cast<const uint32_t*>(c->ws + L.smat);
   a.mat = reinterpret_cast<const MatRT*>(c->ws + L.mat);
+  a.el_c = reinterpret_cast<const double*>(c->ws + L.elem);
+  a.el_tab = c->ws + L.elem + elem_const_bytes(geo);
   a.log = reinterpret_cast<StepRec*>(c->ws + L.log);
   a.profile = reinterpret_cast<uint32_t*>(c->ws + L.profile);
   a.live_ev = reinterpret_cast<int32_t*>(c->ws + L.live);
@@ -357,13 +391,15 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
     return bad(fail(EMS_E_DEVICE, "pinned host allocation or event creation failed"));
   // device table layout: photon block [mat][3][nodes], then lepton block
   // [mat][10][nodes], in the arithmetic type of the chosen form
-  std::vector<char> packed;
+  std::vector<char> packed, elem;
   std::vector<MatRT> rt = c->ts.rt;
   if (cfg->precision == EMS_MIXED) {
     pack_tables<float>(c->ts, geo->n_materials, packed);
+    pack_elements<float>(c->ts, elem);
     for (MatRT& m : rt) inflate_bounds(m);
   } else {
     pack_tables<double>(c->ts, geo->n_materials, packed);
+    pack_elements<double>(c->ts, elem);
   }
   c->keys.resize(cfg->max_events);
   for (uint32_t i = 0; i < cfg->max_events; ++i) c->keys[i] = i;
@@ -380,6 +416,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
+            hipMemcpyAsync(c->ws + L.elem, elem.data(), elem.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.edep, 0, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
             hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
@@ -585,6 +622,10 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
   env.zplane = geo->z_mm;
   env.slab_mat = geo->material;
   env.mat = rt.data();
+  std::vector<char> elem;
+  pack_elements<R>(ts, elem);
+  env.elc = reinterpret_cast<const double*>(elem.data());
+  env.elt = reinterpret_cast<const R*>(elem.data() + ts.elc.size() * sizeof(double));
   std::vector<uint64_t> rows(n_events, 0);
   std::vector<uint32_t> row_keys(n_events);
   for (uint32_t e = 0; e < n_events; ++e) row_keys[e] = keys ? keys[e] : e;

@@ -124,6 +124,8 @@ struct KArgs {
   const double* zplane;
   const uint32_t* slab_mat;
   const MatRT* mat;
+  const double* el_c;   // element screening constants [mat][4][2]
+  const void* el_tab;   // partial pair / brems totals [mat][4][2][nodes] (double or float)
   StepRec* log;
   uint32_t* profile;   // [profile_cap][3]
   int32_t* live_ev;    // [rows] live tracks per event (kFlagEventLive)

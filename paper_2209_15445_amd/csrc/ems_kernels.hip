@@ -312,6 +312,8 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
   env.tl = photons ? nullptr : lds;
   env.zplane = zp;
   env.mat = mr;
+  env.elc = a.el_c;
+  env.elt = static_cast<const R*>(a.el_tab);
   env.slab_mat = sm;
   return env;
 }

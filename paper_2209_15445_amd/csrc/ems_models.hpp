@@ -17,12 +17,16 @@ namespace ems {
 
 // Material constants needed at run time by the samplers and the
 // null-collision bound.
+constexpr int kMaxElements = 4;  // elements of a compound material
+
 struct MatRT {
-  double c136;    // 136 Z^{-1/3}: screening variable prefactor
-  double gshift;  // ln Z / 3 + f_c: subtracted from phi / 4
+  double c136;    // 136 Z^{-1/3}: screening variable prefactor (first element)
+  double gshift;  // ln Z / 3 + f_c: subtracted from phi / 4 (first element)
   // right-continuous discrete totals at the process thresholds (1/mm):
   // e- at 2 T_cut (Moller) and k_c (brems); e+ at T_cut (Bhabha) and k_c
   double up_em[2], up_ep[2];
+  uint32_t n_el;  // elements (1: pair and brems target needs no draw)
+  uint32_t pad_;
 };
 
 // Thomas-Fermi screening functions in the Butcher-Messel parametrisation.

@@ -20,7 +20,7 @@ hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
-  uint64_t ctl, tab, zp, smat, mat, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
+  uint64_t ctl, tab, zp, smat, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t cap;
 };
 

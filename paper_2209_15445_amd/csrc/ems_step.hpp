@@ -33,6 +33,8 @@ struct StepEnv {
   const double* zplane;      // n_slabs + 1
   const uint32_t* slab_mat;  // n_slabs
   const MatRT* mat;
+  const double* elc;         // element screening constants [mat][4][2]
+  const R* elt;              // partial pair / brems totals [mat][4][2][nodes]
   uint32_t nodes, n_slabs;
   R lnemin, dlog, inv_dlog;
   double half_xy, bz;
@@ -56,6 +58,8 @@ EMS_HD StepEnv<R> retype(const StepEnv<S>& a) {
   e.zplane = a.zplane;
   e.slab_mat = a.slab_mat;
   e.mat = a.mat;
+  e.elc = a.elc;
+  e.elt = nullptr;
   e.nodes = a.nodes;
   e.n_slabs = a.n_slabs;
   e.lnemin = (R)a.lnemin;
@@ -513,6 +517,41 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   o.pending = true;
 }
 
+// Target element of a pair (w = 0) or bremsstrahlung (w = 1) interaction at
+// energy E in material m.  In a compound the next draw u picks the first
+// element whose running sum of interpolated partial totals exceeds u times
+// their sum; a single element takes no draw.
+template <class R>
+EMS_HD MatRT target_element(const StepEnv<R>& e, uint32_t m, int w, double E, Draws& r) {
+  MatRT me = e.mat[m];
+  const uint32_t n = me.n_el;
+  if (n <= 1) return me;
+  const R u = r.u<R>();
+  const Bin<R> b = bin_of(e, xlog((R)E));
+  R s[kMaxElements];
+  R tot = R(0);
+#pragma unroll
+  for (int i = 0; i < kMaxElements; ++i) {
+    s[i] = (uint32_t)i < n ? lerp(e.elt + (((size_t)m * kMaxElements + i) * 2 + w) * e.nodes, b) : R(0);
+    tot += s[i];
+  }
+  uint32_t k = n - 1;
+  R cum = R(0);
+  bool found = false;
+#pragma unroll
+  for (int i = 0; i + 1 < kMaxElements; ++i) {
+    if ((uint32_t)i + 1 >= n || found) continue;
+    cum += s[i];
+    if (u * tot < cum) {
+      k = (uint32_t)i;
+      found = true;
+    }
+  }
+  me.c136 = e.elc[((size_t)m * kMaxElements + k) * 2];
+  me.gshift = e.elc[((size_t)m * kMaxElements + k) * 2 + 1];
+  return me;
+}
+
 // The discrete interaction selected by the step (o.process, o.pending):
 // sampling from the step's draws U2, U3, ... (U1, U2 for annihilation at
 // rest), secondaries handed out, parent updated, then the step counter and
@@ -526,21 +565,21 @@ EMS_HD void interact(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   Outcome<R> oc;
   const double E = t.E;
   const V3T<R> u{t.ux, t.uy, t.uz};
-  const MatRT& mr = e.mat[e.slab_mat[t.slab]];
+  const uint32_t m = e.slab_mat[t.slab];
   const uint32_t p = o.process;
   if (KIND != 1 && p == kXCompton) {
     compton(E, u, r, oc);
   } else if (KIND != 1 && p == kXPhot) {
     photo(E, u, oc);
   } else if (KIND != 1 && p == kXConv) {
-    pair(mr, E, u, r, oc);
+    pair(target_element(e, m, 0, E, r), E, u, r, oc);
     o.pair += 1;
   } else if (KIND != 0 && p == kXMoller) {
     moller(E, e.tcut, u, r, oc);
   } else if (KIND != 0 && p == kXBhabha) {
     bhabha(E, e.tcut, u, r, oc);
   } else if (KIND != 0 && p == kXBrem) {
-    brem(mr, E, e.kcut, u, r, oc);
+    brem(target_element(e, m, 1, E, r), E, e.kcut, u, r, oc);
   } else if (KIND != 0 && p == kXAnnih) {
     annihilate(E, u, r, oc);
     o.annih += 1;

@@ -92,19 +92,50 @@ double pref(const MatFull& m) { return 4.0 * kAlpha * kRe * kRe * m.Z * (m.Z + 1
 
 }  // namespace
 
-MatFull derive_material(const MaterialIn& in) {
+namespace {
+// one element present with nat atoms per mm^3
+MatFull derive_element(double Z, double nat) {
   MatFull m;
-  m.Z = in.Z;
-  m.nat = in.rho * kNA / in.A * 1e-3;  // per mm^3
-  m.nel = in.Z * m.nat;
-  m.I = in.I_eV * 1e-6;
-  m.plasma = 28.816e-6 * sqrt(in.rho * in.Z / in.A);
-  const double az2 = (kAlpha * in.Z) * (kAlpha * in.Z);
+  m.Z = Z;
+  m.nat = nat;
+  m.nel = Z * nat;
+  m.I = m.plasma = 0.0;
+  const double az2 = (kAlpha * Z) * (kAlpha * Z);
   const double fc = az2 * (1.0 / (1.0 + az2) + 0.20206 + az2 * (-0.0369 + az2 * (0.0083 - 0.002 * az2)));
-  m.rt.c136 = 136.0 / cbrt(in.Z);
-  m.rt.gshift = log(in.Z) / 3.0 + fc;
+  m.rt.c136 = 136.0 / cbrt(Z);
+  m.rt.gshift = log(Z) / 3.0 + fc;
   m.rt.up_em[0] = m.rt.up_em[1] = m.rt.up_ep[0] = m.rt.up_ep[1] = 0.0;
+  m.rt.n_el = 1;
+  m.rt.pad_ = 0;
   return m;
+}
+}  // namespace
+
+MatSet derive_material(const MaterialIn& in) {
+  MatSet s;
+  double zpu, apu;  // electrons and grams per mole of formula units
+  if (in.n_el == 0) {
+    s.n = 1;
+    s.el[0] = derive_element(in.Z, in.rho * kNA / in.A * 1e-3);  // per mm^3
+    zpu = in.Z;
+    apu = in.A;
+  } else {
+    s.n = in.n_el;
+    zpu = apu = 0.0;
+    for (uint32_t i = 0; i < s.n; ++i) {
+      zpu += in.el_atoms[i] * in.el_Z[i];
+      apu += in.el_atoms[i] * in.el_A[i];
+    }
+    const double units = in.rho * kNA / apu * 1e-3;  // formula units per mm^3
+    for (uint32_t i = 0; i < s.n; ++i) s.el[i] = derive_element(in.el_Z[i], in.el_atoms[i] * units);
+  }
+  s.bulk = s.el[0];
+  s.bulk.nel = 0.0;
+  for (uint32_t i = 0; i < s.n; ++i) s.bulk.nel += s.el[i].nel;
+  s.bulk.I = in.I_eV * 1e-6;
+  s.bulk.plasma = 28.816e-6 * sqrt(in.rho * zpu / apu);
+  s.bulk.rt.n_el = s.n;
+  return s;
 }
 
 double kn_sigma(double E) {
@@ -210,24 +241,43 @@ TableSet build_tables(const TableParams& p, const std::vector<MaterialIn>& mats)
   ts.lnemin = log(p.emin);
   ts.dlog = (log(p.emax) - log(p.emin)) / p.n_bins;
   ts.v.assign((size_t)ts.n_mat * kNumTables * ts.nodes, 0.0);
+  ts.el.assign((size_t)ts.n_mat * kMaxElements * 2 * ts.nodes, 0.0);
+  ts.elc.assign((size_t)ts.n_mat * kMaxElements * 2, 0.0);
   const uint32_t N = ts.nodes;
   auto T = [&](uint32_t m, int t) { return &ts.v[((size_t)m * kNumTables + t) * N]; };
   const bool on_c = p.process_mask & kPCompton, on_p = p.process_mask & kPPhot,
              on_v = p.process_mask & kPConv, on_i = p.process_mask & kPEIoni,
              on_b = p.process_mask & kPEBrem, on_a = p.process_mask & kPAnnih;
   for (uint32_t mi = 0; mi < ts.n_mat; ++mi) {
-    const MatFull m = derive_material(mats[mi]);
+    const MatSet ms = derive_material(mats[mi]);
+    const MatFull& m = ms.bulk;
     ts.rt.push_back(m.rt);
+    for (uint32_t i = 0; i < ms.n; ++i) {
+      ts.elc[((size_t)mi * kMaxElements + i) * 2] = ms.el[i].rt.c136;
+      ts.elc[((size_t)mi * kMaxElements + i) * 2 + 1] = ms.el[i].rt.gshift;
+    }
     for (uint32_t j = 0; j < N; ++j) {
       const double E = exp(ts.lnemin + j * ts.dlog);
+      // per-atom processes: sums over the elements (Bragg additivity)
+      double sp = 0.0, sv = 0.0, sb = 0.0, rl = 0.0;
+      for (uint32_t i = 0; i < ms.n; ++i) {
+        const MatFull& el = ms.el[i];
+        const double v = on_v ? el.nat * pair_sigma(el, E) : 0.0;
+        const double b = on_b ? el.nat * brem_sigma(el, E, p.gamma_cut) : 0.0;
+        ts.el[(((size_t)mi * kMaxElements + i) * 2) * N + j] = v;
+        ts.el[(((size_t)mi * kMaxElements + i) * 2 + 1) * N + j] = b;
+        sp += on_p ? el.nat * photo_sigma(el, E) : 0.0;
+        sv += v;
+        sb += b;
+        rl += brem_loss(el, E, p.gamma_cut);
+      }
       T(mi, tCompt)[j] = on_c ? m.nel * kn_sigma(E) : 0.0;
-      T(mi, tPhot)[j] = on_p ? m.nat * photo_sigma(m, E) : 0.0;
-      T(mi, tConv)[j] = on_v ? m.nat * pair_sigma(m, E) : 0.0;
-      T(mi, tBrem)[j] = on_b ? m.nat * brem_sigma(m, E, p.gamma_cut) : 0.0;
+      T(mi, tPhot)[j] = sp;
+      T(mi, tConv)[j] = sv;
+      T(mi, tBrem)[j] = sb;
       T(mi, tMoller)[j] = on_i ? m.nel * moller_sigma(E, p.electron_cut) : 0.0;
       T(mi, tBhabha)[j] = on_i ? m.nel * bhabha_sigma(E, p.electron_cut) : 0.0;
       T(mi, tAnnih)[j] = on_a ? m.nel * heitler_sigma(E) : 0.0;
-      const double rl = brem_loss(m, E, p.gamma_cut);
       T(mi, tSem)[j] = ion_loss(m, E, p.electron_cut, false) + rl;
       T(mi, tSep)[j] = ion_loss(m, E, p.electron_cut, true) + rl;
     }

@@ -25,6 +25,8 @@ enum : int {
 
 struct MaterialIn {
   double Z, A, rho, I_eV;
+  uint32_t n_el;  // 0: the single element (Z, A); else a compound of n_el elements
+  double el_Z[kMaxElements], el_A[kMaxElements], el_atoms[kMaxElements];
 };
 
 struct MatFull {
@@ -32,7 +34,16 @@ struct MatFull {
   MatRT rt;
 };
 
-MatFull derive_material(const MaterialIn& in);
+// A material as a whole (electron density, I, plasma energy; the screening
+// constants of its first element) and its elements, each with its own atom
+// density and screening constants.
+struct MatSet {
+  MatFull bulk;
+  uint32_t n;
+  MatFull el[kMaxElements];
+};
+
+MatSet derive_material(const MaterialIn& in);
 
 struct TableParams {
   uint32_t n_bins;
@@ -41,11 +52,14 @@ struct TableParams {
   uint32_t process_mask;
 };
 
-// tables[(m * kNumTables + t) * (n_bins + 1) + j]
+// tables[(m * kNumTables + t) * (n_bins + 1) + j]; per-element partial pair
+// (w = 0) and bremsstrahlung (w = 1) totals el[((m * kMaxElements + i) * 2 +
+// w) * nodes + j] (zero beyond a material's elements) and the elements'
+// screening constants elc[(m * kMaxElements + i) * 2 + {0: c136, 1: gshift}]
 struct TableSet {
   uint32_t n_mat = 0, nodes = 0;
   double lnemin = 0, dlog = 0;
-  std::vector<double> v;
+  std::vector<double> v, el, elc;
   std::vector<MatRT> rt;
   double at(uint32_t m, int t, uint32_t j) const { return v[((size_t)m * kNumTables + t) * nodes + j]; }
 };

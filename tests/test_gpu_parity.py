@@ -87,6 +87,36 @@ def test_1gev_32_events_all_slabs(E, oracle_mod):
     assert g["stats"]["steps"] == [int(x) for x in r["profile"].sum(axis=0)]
 
 
+@pytest.mark.parametrize("bz", [0.0, 3.8])
+def test_history_parity_pbwo4(E, oracle_mod, bz):
+    """Lead tungstate absorber: pair and bremsstrahlung targets drawn per
+    element, every step equal to the oracle's"""
+    print(f"history parity PbWO4 bz={bz}", flush=True)
+    geo = I.calorimeter(absorber=I.LEAD_TUNGSTATE)
+    cfg = I.RunConfig(seed=13, bz_tesla=bz)
+    prim = tiny_mixed_primaries()
+    prim["ekin"] *= 30.0
+    g = run_gpu(E, geo, cfg, prim, 48, flags=E.F_STEPLOG | E.F_FULL_LEDGER, log_cap=400000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, log_cap=400000)
+    assert g["n_log"] == r["n_log"]
+    compare_logs(g["log"], r["log"], e_rtol=1e-9, pos_atol=1e-7)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(g["ledger"][f], r["ledger"][f]), f
+    assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
+def test_pbwo4_1gev_32_events(E, oracle_mod):
+    print("PbWO4 1 GeV x 32", flush=True)
+    geo, cfg, prim = I.workload("calPbWO4_1GeV_e-_x32")
+    g = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER)
+    r = oracle_mod.Oracle(geo, cfg).run(prim)
+    assert np.array_equal(g["ledger"]["n_steps"], r["ledger"]["n_steps"])
+    assert np.array_equal(g["ledger"]["n_created"], r["ledger"]["n_created"])
+    assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
 @pytest.mark.parametrize("visit", [2, 16, 1024])
 def test_visit_length_does_not_change_results(E, visit):
     print(f"visit length {visit}", flush=True)
@@ -191,7 +221,7 @@ def test_empty_run_and_edges(E):
     assert L["n_annih"][1] == 1 and abs(e[1].sum() + L["escaped"][1].sum() - (5e-4 + 2 * 0.51099895)) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k", "cal_mixed_1-100GeV_bz3.8_x10k"])
+@pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k", "cal_mixed_1-100GeV_bz3.8_x10k", "calPbWO4_10GeV_e-_x10k"])
 def test_full_size_workload_sampled(E, oracle_mod, name):
     """Full-size workloads in the benchmark's launch configuration: every
     event conserves energy, oracle-sampled events agree exactly, per-layer
@@ -200,7 +230,7 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     geo, cfg, prim = I.workload(name)
     n = len(prim)
     # the capacities bench.py uses for these workloads
-    g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 25) if name == "cal_10GeV_e-_x10k" else (1 << 26))
+    g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 26) if "mixed" in name else (1 << 25))
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -218,7 +248,7 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     assert np.all(np.abs(mg - mo) <= 3 * sig + 0.005 * np.abs(mo) + 1e-9)
 
 
-@pytest.mark.parametrize("case", ["1GeV_e-", "mixed_species_bz3.8"])
+@pytest.mark.parametrize("case", ["1GeV_e-", "mixed_species_bz3.8", "PbWO4_1GeV_e-"])
 def test_mixed_precision_against_fp64_oracle(E, oracle_mod, case):
     """Mixed form on the GPU: conservation 1e-5, secondary counts per-mil,
     per-layer means within 3 sigma + 0.5% of the FP64 oracle on the same
@@ -227,6 +257,8 @@ def test_mixed_precision_against_fp64_oracle(E, oracle_mod, case):
     print(f"mixed precision {case}", flush=True)
     if case == "1GeV_e-":
         geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    elif case == "PbWO4_1GeV_e-":
+        geo, cfg, prim = I.workload("calPbWO4_1GeV_e-_x32")
     else:
         geo = I.calorimeter()
         cfg = I.RunConfig(seed=3, bz_tesla=3.8)

@@ -157,3 +157,56 @@ def test_host_mixed_precision_against_fp64_oracle(E, oracle_mod, case):
     r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=n)
     rep = mixed_precision_check(h["edep"], h["ledger"], r["edep"], r["ledger"], prim)
     assert rep["rms"] < 0.01
+
+
+# ---------------------------------------------------------------- compounds
+def test_compound_tables_agree_with_oracle(E, oracle_mod):
+    geo = I.calorimeter(absorber=I.LEAD_TUNGSTATE)
+    for mask in (I.P_ALL, I.P_CONV | I.P_EBREM | I.P_CONT):
+        cfg = I.RunConfig(process_mask=mask)
+        lt = E.host_tables(E.make_config(cfg, 1), geo)
+        ot = oracle_mod.Oracle(geo, cfg).tables()
+        assert np.array_equal(lt == 0, ot == 0)
+        nz = ot != 0
+        assert np.max(np.abs(lt[nz] - ot[nz]) / np.abs(ot[nz])) < 1e-12
+
+
+def test_compound_validation(E):
+    good = E.make_config(I.RunConfig(), 4)
+    assert _bad(E, good, I.calorimeter(absorber=I.LEAD_TUNGSTATE)) == E.OK
+    bad_mats = [
+        I.compound(8.3, 600.7, ((82, 207.2, 1), (74, 183.84, 1), (8, 16.0, 4), (1, 1.0, 1), (2, 4.0, 1))),
+        (82.0, 207.2, 8.3, 600.7, ((82.0, 207.2, 0.0),)),
+        I.compound(8.3, 600.7, ((0.5, 207.2, 1),)),
+        I.compound(8.3, 600.7, ((82, -1.0, 1),)),
+        I.compound(0.0, 600.7, ((82, 207.2, 1),)),
+    ]
+    for m in bad_mats:
+        assert _bad(E, good, I.calorimeter(absorber=m)) == E.E_INVALID, m
+
+
+@pytest.mark.parametrize("bz", [0.0, 3.8])
+def test_host_step_code_history_parity_pbwo4(E, oracle_mod, bz):
+    """Every step of 48 tracks in the lead tungstate stack (element selection
+    on pair production and bremsstrahlung) equal to the oracle's"""
+    geo = I.calorimeter(absorber=I.LEAD_TUNGSTATE)
+    cfg = I.RunConfig(seed=13, bz_tesla=bz)
+    prim = tiny_mixed_primaries()
+    prim["ekin"] *= 30.0
+    h = E.debug_host_transport(E.make_config(cfg, 48), geo, prim, 48, log_cap=400000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, log_cap=400000)
+    st = compare_logs(h["log"], r["log"], e_rtol=1e-10, pos_atol=1e-8)
+    assert st["n"] == r["n_log"]
+    assert r["ledger"]["n_pair"].sum() > 5
+    assert np.allclose(h["edep"], r["edep"], rtol=1e-10, atol=1e-10)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(h["ledger"][f], r["ledger"][f]), f
+    assert ledger_residual(h["edep"], h["ledger"], prim).max() < 1e-12
+
+
+def test_host_step_code_1gev_showers_pbwo4(E, oracle_mod):
+    geo, cfg, prim = I.workload("calPbWO4_1GeV_e-_x32")
+    h = E.debug_host_transport(E.make_config(cfg, 6), geo, prim[:6], 6)
+    r = oracle_mod.Oracle(geo, cfg).run(prim[:6])
+    assert np.array_equal(h["ledger"]["n_steps"], r["ledger"]["n_steps"])
+    assert np.allclose(h["edep"], r["edep"], rtol=1e-9, atol=1e-9)
