@@ -24,6 +24,9 @@ GAMMA, ELECTRON, POSITRON = 0, 1, 2
 # Process-mask bits (same meaning on both sides).
 P_COMPTON, P_PHOT, P_CONV, P_EIONI, P_EBREM, P_ANNIH, P_CONT = (1 << i for i in range(7))
 P_ALL = 0x7F
+# Optional along-step processes of e-/e+ (outside P_ALL): multiple
+# scattering and fluctuations of the restricted loss.
+P_MSC, P_FLUCT = 1 << 7, 1 << 8
 
 # Materials: (Z, A [g/mol], density [g/cm3], mean excitation energy I [eV]).
 # Z and density of lead and liquid argon as in the workload definition;

@@ -24,7 +24,7 @@ TABLE_NAMES = ["sigma_compton", "sigma_phot", "sigma_conv", "S_e-", "R_e-", "sig
 F = dict(SIGMA_KN=0, SIGMA_PE=1, SIGMA_PAIR=2, DSDE_PAIR=3, SIGMA_BREM=4, DSDK_BREM=5,
          SBREM=6, SIGMA_MOLLER=7, DSDE_MOLLER=8, SIGMA_BHABHA=9, DSDE_BHABHA=10,
          SION_E=11, SION_P=12, SIGMA_ANNIH=13, DSDE_COMPTON=14, PAIR_FMAX=15, PAIR_F=16,
-         BREM_BOUND=17, BREM_F=18)
+         BREM_BOUND=17, BREM_F=18, X0=19, HIGHLAND=20, FLUCT_VAR_E=21, FLUCT_VAR_P=22)
 SAMPLERS = dict(compton=0, pair=1, brem=2, moller=3, bhabha=4, annih=5)
 
 LIMITERS = dict(ZPLANE=0, WALL=1, SAFETY=2, CONT=3, DISCRETE=4, STOPPED=5, SUBCUT=6,
@@ -130,6 +130,10 @@ def lib():
         L.or_sample.argtypes = [vp, C.c_int, C.c_uint32, C.c_double, C.POINTER(C.c_double),
                                 C.POINTER(C.c_uint32), C.c_uint64, C.c_uint32, C.POINTER(C.c_double)]
         L.or_sample.restype = C.c_int
+        L.or_sample_along.argtypes = [vp, C.c_int, C.c_uint32, C.c_double, C.c_double, C.c_double,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_uint32), C.c_uint64, C.c_uint32,
+                                      C.POINTER(C.c_double)]
+        L.or_sample_along.restype = C.c_int
         _lib = L
     return _lib
 
@@ -218,6 +222,17 @@ class Oracle:
         rc = lib().or_sample(self._h, w, material, E, d, _u32(key), track_id, step, out)
         if rc != 0:
             raise ValueError("or_sample rejected its arguments")
+        return np.array(out[:])
+
+    def sample_along(self, which, material, T, s, key, track_id, step, mean=0.0, direction=(0.0, 0.0, 1.0)):
+        """which: 'msc' -> [theta0, ux, uy, uz]; 'fluct_e-' / 'fluct_e+' ->
+        [loss, variance]"""
+        out = (C.c_double * 4)()
+        d = (C.c_double * 3)(*direction)
+        w = dict(msc=0, **{"fluct_e-": 1, "fluct_e+": 2})[which]
+        rc = lib().or_sample_along(self._h, w, material, T, s, mean, d, _u32(key), track_id, step, out)
+        if rc != 0:
+            raise ValueError("or_sample_along rejected its arguments")
         return np.array(out[:])
 
     # -- transport ------------------------------------------------------

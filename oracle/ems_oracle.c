@@ -49,6 +49,8 @@ typedef struct {
   double I;              /* mean excitation energy, MeV */
   double plasma;         /* plasma energy, MeV          */
   double zm13, lnz, fc;  /* Z^{-1/3}, ln Z, Coulomb correction */
+  double x0;             /* radiation length, mm (of the element alone at
+                            its atom density, or of the whole material) */
 } or_mat;
 
 enum { OR_MAX_EL = 4 };
@@ -112,6 +114,21 @@ static double integrate(or_fn f, const void* par, double a, double b, int np,
 /* ------------------------------------------------------------------ */
 /* Materials                                                           */
 /* ------------------------------------------------------------------ */
+/* Tsai's radiation logarithms L_rad and L'_rad (PDG RPP, radiation
+ * length); below Z = 5 his tabulated values */
+static void rad_logs(double Z, double* l, double* lp) {
+  static const double tl[4] = {5.31, 4.79, 4.74, 4.71};
+  static const double tlp[4] = {6.144, 5.621, 5.805, 5.924};
+  int z = (int)floor(Z + 0.5);
+  if (z >= 1 && z <= 4 && Z == (double)z) {
+    *l = tl[z - 1];
+    *lp = tlp[z - 1];
+  } else {
+    *l = log(184.15 * pow(Z, -1.0 / 3.0));
+    *lp = log(1194.0 * pow(Z, -2.0 / 3.0));
+  }
+}
+
 /* one element of atomic number Z and molar mass A present with n_at atoms
  * per mm^3 */
 static void derive_element(double Z, double A, double n_at, or_mat* m) {
@@ -125,6 +142,10 @@ static void derive_element(double Z, double A, double n_at, or_mat* m) {
   double a2 = (ALPHA * Z) * (ALPHA * Z);
   m->fc = a2 * (1.0 / (1.0 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 * a2 -
                 0.002 * a2 * a2 * a2);
+  /* 1/X0 = n_at 4 alpha r_e^2 [Z^2 (L_rad - f_c) + Z L'_rad] */
+  double l, lp;
+  rad_logs(Z, &l, &lp);
+  m->x0 = 1.0 / (n_at * 4.0 * ALPHA * RE * RE * (Z * Z * (l - m->fc) + Z * lp));
 }
 
 /* the material as a whole (m) and its elements (el[0..*n)); a single
@@ -151,6 +172,10 @@ static void derive_material_el(const or_material* in, or_mat* m, or_mat* el, uin
   m->n_el = 0.0;
   for (uint32_t i = 0; i < *n; ++i) m->n_el += el[i].n_el;
   m->I = in->I_eV * 1e-6;
+  /* radiation lengths combine as 1/X0 = sum_i 1/X0_i */
+  double inv_x0 = 0.0;
+  for (uint32_t i = 0; i < *n; ++i) inv_x0 += 1.0 / el[i].x0;
+  m->x0 = 1.0 / inv_x0;
   /* plasma energy 28.816 eV * sqrt(rho <Z/A>)  (PDG RPP, passage of
    * particles through matter) */
   m->plasma = 28.816e-6 * sqrt(in->density_g_cm3 * zsum / msum);
@@ -1020,17 +1045,16 @@ static void record_exit(or_event* ev, const or_track* t) {
   }
 }
 
-/* put the track on the plane it reached and change slab; escape if it
- * leaves the stack */
-static void cross_z(or_event* ev, or_track* t) {
+/* put the track on the plane it reached (the upper one if up) and enter
+ * the next slab; a track that reaches the first or last plane leaves the
+ * stack.  On an inner plane the direction decides: a track deflected back
+ * (multiple scattering at the step's end) stays in its slab. */
+static void cross_z(or_event* ev, or_track* t, int up) {
   or_ctx* c = ev->c;
-  if (t->dir[2] > 0.0) {
-    t->pos[2] = c->z[t->slab + 1];
-    t->slab += 1;
-  } else {
-    t->pos[2] = c->z[t->slab];
-    t->slab -= 1;
-  }
+  t->pos[2] = up ? c->z[t->slab + 1] : c->z[t->slab];
+  int next = up ? t->slab + 1 : t->slab - 1;
+  int outer = next < 0 || next >= (int)c->n_slabs;
+  if (outer || (up ? t->dir[2] > 0.0 : t->dir[2] < 0.0)) t->slab = next;
   if (t->slab < 0 || t->slab >= (int)c->n_slabs) {
     record_exit(ev, t);
     ev->led->escaped[t->species] += t->E;
@@ -1071,7 +1095,7 @@ static void gamma_step(or_event* ev, or_track* t, or_step_rec* rec) {
     rec->step_len = sgeom;
     if (sz <= sw) {
       rec->limiter = OR_L_ZPLANE;
-      cross_z(ev, t);
+      cross_z(ev, t, t->dir[2] > 0.0);
     } else {
       rec->limiter = OR_L_WALL;
       escape(ev, t);
@@ -1167,11 +1191,81 @@ static double sigma_bound(const or_ctx* c, uint32_t m, const or_proclist* p, dou
   return best;
 }
 
+/* ------------------------------------------------------------------ */
+/* Along-step processes of e-/e+ (optional)                            */
+/* ------------------------------------------------------------------ */
+/* their draws sit far above any sampler's, so switching them on leaves the
+ * other draws of a step where they are */
+enum { OR_DRAW_MSC = 1u << 16, OR_DRAW_FLUCT = (1u << 16) + 8u, OR_FLUCT_TRIALS = 16 };
+
+/* Highland's width of the projected angle after a path s (PDG RPP,
+ * multiple scattering through small angles), unit charge; zero where the
+ * logarithmic correction would make it negative */
+static double highland(double T, double s, double x0) {
+  double p = sqrt(T * (T + 2.0 * ME));
+  double beta = p / (T + ME);
+  double r = s / x0;
+  double corr = 1.0 + 0.038 * log(r / (beta * beta));
+  if (!(corr > 0.0)) return 0.0;
+  return 13.6 / (beta * p) * sqrt(r) * corr;
+}
+
+/* Gaussian multiple scattering: the plane angles are independent normal
+ * with width theta_0, so the space angle is theta_0 sqrt(-2 ln u1) and the
+ * azimuth 2 pi u2 (capped at pi) */
+static void msc_deflect(double theta0, const or_stream* as, double dir[3]) {
+  double u1 = draw_at(as, OR_DRAW_MSC), u2 = draw_at(as, OR_DRAW_MSC + 1);
+  if (!(theta0 > 0.0)) return;
+  double th = theta0 * sqrt(-2.0 * log(u1));
+  if (th > PI) th = PI;
+  double out[3];
+  rotate_to(dir, sin(th), cos(th), 2.0 * PI * u2, out);
+  for (int i = 0; i < 3; ++i) dir[i] = out[i];
+}
+
+/* variance of the restricted loss over a path s: the second moment of the
+ * sub-cut delta-ray spectrum for the spin-0 Bethe cross section,
+ * n_el s (2 pi r_e^2 m_e / beta^2) (W_up - beta^2 W_up^2 / (2 W_max)),
+ * W_max = T/2 (e-) or T (e+), W_up = min(cut, W_max) */
+static double fluct_var(const or_mat* m, double cut, double T, double s, int positron) {
+  double g = T / ME + 1.0, b2 = 1.0 - 1.0 / (g * g);
+  double wmax = positron ? T : 0.5 * T;
+  double wup = cut < wmax ? cut : wmax;
+  return m->n_el * s * 2.0 * PI * RE * RE * ME / b2 * (wup - b2 * wup * wup / (2.0 * wmax));
+}
+
+/* loss drawn from the gamma distribution with the given mean and variance:
+ * Marsaglia and Tsang's method (2000) with shape k (raised by one and the
+ * result scaled by u^(1/k) when k < 1), at most OR_FLUCT_TRIALS trials of
+ * three draws each (after them: the mode d of the raised shape) */
+static double gamma_loss(double mean, double var, const or_stream* fs) {
+  double k = mean * mean / var, theta = var / mean;
+  double kk = k < 1.0 ? k + 1.0 : k;
+  double d = kk - 1.0 / 3.0, cc = 1.0 / sqrt(9.0 * d);
+  double x = d;
+  for (uint32_t i = 0; i < OR_FLUCT_TRIALS; ++i) {
+    double u1 = draw_at(fs, OR_DRAW_FLUCT + 3 * i), u2 = draw_at(fs, OR_DRAW_FLUCT + 3 * i + 1);
+    double u3 = draw_at(fs, OR_DRAW_FLUCT + 3 * i + 2);
+    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * PI * u2);
+    double v = 1.0 + cc * z;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    if (log(u3) < 0.5 * z * z + d - d * v + d * log(v)) {
+      x = d * v;
+      break;
+    }
+  }
+  if (k < 1.0) x *= pow(draw_at(fs, OR_DRAW_FLUCT + 3 * OR_FLUCT_TRIALS), 1.0 / k);
+  return x * theta;
+}
+
 static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
   or_ctx* c = ev->c;
   int positron = (t->species == OR_POSITRON);
   uint32_t mask = c->s.process_mask;
   int cont = (mask & OR_P_CONT) != 0;
+  int fluct = cont && (mask & OR_P_FLUCT) != 0;
+  int msc = (mask & OR_P_MSC) != 0;
   or_stream rs = {{ev->key[0], ev->key[1]}, t->id, t->step, 0};
   or_inter o;
   double T = t->E;
@@ -1231,7 +1325,8 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
       if (e2 < elo) elo = e2;
     }
   }
-  double a = elo > c->ecut ? elo : c->ecut;
+  /* with fluctuations any energy down to the cut is reachable */
+  double a = (elo > c->ecut && !fluct) ? elo : c->ecut;
   or_proclist pl = lepton_procs(c, positron);
   double bound = sigma_bound(c, m, &pl, a, T);
 
@@ -1264,6 +1359,13 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
 
   /* continuous loss in the slab the step was taken in */
   double dE = cont ? cont_loss(c, Rtab, T, S, R, s) : 0.0;
+  if (fluct && dE > 0.0 && dE < T) {
+    double var = fluct_var(&c->mat[m], c->tcut, T, s, positron);
+    if (var > 0.0) {
+      dE = gamma_loss(dE, var, &rs);
+      if (dE > T) dE = T;
+    }
+  }
   deposit(ev, t->slab, dE, rec);
   double Tp = T - dE;
   t->E = Tp;
@@ -1280,8 +1382,11 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
     t->slab = -1;
     return;
   }
+  /* the plane reached is fixed before any deflection */
+  int up = t->dir[2] > 0.0;
+  if (msc && s > 0.0) msc_deflect(highland(T, s, c->mat[m].x0), &rs, t->dir);
   if (lim == OR_L_ZPLANE) {
-    cross_z(ev, t);
+    cross_z(ev, t, up);
     return;
   }
   if (lim == OR_L_WALL) {
@@ -1557,6 +1662,10 @@ double or_formula(int which, const or_material* in, double cut, double E, double
     case OR_F_PAIR_F: return pair_F(&m, E, arg2);
     case OR_F_BREM_BOUND: return brem_bound(&m, E, cut);
     case OR_F_BREM_F: return brem_brace(&m, E, arg2);
+    case OR_F_X0: return m.x0;
+    case OR_F_HIGHLAND: return highland(E, arg2, m.x0);
+    case OR_F_FLUCT_VAR_E: return fluct_var(&m, cut, E, arg2, 0);
+    case OR_F_FLUCT_VAR_P: return fluct_var(&m, cut, E, arg2, 1);
     default: return NAN;
   }
 }
@@ -1605,4 +1714,27 @@ int or_sample(const or_ctx* c, int which, uint32_t material, double E, const dou
   for (int i = 0; i < 3; ++i) out[11 + i] = o.sec_dir[1][i];
   out[15] = (double)(m - el0);
   return 0;
+}
+
+int or_sample_along(const or_ctx* c, int which, uint32_t material, double T, double s, double mean,
+                    const double dir[3], const uint32_t key[2], uint64_t id, uint32_t step, double* out) {
+  if (!c || material >= c->n_mat || !out || !(T > 0.0) || !(s >= 0.0)) return -1;
+  or_stream rs = {{key[0], key[1]}, id, step, 0};
+  const or_mat* m = &c->mat[material];
+  for (int i = 0; i < 4; ++i) out[i] = 0.0;
+  if (which == 0) {
+    double u[3] = {dir[0], dir[1], dir[2]};
+    normalise(u);
+    out[0] = highland(T, s, m->x0);
+    msc_deflect(out[0], &rs, u);
+    for (int i = 0; i < 3; ++i) out[1 + i] = u[i];
+    return 0;
+  }
+  if (which == 1 || which == 2) {
+    if (!(mean > 0.0)) return -1;
+    out[1] = fluct_var(m, c->tcut, T, s, which == 2);
+    out[0] = out[1] > 0.0 ? gamma_loss(mean, out[1], &rs) : mean;
+    return 0;
+  }
+  return -1;
 }

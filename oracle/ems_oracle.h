@@ -42,7 +42,15 @@ enum {
   OR_P_EBREM = 1u << 4,   /* discrete bremsstrahlung above the cut     */
   OR_P_ANNIH = 1u << 5,   /* e+ annihilation in flight                 */
   OR_P_CONT = 1u << 6,    /* continuous (restricted) energy loss       */
-  OR_P_ALL = 0x7fu
+  OR_P_ALL = 0x7fu,
+  /* optional along-step processes of e-/e+ (not in OR_P_ALL):            */
+  OR_P_MSC = 1u << 7,     /* multiple Coulomb scattering: Gaussian
+                             deflection with the Highland width at the end
+                             of every charged step                        */
+  OR_P_FLUCT = 1u << 8    /* fluctuations of the restricted loss: gamma
+                             distribution with the step's mean loss and the
+                             Bethe second moment of the sub-cut delta rays
+                             (needs OR_P_CONT)                            */
 };
 
 /* limiter codes written to the step log */
@@ -196,7 +204,13 @@ enum {
   OR_F_PAIR_FMAX = 15,    /* rejection bound of the pair sampler          */
   OR_F_PAIR_F = 16,       /* rejection function of the pair sampler       */
   OR_F_BREM_BOUND = 17,   /* rejection bound of the brems sampler         */
-  OR_F_BREM_F = 18        /* rejection function (brace) at arg2 = k       */
+  OR_F_BREM_F = 18,       /* rejection function (brace) at arg2 = k       */
+  OR_F_X0 = 19,           /* radiation length (mm), Tsai's form           */
+  OR_F_HIGHLAND = 20,     /* theta_0 (rad) of e-/e+ with kinetic energy E
+                             after a path arg2 (mm)                       */
+  OR_F_FLUCT_VAR_E = 21,  /* loss variance (MeV^2) of an e- over a path
+                             arg2 with delta-ray cut `cut`                */
+  OR_F_FLUCT_VAR_P = 22   /* the same for an e+                           */
 };
 double or_formula(int which, const or_material* m, double cut, double E,
                   double arg2);
@@ -223,6 +237,19 @@ uint64_t or_child_id(const uint32_t key[2], uint64_t id, uint32_t step,
 int or_sample(const or_ctx* c, int which, uint32_t material, double E,
               const double dir[3], const uint32_t key[2], uint64_t id,
               uint32_t step, double* out);
+
+/*
+ * Runs one along-step sampler on the draws a charged step of (key, id,
+ * step) uses for it.  which 0: multiple scattering of a track of kinetic
+ * energy T after a path s, out[0] = theta_0, out[1..3] = new direction;
+ * which 1 (e-) / 2 (e+): loss fluctuation, out[0] = the loss sampled
+ * around the mean loss `mean` over the path s from kinetic energy T
+ * (not clamped to T), out[1] = its variance.
+ */
+int or_sample_along(const or_ctx* c, int which, uint32_t material, double T,
+                    double s, double mean, const double dir[3],
+                    const uint32_t key[2], uint64_t id, uint32_t step,
+                    double* out);
 
 #ifdef __cplusplus
 }
