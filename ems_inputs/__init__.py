@@ -150,6 +150,10 @@ def workload(name: str):
         return geo, RunConfig(seed=3, bz_tesla=3.8), mixed_species(10_000, seed=3)
     if name == "cal_10GeV_e-_x100k":
         return geo, RunConfig(seed=4), beam(100_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=4)
+    if name == "cal_10GeV_e-_x10k_msc_fluct":
+        # the benchmark beam with multiple scattering and loss fluctuations
+        return geo, RunConfig(seed=7, process_mask=P_ALL | P_MSC | P_FLUCT), \
+            beam(10_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=7)
     # the same stack with the paper's lead tungstate absorber
     pbwo4 = calorimeter(absorber=LEAD_TUNGSTATE)
     if name == "calPbWO4_1GeV_e-_x32":

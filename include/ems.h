@@ -55,7 +55,22 @@ enum {
   EMS_P_EBREM = 1u << 4,   /* bremsstrahlung photons above the cut         */
   EMS_P_ANNIH = 1u << 5,   /* positron annihilation in flight               */
   EMS_P_CONT = 1u << 6,    /* continuous restricted energy loss             */
-  EMS_P_ALL = 0x7fu
+  EMS_P_ALL = 0x7fu,
+  /* Optional along-step processes of e-/e+ (not in EMS_P_ALL), the rest of
+   * the electromagnetic physics the paper's G4HepEm covers (section 2.2):  */
+  EMS_P_MSC = 1u << 7,     /* multiple Coulomb scattering: at the end of each
+                              charged step of length s the direction turns by
+                              a space angle theta_0 sqrt(-2 ln u1), azimuth
+                              2 pi u2, theta_0 Highland's width for s / X0
+                              (X0 after Tsai, 1/X0 summed over elements); a
+                              track turned back on an inner plane stays in
+                              its slab, one reaching the first or last plane
+                              or a wall leaves the stack                     */
+  EMS_P_FLUCT = 1u << 8    /* restricted-loss fluctuations (with EMS_P_CONT):
+                              the step's loss is drawn from a gamma law with
+                              its mean loss and the Bethe second moment of
+                              the sub-cut delta rays (Marsaglia-Tsang, at most
+                              16 trials), capped at the kinetic energy       */
 };
 /* flags bits */
 enum {

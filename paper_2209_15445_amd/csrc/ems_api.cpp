@@ -75,6 +75,7 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
       !(c->lin_loss_limit > 0.0 && c->lin_loss_limit < 1.0))
     return fail(EMS_E_INVALID, "bad step-function parameters");
   if (!isfinite(c->bz_tesla)) return fail(EMS_E_INVALID, "bz must be finite");
+  if (c->process_mask & ~kPAllBits) return fail(EMS_E_INVALID, "unknown process_mask bits");
   if (c->max_steps_per_track < 1 || c->max_steps_per_track > kMaxStepsPerTrack || c->max_events < 1)
     return fail(EMS_E_INVALID, "max_steps_per_track in [1, 2^20 - 1] and max_events >= 1");
   if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");

@@ -38,7 +38,8 @@ enum Species : int { kGamma = 0, kElectron = 1, kPositron = 2 };
 // process mask bits (same values as the public header)
 enum : uint32_t {
   kPCompton = 1u << 0, kPPhot = 1u << 1, kPConv = 1u << 2, kPEIoni = 1u << 3,
-  kPEBrem = 1u << 4, kPAnnih = 1u << 5, kPCont = 1u << 6
+  kPEBrem = 1u << 4, kPAnnih = 1u << 5, kPCont = 1u << 6, kPMsc = 1u << 7, kPFluct = 1u << 8,
+  kPAllBits = 0x1FFu
 };
 // step-log limiter / process codes (same values as the oracle's log)
 enum : uint32_t {
@@ -91,6 +92,8 @@ EMS_HD double xcos(double v) { return cos(v); }
 EMS_HD float xfloor(float v) { return floorf(v); }
 EMS_HD double xfloor(double v) { return floor(v); }
 EMS_HD float xceil(float v) { return ceilf(v); }
+EMS_HD float xpow(float a, float b) { return powf(a, b); }
+EMS_HD double xpow(double a, double b) { return pow(a, b); }
 EMS_HD double xceil(double v) { return ceil(v); }
 
 // A uniform draw in the arithmetic type: the FP64 value itself, or that

@@ -27,6 +27,8 @@ struct MatRT {
   double up_em[2], up_ep[2];
   uint32_t n_el;  // elements (1: pair and brems target needs no draw)
   uint32_t pad_;
+  double x0;      // radiation length (mm)
+  double nel;     // electrons per mm^3
 };
 
 // Thomas-Fermi screening functions in the Butcher-Messel parametrisation.

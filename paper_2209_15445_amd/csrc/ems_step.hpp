@@ -176,14 +176,14 @@ EMS_HD double phys_distance(Draws& r, R sig, double reach) {
 }
 
 template <class R>
-EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
-  if (t.uz > R(0)) {
-    t.z = e.zplane[t.slab + 1];
-    t.slab += 1;
-  } else {
-    t.z = e.zplane[t.slab];
-    t.slab -= 1;
-  }
+EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o, bool up) {
+  // on the plane reached (the upper one if up), into the next slab; the
+  // first and last planes are the stack's surface.  A track turned back on
+  // an inner plane by multiple scattering stays in its slab.
+  t.z = up ? e.zplane[t.slab + 1] : e.zplane[t.slab];
+  const int next = up ? t.slab + 1 : t.slab - 1;
+  const bool outer = next < 0 || next >= (int)e.n_slabs;
+  if (outer || (up ? t.uz > R(0) : t.uz < R(0))) t.slab = next;
   if (t.slab < 0 || t.slab >= (int)e.n_slabs) {
     o.escaped += t.E;
     t.E = 0.0;
@@ -278,7 +278,7 @@ EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
     o.step_len = sg;
     if (sz <= sw) {
       o.limiter = kLimZ;
-      land_on_plane(e, t, o);
+      land_on_plane(e, t, o, t.uz > R(0));
     } else {
       o.limiter = kLimWall;
       o.escaped += t.E;
@@ -373,6 +373,75 @@ EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, b
   return best;
 }
 
+// Optional along-step processes of e-/e+.  Their draws sit far above the
+// samplers' (which stop after kMaxTrials trials), so switching them on
+// moves no other draw of a step.
+constexpr uint32_t kDrawMsc = 1u << 16, kDrawFluct = (1u << 16) + 8u;
+constexpr int kFluctTrials = 16;
+
+// Highland's width of the projected angle after a path s (unit charge);
+// zero where its logarithmic correction is not positive
+template <class R>
+EMS_HD R highland_width(double T, double s, double x0) {
+  const R p = xsqrt((R)(T * (T + 2.0 * kMe)));
+  const R beta = p / (R)(T + kMe);
+  const R r = (R)(s / x0);
+  const R corr = R(1) + R(0.038) * xlog(r / (beta * beta));
+  return corr > R(0) ? R(13.6) / (beta * p) * xsqrt(r) * corr : R(0);
+}
+
+// Gaussian multiple scattering: independent normal plane angles of width
+// th0 give the space angle th0 sqrt(-2 ln u1) (capped at pi) and a uniform
+// azimuth 2 pi u2 about the current direction
+template <class R>
+EMS_HD void msc_deflect(R th0, Draws& r, Trk<R>& t) {
+  const R u1 = r.u_at<R>(kDrawMsc), u2 = r.u_at<R>(kDrawMsc + 1);
+  if (!(th0 > R(0))) return;
+  R th = th0 * xsqrt(R(-2) * xlog(u1));
+  th = th > R(kPi) ? R(kPi) : th;
+  const V3T<R> d = about_axis(V3T<R>{t.ux, t.uy, t.uz}, xcos(th), xsin(th), R(kTwoPi) * u2);
+  t.ux = d.x;
+  t.uy = d.y;
+  t.uz = d.z;
+}
+
+// variance of the restricted loss over a path s: second moment of the
+// sub-cut delta rays of the spin-0 Bethe cross section,
+// n_el s (2 pi r_e^2 m_e / beta^2) (W_up - beta^2 W_up^2 / (2 W_max))
+template <class R>
+EMS_HD R loss_variance(double nel, double cut, double T, double s, bool positron) {
+  const R g = (R)(T / kMe + 1.0), b2 = R(1) - R(1) / (g * g);
+  const R wmax = (R)(positron ? T : 0.5 * T);
+  const R wup = (R)cut < wmax ? (R)cut : wmax;
+  return (R)(nel * s * (2.0 * kPi * kRe * kRe * kMe)) / b2 * (wup - b2 * wup * wup / (R(2) * wmax));
+}
+
+// a loss drawn from the gamma law of the given mean and variance
+// (Marsaglia-Tsang 2000; shape raised by one and the result scaled by
+// u^(1/k) below k = 1); kFluctTrials trials of three draws at fixed
+// indices, after which the mode of the raised shape is taken
+template <class R>
+EMS_HD R gamma_loss(R mean, R var, Draws& r) {
+  const R k = mean * mean / var, theta = var / mean;
+  const R kk = k < R(1) ? k + R(1) : k;
+  const R d = kk - R(1) / R(3), cc = R(1) / xsqrt(R(9) * d);
+  R x = d;
+  for (int i = 0; i < kFluctTrials; ++i) {
+    const uint32_t b = kDrawFluct + 3u * (uint32_t)i;
+    const R u1 = r.u_at<R>(b), u2 = r.u_at<R>(b + 1), u3 = r.u_at<R>(b + 2);
+    const R z = xsqrt(R(-2) * xlog(u1)) * xcos(R(kTwoPi) * u2);
+    R v = R(1) + cc * z;
+    if (v <= R(0)) continue;
+    v = v * v * v;
+    if (xlog(u3) < R(0.5) * z * z + d - d * v + d * xlog(v)) {
+      x = d * v;
+      break;
+    }
+  }
+  if (k < R(1)) x *= xpow(r.u_at<R>(kDrawFluct + 3u * kFluctTrials), R(1) / k);
+  return x * theta;
+}
+
 template <class R>
 EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
   Draws r;
@@ -413,6 +482,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   }
   const uint32_t m = e.slab_mat[t.slab];
   const bool cont = (e.mask & kPCont) != 0;
+  const bool fluct = cont && (e.mask & kPFluct) != 0;
   const R lnT = xlog((R)T);
   const Bin<R> b = bin_of(e, lnT);
   const R* Rt = e.T(m, positron ? tRep : tRem);
@@ -434,7 +504,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
       elo = e2 < elo ? e2 : elo;
     }
   }
-  const bool from_cut = !(elo > e.ecut);
+  const bool from_cut = fluct || !(elo > e.ecut);  // with fluctuations: anything down to the cut
   const double a = from_cut ? e.ecut : elo;
   const LeptonProcs pl = lepton_procs(e, positron);
   const R bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
@@ -472,7 +542,14 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   o.step_len = s;
   o.clen += s;
   // the step ends at s_max unless a discrete interaction came first
-  const double dE = !cont ? 0.0 : (lim == kLimDiscrete ? cont_loss(e, Rt, b.j, T, S, Rv, s) : loss_max);
+  double dE = !cont ? 0.0 : (lim == kLimDiscrete ? cont_loss(e, Rt, b.j, T, S, Rv, s) : loss_max);
+  if (fluct && dE > 0.0 && dE < T) {
+    const R var = loss_variance<R>(e.mat[m].nel, e.tcut, T, s, positron);
+    if (var > R(0)) {
+      const double x = (double)gamma_loss<R>((R)dE, var, r);
+      dE = x > T ? T : x;
+    }
+  }
   o.dep += dE;
   const double Tp = T - dE;
   t.E = Tp;
@@ -487,8 +564,10 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     }
     return;
   }
+  const bool up = t.uz > R(0);  // the plane reached, fixed before any deflection
+  if ((e.mask & kPMsc) && s > 0.0) msc_deflect(highland_width<R>(T, s, e.mat[m].x0), r, t);
   if (lim == kLimZ) {
-    land_on_plane(e, t, o);
+    land_on_plane(e, t, o, up);
     return;
   }
   if (lim == kLimWall) {
@@ -689,7 +768,7 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
       o.step_len = sg;
       if (sz <= sw) {
         o.limiter = kLimZ;
-        land_on_plane(e, t, o);
+        land_on_plane(e, t, o, t.uz > R(0));
       } else {
         o.limiter = kLimWall;
         o.escaped += t.E;

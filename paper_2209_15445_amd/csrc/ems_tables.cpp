@@ -107,6 +107,15 @@ MatFull derive_element(double Z, double nat) {
   m.rt.up_em[0] = m.rt.up_em[1] = m.rt.up_ep[0] = m.rt.up_ep[1] = 0.0;
   m.rt.n_el = 1;
   m.rt.pad_ = 0;
+  // Tsai's radiation logarithms (tabulated below Z = 5):
+  // 1/X0 = n_at 4 alpha r_e^2 [Z^2 (L_rad - f_c) + Z L'_rad]
+  static const double lrad[4] = {5.31, 4.79, 4.74, 4.71}, lprad[4] = {6.144, 5.621, 5.805, 5.924};
+  const int iz = (int)floor(Z + 0.5);
+  const bool light = iz >= 1 && iz <= 4 && Z == (double)iz;
+  const double l = light ? lrad[iz - 1] : log(184.15 / cbrt(Z));
+  const double lp = light ? lprad[iz - 1] : log(1194.0 / (cbrt(Z) * cbrt(Z)));
+  m.rt.x0 = 1.0 / (nat * 4.0 * kAlpha * kRe * kRe * (Z * Z * (l - fc) + Z * lp));
+  m.rt.nel = m.nel;
   return m;
 }
 }  // namespace
@@ -135,6 +144,10 @@ MatSet derive_material(const MaterialIn& in) {
   s.bulk.I = in.I_eV * 1e-6;
   s.bulk.plasma = 28.816e-6 * sqrt(in.rho * zpu / apu);
   s.bulk.rt.n_el = s.n;
+  s.bulk.rt.nel = s.bulk.nel;
+  double inv_x0 = 0.0;
+  for (uint32_t i = 0; i < s.n; ++i) inv_x0 += 1.0 / s.el[i].rt.x0;
+  s.bulk.rt.x0 = 1.0 / inv_x0;
   return s;
 }
 

@@ -210,3 +210,33 @@ def test_host_step_code_1gev_showers_pbwo4(E, oracle_mod):
     r = oracle_mod.Oracle(geo, cfg).run(prim[:6])
     assert np.array_equal(h["ledger"]["n_steps"], r["ledger"]["n_steps"])
     assert np.allclose(h["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+
+
+# ---------------------------------------------------------------- along-step processes
+@pytest.mark.parametrize("bz", [0.0, 3.8])
+def test_host_step_code_history_parity_msc_fluct(E, oracle_mod, bz):
+    """multiple scattering and loss fluctuations on: every step of 48
+    tracks (and the PbWO4 stack for the compound radiation length) equal to
+    the oracle's"""
+    for absorber in (I.LEAD, I.LEAD_TUNGSTATE):
+        geo = I.calorimeter(absorber=absorber)
+        cfg = I.RunConfig(seed=17, bz_tesla=bz, process_mask=I.P_ALL | I.P_MSC | I.P_FLUCT)
+        prim = tiny_mixed_primaries()
+        prim["ekin"] *= 10.0
+        h = E.debug_host_transport(E.make_config(cfg, 48), geo, prim, 48, log_cap=400000)
+        r = oracle_mod.Oracle(geo, cfg).run(prim, log_cap=400000)
+        # a gamma draw of small shape k scales by u^(1/k), which multiplies
+        # the rounding difference of k by up to ~1/k: energies to 1e-9
+        st = compare_logs(h["log"], r["log"], e_rtol=1e-9, pos_atol=1e-8)
+        assert st["n"] == r["n_log"]
+        assert np.allclose(h["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+        for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+            assert np.array_equal(h["ledger"][f], r["ledger"][f]), f
+        assert ledger_residual(h["edep"], h["ledger"], prim).max() < 1e-12
+
+
+def test_unknown_process_bits_rejected(E):
+    c = E.make_config(I.RunConfig(process_mask=I.P_ALL | I.P_MSC | I.P_FLUCT), 4)
+    assert _bad(E, c, I.calorimeter()) == E.OK
+    c = E.make_config(I.RunConfig(process_mask=I.P_ALL | (1 << 9)), 4)
+    assert _bad(E, c, I.calorimeter()) == E.E_INVALID
