@@ -68,6 +68,32 @@ class Geometry:
     def n_slabs(self) -> int:
         return int(self.material.shape[0])
 
+    @property
+    def n_cols(self) -> int:
+        """deposit columns: one per slab"""
+        return self.n_slabs
+
+
+@dataclasses.dataclass
+class BoxGeometry:
+    """Non-overlapping axis-aligned boxes inside a world box whose remaining
+    volume is world_material; deposits per box, the world last."""
+    lo: np.ndarray            # (n_boxes, 3) mm
+    hi: np.ndarray            # (n_boxes, 3) mm
+    material: np.ndarray      # n_boxes indices (uint32)
+    materials: list
+    world_lo: tuple
+    world_hi: tuple
+    world_material: int
+
+    @property
+    def n_boxes(self) -> int:
+        return int(self.material.shape[0])
+
+    @property
+    def n_cols(self) -> int:
+        return self.n_boxes + 1
+
 
 def calorimeter(n_layers: int = 50, absorber_mm: float = 2.3, gap_mm: float = 5.7,
                 half_xy_mm: float = 200.0, absorber=LEAD, gap=LIQUID_ARGON) -> Geometry:
@@ -77,6 +103,45 @@ def calorimeter(n_layers: int = 50, absorber_mm: float = 2.3, gap_mm: float = 5.
     mat = np.tile(np.array([0, 1], dtype=np.uint32), n_layers)
     return Geometry(z_mm=z.astype(np.float64), material=mat, materials=[absorber, gap],
                     half_xy_mm=float(half_xy_mm))
+
+
+def boxes_from_slabs(geo: Geometry) -> BoxGeometry:
+    """The slab stack written as boxes: box k is slab k over the whole
+    transverse extent, the world box is the stack itself."""
+    n = geo.n_slabs
+    h = geo.half_xy_mm
+    lo = np.empty((n, 3))
+    hi = np.empty((n, 3))
+    lo[:, 0], lo[:, 1], lo[:, 2] = -h, -h, geo.z_mm[:-1]
+    hi[:, 0], hi[:, 1], hi[:, 2] = h, h, geo.z_mm[1:]
+    return BoxGeometry(lo=lo, hi=hi, material=geo.material.astype(np.uint32).copy(), materials=list(geo.materials),
+                       world_lo=(-h, -h, float(geo.z_mm[0])), world_hi=(h, h, float(geo.z_mm[-1])),
+                       world_material=int(geo.material[0]))
+
+
+def towers(cells: int = 9, pitch_mm: float = 40.0, crack_mm: float = 1.0, n_layers: int = 50,
+           absorber_mm: float = 2.3, gap_mm: float = 5.7, absorber=LEAD, gap=LIQUID_ARGON,
+           margin_mm: float = 20.0) -> BoxGeometry:
+    """A cells x cells array of sampling towers (the 50-layer absorber / gap
+    sequence, each layer one box per tower) with cracks of crack_mm between
+    towers; cracks and the surroundings are the world, of the gap material.
+    Tower (i, j) is centred at ((i - c) pitch, (j - c) pitch), c = (cells - 1)/2;
+    an odd count keeps the beam axis inside the central tower."""
+    widths = np.tile(np.array([absorber_mm, gap_mm]), n_layers)
+    z = np.concatenate([[0.0], np.cumsum(widths)])
+    half = 0.5 * (pitch_mm - crack_mm)
+    centres = (np.arange(cells) - 0.5 * (cells - 1)) * pitch_mm
+    lo, hi, mat = [], [], []
+    for i in range(cells):
+        for j in range(cells):
+            for k in range(2 * n_layers):
+                lo.append((centres[i] - half, centres[j] - half, z[k]))
+                hi.append((centres[i] + half, centres[j] + half, z[k + 1]))
+                mat.append(k % 2)
+    w = centres[-1] + half + margin_mm
+    return BoxGeometry(lo=np.array(lo), hi=np.array(hi), material=np.array(mat, dtype=np.uint32),
+                       materials=[absorber, gap], world_lo=(-w, -w, float(z[0])), world_hi=(w, w, float(z[-1])),
+                       world_material=1)
 
 
 def single_slab(thickness_mm: float, material=LEAD, half_xy_mm: float = 200.0) -> Geometry:

@@ -75,6 +75,12 @@ class Setup(C.Structure):
                 ("max_steps_per_track", C.c_uint32), ("seed", C.c_uint32)]
 
 
+class Boxes(C.Structure):
+    _fields_ = [("n_boxes", C.c_uint32), ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)),
+                ("material", C.POINTER(C.c_uint32)), ("world_lo", C.c_double * 3), ("world_hi", C.c_double * 3),
+                ("world_material", C.c_uint32)]
+
+
 class Ledger(C.Structure):
     _fields_ = [("edep", C.c_double), ("escaped", C.c_double * 3), ("killed", C.c_double),
                 ("charged_len", C.c_double), ("n_steps", C.c_uint64),
@@ -134,6 +140,13 @@ def lib():
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint32), C.c_uint64, C.c_uint32,
                                       C.POINTER(C.c_double)]
         L.or_sample_along.restype = C.c_int
+        L.or_create_boxes.argtypes = [C.POINTER(Setup), C.POINTER(Boxes), C.POINTER(vp)]
+        L.or_create_boxes.restype = C.c_int
+        L.or_geo_locate.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_geo_locate.restype = C.c_int
+        L.or_geo_distance.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.or_geo_distance.restype = C.c_double
         _lib = L
     return _lib
 
@@ -168,23 +181,40 @@ class Oracle:
     def __init__(self, geometry, config):
         self.geo = geometry
         self.cfg = config
-        self._z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
+        boxes = hasattr(geometry, "world_lo")
         self._mat = np.ascontiguousarray(geometry.material, dtype=np.uint32)
         self._mats = (Material * len(geometry.materials))(*[material_struct(m) for m in geometry.materials])
         s = Setup()
-        s.n_slabs = geometry.n_slabs
-        s.z_mm = self._z.ctypes.data_as(C.POINTER(C.c_double))
-        s.material = self._mat.ctypes.data_as(C.POINTER(C.c_uint32))
+        if boxes:
+            self._lo = np.ascontiguousarray(geometry.lo, dtype=np.float64)
+            self._hi = np.ascontiguousarray(geometry.hi, dtype=np.float64)
+            b = Boxes()
+            b.n_boxes = geometry.n_boxes
+            b.lo = self._lo.ctypes.data_as(C.POINTER(C.c_double))
+            b.hi = self._hi.ctypes.data_as(C.POINTER(C.c_double))
+            b.material = self._mat.ctypes.data_as(C.POINTER(C.c_uint32))
+            b.world_lo[:] = geometry.world_lo
+            b.world_hi[:] = geometry.world_hi
+            b.world_material = geometry.world_material
+            self._boxes = b
+        else:
+            self._z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
+            s.n_slabs = geometry.n_slabs
+            s.z_mm = self._z.ctypes.data_as(C.POINTER(C.c_double))
+            s.material = self._mat.ctypes.data_as(C.POINTER(C.c_uint32))
+            s.half_xy_mm = geometry.half_xy_mm
         s.n_materials = len(geometry.materials)
         s.materials = self._mats
-        s.half_xy_mm = geometry.half_xy_mm
         for f in ("bz_tesla", "gamma_cut_MeV", "electron_cut_MeV", "n_bins", "emin_MeV", "emax_MeV",
                   "dr_over_range", "final_range_mm", "lin_loss_limit", "process_mask",
                   "max_steps_per_track", "seed"):
             setattr(s, f, getattr(config, f))
         self._setup = s
         h = C.c_void_p()
-        rc = lib().or_create(C.byref(s), C.byref(h))
+        if boxes:
+            rc = lib().or_create_boxes(C.byref(s), C.byref(self._boxes), C.byref(h))
+        else:
+            rc = lib().or_create(C.byref(s), C.byref(h))
         if rc != 0:
             raise ValueError(f"or_create failed ({rc})")
         self._h = h
@@ -235,6 +265,16 @@ class Oracle:
             raise ValueError("or_sample_along rejected its arguments")
         return np.array(out[:])
 
+    def geo_locate(self, p, u):
+        return lib().or_geo_locate(self._h, (C.c_double * 3)(*p), (C.c_double * 3)(*u))
+
+    def geo_distance(self, v, p, u):
+        """(distance, axis, face coordinate) to the next boundary"""
+        ax = C.c_int()
+        f = C.c_double()
+        d = lib().or_geo_distance(self._h, v, (C.c_double * 3)(*p), (C.c_double * 3)(*u), C.byref(ax), C.byref(f))
+        return d, ax.value, f.value
+
     # -- transport ------------------------------------------------------
     def run(self, prim: np.ndarray, n_events: int | None = None, event_keys=None,
             log_cap: int = 0, profile_cap: int = 0, stack_order: int = 0, exit_cap: int = 0):
@@ -244,7 +284,7 @@ class Oracle:
         prim = np.ascontiguousarray(prim)
         if n_events is None:
             n_events = int(prim["event"].max()) + 1 if len(prim) else 0
-        edep = np.zeros((n_events, self.geo.n_slabs), dtype=np.float64)
+        edep = np.zeros((n_events, self.geo.n_cols), dtype=np.float64)
         ledger = np.zeros(n_events, dtype=LEDGER_DTYPE)
         keys = None
         if event_keys is not None:

@@ -58,6 +58,12 @@ enum { OR_MAX_EL = 4 };
 struct or_ctx {
   or_setup s;
   uint32_t n_slabs, n_mat, nb;       /* nb = n_bins: nodes 0..nb */
+  uint32_t n_cols;                   /* deposit columns: slabs, or boxes + world */
+  uint32_t nbox;                     /* box geometry: boxes (0: slab stack) */
+  double *blo, *bhi;                 /* [nbox][3] */
+  uint32_t* bmat;
+  double wlo[3], whi[3];
+  uint32_t wmat;
   double* z;
   uint32_t* slab_mat;
   or_mat* mat;                       /* material as a whole: electron density, I, plasma energy */
@@ -1014,6 +1020,73 @@ static double dist_wall(const or_ctx* c, const or_track* t) {
   }
   return s;
 }
+/* ---- box geometry ---- */
+static uint32_t vol_material(const or_ctx* c, int v) {
+  if (!c->nbox) return c->slab_mat[v];
+  return (uint32_t)v < c->nbox ? c->bmat[v] : c->wmat;
+}
+static int in_axis(double p, double lo, double hi, double u) {
+  return (p > lo && p < hi) || (p == lo && u >= 0.0) || (p == hi && u < 0.0);
+}
+static int in_box(const double* lo, const double* hi, const double p[3], const double u[3]) {
+  return in_axis(p[0], lo[0], hi[0], u[0]) && in_axis(p[1], lo[1], hi[1], u[1]) &&
+         in_axis(p[2], lo[2], hi[2], u[2]);
+}
+static int box_locate(const or_ctx* c, const double p[3], const double u[3]) {
+  for (uint32_t b = 0; b < c->nbox; ++b)
+    if (in_box(c->blo + 3 * b, c->bhi + 3 * b, p, u)) return (int)b;
+  return in_box(c->wlo, c->whi, p, u) ? (int)c->nbox : -1;
+}
+/* leaving a box from inside: nearest exit face (first axis on ties) */
+static double ray_exit(const double* lo, const double* hi, const double p[3], const double u[3],
+                       int* ax, double* face) {
+  double s = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    double d = INFINITY, f = 0.0;
+    if (u[k] > 0.0) { d = (hi[k] - p[k]) / u[k]; f = hi[k]; }
+    else if (u[k] < 0.0) { d = (lo[k] - p[k]) / u[k]; f = lo[k]; }
+    if (d < s) { s = d; *ax = k; *face = f; }
+  }
+  return s;
+}
+/* entering a box from outside (slab method): the entry distance, or
+ * infinity if the ray misses it, grazes an edge or moves away */
+static double ray_entry(const double* lo, const double* hi, const double p[3], const double u[3],
+                        int* ax, double* face) {
+  double tn = -INFINITY, tf = INFINITY;
+  int a = -1;
+  double f = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    if (u[k] == 0.0) {
+      if (!(p[k] >= lo[k] && p[k] < hi[k])) return INFINITY;
+      continue;
+    }
+    double t1 = (lo[k] - p[k]) / u[k], t2 = (hi[k] - p[k]) / u[k];
+    double near = t1 < t2 ? t1 : t2, far = t1 < t2 ? t2 : t1;
+    if (near > tn) { tn = near; a = k; f = u[k] > 0.0 ? lo[k] : hi[k]; }
+    if (far < tf) tf = far;
+  }
+  if (a < 0 || !(tn < tf) || !(tf > 0.0)) return INFINITY;
+  *ax = a;
+  *face = f;
+  return tn > 0.0 ? tn : 0.0;
+}
+/* distance to the next boundary from volume v: a box's own faces, or from
+ * the world the nearer of its exit and the first box entered (boxes win
+ * ties) */
+static double box_distance(const or_ctx* c, int v, const double p[3], const double u[3],
+                           int* ax, double* face) {
+  if ((uint32_t)v < c->nbox) return ray_exit(c->blo + 3 * v, c->bhi + 3 * v, p, u, ax, face);
+  double s = ray_exit(c->wlo, c->whi, p, u, ax, face);
+  for (uint32_t b = 0; b < c->nbox; ++b) {
+    int a = 0;
+    double f = 0.0;
+    double d = ray_entry(c->blo + 3 * b, c->bhi + 3 * b, p, u, &a, &f);
+    if (d <= s) { s = d; *ax = a; *face = f; }
+  }
+  return s;
+}
+
 static void move_straight(or_track* t, double s) {
   for (int i = 0; i < 3; ++i) t->pos[i] += s * t->dir[i];
 }
@@ -1068,6 +1141,15 @@ static void escape(or_event* ev, or_track* t) {
   t->E = 0.0;
   t->slab = -1;
 }
+/* box geometry: put the track on the face it reached and find the volume
+ * it moves into; reaching the world's surface leaves the geometry */
+static void box_cross(or_event* ev, or_track* t, int ax, double face) {
+  const or_ctx* c = ev->c;
+  t->pos[ax] = face;
+  int v = (face == c->wlo[ax] || face == c->whi[ax]) ? -1 : box_locate(c, t->pos, t->dir);
+  if (v < 0) escape(ev, t);
+  else t->slab = v;
+}
 
 static void gamma_step(or_event* ev, or_track* t, or_step_rec* rec) {
   or_ctx* c = ev->c;
@@ -1079,13 +1161,20 @@ static void gamma_step(or_event* ev, or_track* t, or_step_rec* rec) {
     rec->limiter = OR_L_SUBCUT;
     return;
   }
-  uint32_t m = c->slab_mat[t->slab];
+  uint32_t m = vol_material(c, t->slab);
   double E = t->E;
   double sc = (mask & OR_P_COMPTON) ? xs_lookup(c, m, T_COMPT, E, 0.0) : 0.0;
   double sp = (mask & OR_P_PHOT) ? xs_lookup(c, m, T_PHOT, E, 0.0) : 0.0;
   double sv = (mask & OR_P_CONV) ? xs_lookup(c, m, T_CONV, E, 2.0 * ME) : 0.0;
   double sig = sc + sp + sv;
-  double sz = dist_z(c, t), sw = dist_wall(c, t);
+  int ax = 0;
+  double face = 0.0, sz, sw = INFINITY;
+  if (c->nbox) {
+    sz = box_distance(c, t->slab, t->pos, t->dir, &ax, &face);
+  } else {
+    sz = dist_z(c, t);
+    sw = dist_wall(c, t);
+  }
   double sgeom = sz <= sw ? sz : sw;
   or_stream rs = {{ev->key[0], ev->key[1]}, t->id, t->step, 0};
   double u0 = draw(&rs);
@@ -1095,7 +1184,8 @@ static void gamma_step(or_event* ev, or_track* t, or_step_rec* rec) {
     rec->step_len = sgeom;
     if (sz <= sw) {
       rec->limiter = OR_L_ZPLANE;
-      cross_z(ev, t, t->dir[2] > 0.0);
+      if (c->nbox) box_cross(ev, t, ax, face);
+      else cross_z(ev, t, t->dir[2] > 0.0);
     } else {
       rec->limiter = OR_L_WALL;
       escape(ev, t);
@@ -1286,7 +1376,10 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
   }
 
   int field = (c->s.bz_tesla != 0.0);
-  double sz = dist_z(c, t), sgeom, sw = INFINITY, dw = INFINITY;
+  int ax = 0;
+  double face = 0.0;
+  double sz = c->nbox ? box_distance(c, t->slab, t->pos, t->dir, &ax, &face) : dist_z(c, t);
+  double sgeom, sw = INFINITY, dw = INFINITY;
   int zlimited;
   if (field) {
     double ax = fabs(t->pos[0]), ay = fabs(t->pos[1]);
@@ -1299,12 +1392,12 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
     sgeom = sz <= dw ? sz : dw;
     zlimited = (sz <= dw);
   } else {
-    sw = dist_wall(c, t);
+    if (!c->nbox) sw = dist_wall(c, t);
     sgeom = sz <= sw ? sz : sw;
     zlimited = (sz <= sw);
   }
 
-  uint32_t m = c->slab_mat[t->slab];
+  uint32_t m = vol_material(c, t->slab);
   const double* Rtab = tab_ptr(c, m, positron ? T_R_EP : T_R_EM);
   double S = 0.0, R = INFINITY, scont = INFINITY;
   if (cont) {
@@ -1386,7 +1479,8 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
   int up = t->dir[2] > 0.0;
   if (msc && s > 0.0) msc_deflect(highland(T, s, c->mat[m].x0), &rs, t->dir);
   if (lim == OR_L_ZPLANE) {
-    cross_z(ev, t, up);
+    if (c->nbox) box_cross(ev, t, ax, face);
+    else cross_z(ev, t, up);
     return;
   }
   if (lim == OR_L_WALL) {
@@ -1469,33 +1563,25 @@ static int locate(const or_ctx* c, double z, double uz) {
 /* ------------------------------------------------------------------ */
 /* API                                                                 */
 /* ------------------------------------------------------------------ */
-int or_create(const or_setup* s, or_ctx** out) {
-  if (!s || !out || s->n_slabs == 0 || s->n_materials == 0 || s->n_bins < 2) return -1;
-  for (uint32_t i = 0; i < s->n_slabs; ++i) {
-    if (!(s->z_mm[i + 1] > s->z_mm[i])) return -1;
-    if (s->material[i] >= s->n_materials) return -1;
-  }
+/* tables and physics constants (everything but the geometry) */
+static int create_common(const or_setup* s, or_ctx** out) {
+  if (!s || !out || s->n_materials == 0 || s->n_bins < 2) return -1;
   or_ctx* c = (or_ctx*)calloc(1, sizeof(or_ctx));
   if (!c) return -2;
   c->s = *s;
-  c->n_slabs = s->n_slabs;
   c->n_mat = s->n_materials;
   c->nb = s->n_bins;
-  c->z = (double*)malloc(sizeof(double) * (s->n_slabs + 1));
-  c->slab_mat = (uint32_t*)malloc(sizeof(uint32_t) * s->n_slabs);
   c->mat = (or_mat*)malloc(sizeof(or_mat) * s->n_materials);
   c->el = (or_mat*)calloc((size_t)s->n_materials * OR_MAX_EL, sizeof(or_mat));
   c->n_el = (uint32_t*)calloc(s->n_materials, sizeof(uint32_t));
   c->tab = (double*)calloc((size_t)s->n_materials * OR_N_TABLES * (s->n_bins + 1), sizeof(double));
   c->eltab = (double*)calloc((size_t)s->n_materials * OR_MAX_EL * 2 * (s->n_bins + 1), sizeof(double));
-  if (!c->z || !c->slab_mat || !c->mat || !c->el || !c->n_el || !c->tab || !c->eltab) {
+  if (!c->mat || !c->el || !c->n_el || !c->tab || !c->eltab) {
     or_destroy(c);
     return -2;
   }
-  memcpy(c->z, s->z_mm, sizeof(double) * (s->n_slabs + 1));
-  memcpy(c->slab_mat, s->material, sizeof(uint32_t) * s->n_slabs);
-  c->s.z_mm = c->z;
-  c->s.material = c->slab_mat;
+  c->s.z_mm = NULL;
+  c->s.material = NULL;
   c->s.materials = NULL;
   for (uint32_t i = 0; i < s->n_materials; ++i)
     derive_material_el(&s->materials[i], &c->mat[i], &c->el[(size_t)i * OR_MAX_EL], &c->n_el[i]);
@@ -1509,10 +1595,93 @@ int or_create(const or_setup* s, or_ctx** out) {
   return 0;
 }
 
+int or_create(const or_setup* s, or_ctx** out) {
+  if (!s || !out || s->n_slabs == 0) return -1;
+  for (uint32_t i = 0; i < s->n_slabs; ++i) {
+    if (!(s->z_mm[i + 1] > s->z_mm[i])) return -1;
+    if (s->material[i] >= s->n_materials) return -1;
+  }
+  or_ctx* c;
+  int rc = create_common(s, &c);
+  if (rc) return rc;
+  c->n_slabs = s->n_slabs;
+  c->n_cols = s->n_slabs;
+  c->z = (double*)malloc(sizeof(double) * (s->n_slabs + 1));
+  c->slab_mat = (uint32_t*)malloc(sizeof(uint32_t) * s->n_slabs);
+  if (!c->z || !c->slab_mat) {
+    or_destroy(c);
+    return -2;
+  }
+  memcpy(c->z, s->z_mm, sizeof(double) * (s->n_slabs + 1));
+  memcpy(c->slab_mat, s->material, sizeof(uint32_t) * s->n_slabs);
+  c->s.z_mm = c->z;
+  c->s.material = c->slab_mat;
+  *out = c;
+  return 0;
+}
+
+int or_create_boxes(const or_setup* s, const or_boxes* b, or_ctx** out) {
+  if (!s || !b || !out || b->n_boxes == 0 || !b->lo || !b->hi || !b->material) return -1;
+  if (s->bz_tesla != 0.0 || b->world_material >= s->n_materials) return -1;
+  for (int k = 0; k < 3; ++k)
+    if (!(b->world_lo[k] < b->world_hi[k])) return -1;
+  for (uint32_t i = 0; i < b->n_boxes; ++i) {
+    const double *lo = b->lo + 3 * i, *hi = b->hi + 3 * i;
+    if (b->material[i] >= s->n_materials) return -1;
+    for (int k = 0; k < 3; ++k)
+      if (!(lo[k] < hi[k]) || lo[k] < b->world_lo[k] || hi[k] > b->world_hi[k]) return -1;
+  }
+  /* no two boxes share interior points */
+  for (uint32_t i = 0; i < b->n_boxes; ++i)
+    for (uint32_t j = i + 1; j < b->n_boxes; ++j) {
+      int apart = 0;
+      for (int k = 0; k < 3; ++k)
+        if (b->hi[3 * i + k] <= b->lo[3 * j + k] || b->hi[3 * j + k] <= b->lo[3 * i + k]) apart = 1;
+      if (!apart) return -1;
+    }
+  or_ctx* c;
+  int rc = create_common(s, &c);
+  if (rc) return rc;
+  c->nbox = b->n_boxes;
+  c->n_cols = b->n_boxes + 1;
+  c->blo = (double*)malloc(sizeof(double) * 3 * b->n_boxes);
+  c->bhi = (double*)malloc(sizeof(double) * 3 * b->n_boxes);
+  c->bmat = (uint32_t*)malloc(sizeof(uint32_t) * b->n_boxes);
+  if (!c->blo || !c->bhi || !c->bmat) {
+    or_destroy(c);
+    return -2;
+  }
+  memcpy(c->blo, b->lo, sizeof(double) * 3 * b->n_boxes);
+  memcpy(c->bhi, b->hi, sizeof(double) * 3 * b->n_boxes);
+  memcpy(c->bmat, b->material, sizeof(uint32_t) * b->n_boxes);
+  for (int k = 0; k < 3; ++k) {
+    c->wlo[k] = b->world_lo[k];
+    c->whi[k] = b->world_hi[k];
+  }
+  c->wmat = b->world_material;
+  *out = c;
+  return 0;
+}
+
+int or_geo_locate(const or_ctx* c, const double p[3], const double u[3]) {
+  if (!c || !c->nbox) return -1;
+  return box_locate(c, p, u);
+}
+
+double or_geo_distance(const or_ctx* c, int v, const double p[3], const double u[3], int* axis,
+                       double* face) {
+  if (!c || !c->nbox || v < 0 || (uint32_t)v > c->nbox || !axis || !face) return NAN;
+  *axis = -1;
+  *face = NAN;
+  return box_distance(c, v, p, u, axis, face);
+}
 void or_destroy(or_ctx* c) {
   if (!c) return;
   free(c->z);
   free(c->slab_mat);
+  free(c->blo);
+  free(c->bhi);
+  free(c->bmat);
   free(c->mat);
   free(c->el);
   free(c->n_el);
@@ -1543,10 +1712,14 @@ int or_run_exits(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_
   for (uint64_t i = 0; i < n_prim; ++i) {
     const or_primary* p = &prim[i];
     double n2 = p->dir[0] * p->dir[0] + p->dir[1] * p->dir[1] + p->dir[2] * p->dir[2];
-    if (p->event >= n_events || p->species > OR_POSITRON || !(p->ekin_MeV > 0.0) ||
-        !(n2 > 0.0) || !(p->pos_mm[2] >= c->z[0] && p->pos_mm[2] <= c->z[c->n_slabs]) ||
-        !(fabs(p->pos_mm[0]) <= c->s.half_xy_mm) || !(fabs(p->pos_mm[1]) <= c->s.half_xy_mm))
+    if (p->event >= n_events || p->species > OR_POSITRON || !(p->ekin_MeV > 0.0) || !(n2 > 0.0))
       return -1;
+    if (c->nbox) {
+      if (box_locate(c, p->pos_mm, p->dir) < 0) return -1;
+    } else if (!(p->pos_mm[2] >= c->z[0] && p->pos_mm[2] <= c->z[c->n_slabs]) ||
+               !(fabs(p->pos_mm[0]) <= c->s.half_xy_mm) || !(fabs(p->pos_mm[1]) <= c->s.half_xy_mm)) {
+      return -1;
+    }
   }
   or_stack st = {NULL, 0, 0, 0};
   uint64_t* count = (uint64_t*)calloc(n_events ? n_events : 1, sizeof(uint64_t));
@@ -1569,7 +1742,7 @@ int or_run_exits(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_
     ev.key[0] = c->s.seed;
     ev.key[1] = event_keys ? event_keys[e] : e;
     ev.row = e;
-    ev.edep = edep + (size_t)e * c->n_slabs;
+    ev.edep = edep + (size_t)e * c->n_cols;
     ev.led = &ledger[e];
     ev.log = log;
     ev.log_cap = log_cap;
@@ -1594,7 +1767,7 @@ int or_run_exits(or_ctx* c, const or_primary* prim, uint64_t n_prim, uint32_t n_
         t.pos[k] = p->pos_mm[k];
         t.dir[k] = p->dir[k] / n;
       }
-      t.slab = locate(c, t.pos[2], t.dir[2]);
+      t.slab = c->nbox ? box_locate(c, t.pos, t.dir) : locate(c, t.pos[2], t.dir[2]);
       t.event = e;
       t.id = count[e]++;
       t.step = 0;

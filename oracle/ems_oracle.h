@@ -141,6 +141,32 @@ typedef struct or_ctx or_ctx;
 
 /* Builds the cross-section / stopping-power / range tables. 0 = OK. */
 int or_create(const or_setup* s, or_ctx** out);
+
+/*
+ * Box geometry (instead of the slab stack): n_boxes non-overlapping
+ * axis-aligned boxes [lo, hi] inside a world box, whose remaining volume is
+ * made of world_material; leaving the world box leaves the geometry.
+ * Volume v < n_boxes is box v, volume n_boxes the world; deposits are
+ * scored per volume (n_boxes + 1 columns).  A point on a face belongs to
+ * the box it moves into (per axis: lo < p < hi, or p = lo moving with
+ * u >= 0, or p = hi moving with u < 0).  Navigation is brute force over all
+ * boxes.  No magnetic field.  The slab fields of s are not used.
+ */
+typedef struct {
+  uint32_t n_boxes;
+  const double* lo;           /* n_boxes x 3 (x, y, z), mm               */
+  const double* hi;           /* n_boxes x 3, lo < hi                     */
+  const uint32_t* material;   /* n_boxes material indices                 */
+  double world_lo[3], world_hi[3];
+  uint32_t world_material;
+} or_boxes;
+int or_create_boxes(const or_setup* s, const or_boxes* b, or_ctx** out);
+/* volume containing point p moving along u (-1: outside the world) */
+int or_geo_locate(const or_ctx* c, const double p[3], const double u[3]);
+/* distance from p in volume v along u to the next boundary, and the
+ * crossed face (axis, coordinate) */
+double or_geo_distance(const or_ctx* c, int v, const double p[3], const double u[3],
+                       int* axis, double* face);
 void or_destroy(or_ctx* c);
 
 /*
