@@ -329,7 +329,8 @@ def main():
     ap.add_argument("--mixed-capacity", type=int, default=1 << 28)
     ap.add_argument("--extra-capacity", type=int, default=1 << 26)
     ap.add_argument("--extra-workload",
-                    default="cal_mixed_1-100GeV_bz3.8_x10k,calPbWO4_10GeV_e-_x10k,cal_10GeV_e-_x10k_msc_fluct",
+                    default="cal_mixed_1-100GeV_bz3.8_x10k,calPbWO4_10GeV_e-_x10k,cal_10GeV_e-_x10k_msc_fluct,"
+                            "towers_10GeV_e-_x10k",
                     help="also time these workloads (comma-separated) in both forms ('' to skip)")
     ap.add_argument("--serve-slots", type=int, default=16384)
     ap.add_argument("--serve-producers", type=int, default=64)

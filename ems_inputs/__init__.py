@@ -219,6 +219,15 @@ def workload(name: str):
         # the benchmark beam with multiple scattering and loss fluctuations
         return geo, RunConfig(seed=7, process_mask=P_ALL | P_MSC | P_FLUCT), \
             beam(10_000, ELECTRON, 10_000.0, smear_rad=1e-3, seed=7)
+    if name in ("towers_1GeV_e-_x32", "towers_10GeV_e-_x10k"):
+        # 9 x 9 towers of the 50-layer sequence (8100 boxes, 1 mm cracks):
+        # impact points uniform over the central 3 x 3 towers and their cracks
+        n, e, seed = (32, 1000.0, 9) if name == "towers_1GeV_e-_x32" else (10_000, 10_000.0, 8)
+        p = beam(n, ELECTRON, e, smear_rad=1e-3, seed=seed)
+        rng = np.random.Generator(np.random.Philox(seed + 100))
+        p["pos"][:, 0] = rng.uniform(-60.0, 60.0, n)
+        p["pos"][:, 1] = rng.uniform(-60.0, 60.0, n)
+        return towers(), RunConfig(seed=seed), p
     # the same stack with the paper's lead tungstate absorber
     pbwo4 = calorimeter(absorber=LEAD_TUNGSTATE)
     if name == "calPbWO4_1GeV_e-_x32":

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 3u
+#define EMS_ABI_VERSION 4u
 
 typedef int32_t ems_status;
 enum {
@@ -108,15 +108,38 @@ typedef struct {
   double el_Z[4], el_A[4], el_atoms[4];
 } ems_material;
 
-/* Slab stack along z (the paper's 50-layer sampling calorimeter, section
- * 2.2): slab k spans [z_mm[k], z_mm[k+1]) and is made of material[k]. */
+/* Geometry, one of two kinds.
+ *
+ * Slab stack along z (the paper's 50-layer sampling calorimeter, section
+ * 2.2; n_boxes = 0): slab k spans [z_mm[k], z_mm[k+1]) and is made of
+ * material[k]; deposits are scored per slab (n_slabs columns).
+ *
+ * Boxes (n_boxes > 0; n_slabs = 0 and the slab fields unused): box v spans
+ * [box_lo[v], box_hi[v]] (x, y, z) and is made of box_material[v]; boxes may
+ * touch but not overlap and lie inside the world box [world_lo, world_hi],
+ * whose remaining volume is world_material; a track reaching the world's
+ * surface leaves the geometry.  A point on a face belongs to the box it
+ * moves into (per axis lo < p < hi, or p = lo moving with u >= 0, or p = hi
+ * moving with u < 0).  Navigation walks a bounding-volume hierarchy built at
+ * ems_create, the acceleration structure of the paper's geometry work
+ * (section 2.1), whose results equal a walk over all boxes.  Deposits are
+ * scored per volume: n_boxes + 1 columns, the world last.  No magnetic
+ * field (bz_tesla must be 0).  The volume index shares a 32-bit word with the
+ * track's step count: max_steps_per_track must stay below 2^(32 - b), b the
+ * bits of n_boxes + 2 (at least 12). */
 typedef struct {
-  uint32_t n_slabs;              /* 1 .. 4095                               */
+  uint32_t n_slabs;              /* 1 .. 4095 (0 with boxes)                */
   const double* z_mm;            /* host, n_slabs + 1 strictly increasing   */
   const uint32_t* material;      /* host, n_slabs indices < n_materials     */
   uint32_t n_materials;          /* 1 .. 4                                  */
   const ems_material* materials; /* host                                    */
   double half_xy_mm;             /* transverse extent [-H, H]^2, H > 0      */
+  uint32_t n_boxes;              /* 0: slab stack; 1 .. 2^24: boxes          */
+  const double* box_lo;          /* host, n_boxes x 3, mm                   */
+  const double* box_hi;          /* host, n_boxes x 3, lo < hi              */
+  const uint32_t* box_material;  /* host, n_boxes indices < n_materials     */
+  double world_lo[3], world_hi[3];
+  uint32_t world_material;
 } ems_geometry;
 
 typedef struct {
@@ -158,8 +181,8 @@ typedef struct {
 typedef struct {
   uint32_t event, species;
   double ekin_MeV;               /* kinetic energy; photon: total energy     */
-  double pos_mm[3];              /* inside the stack (on a plane: the slab
-                                    the direction enters)                    */
+  double pos_mm[3];              /* inside the geometry (on a plane or face:
+                                    the volume the direction enters)         */
   double dir[3];                 /* non-zero; normalised by the library      */
 } ems_primary;
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
@@ -46,7 +46,10 @@ class Material(C.Structure):
 
 class Geometry(C.Structure):
     _fields_ = [("n_slabs", C.c_uint32), ("z_mm", C.POINTER(C.c_double)), ("material", C.POINTER(C.c_uint32)),
-                ("n_materials", C.c_uint32), ("materials", C.POINTER(Material)), ("half_xy_mm", C.c_double)]
+                ("n_materials", C.c_uint32), ("materials", C.POINTER(Material)), ("half_xy_mm", C.c_double),
+                ("n_boxes", C.c_uint32), ("box_lo", C.POINTER(C.c_double)), ("box_hi", C.POINTER(C.c_double)),
+                ("box_material", C.POINTER(C.c_uint32)), ("world_lo", C.c_double * 3), ("world_hi", C.c_double * 3),
+                ("world_material", C.c_uint32)]
 
 
 class Config(C.Structure):
@@ -151,18 +154,30 @@ class _GeoHolder:
     """Keeps the arrays a Geometry struct points to alive."""
 
     def __init__(self, geometry):
-        self.z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
         self.mat = np.ascontiguousarray(geometry.material, dtype=np.uint32)
         self.mats = (Material * len(geometry.materials))(*[Material.of(m) for m in geometry.materials])
         g = Geometry()
-        g.n_slabs = len(self.mat)
-        g.z_mm = self.z.ctypes.data_as(C.POINTER(C.c_double))
-        g.material = self.mat.ctypes.data_as(C.POINTER(C.c_uint32))
+        if hasattr(geometry, "world_lo"):  # boxes
+            self.lo = np.ascontiguousarray(geometry.lo, dtype=np.float64)
+            self.hi = np.ascontiguousarray(geometry.hi, dtype=np.float64)
+            g.n_boxes = len(self.mat)
+            g.box_lo = self.lo.ctypes.data_as(C.POINTER(C.c_double))
+            g.box_hi = self.hi.ctypes.data_as(C.POINTER(C.c_double))
+            g.box_material = self.mat.ctypes.data_as(C.POINTER(C.c_uint32))
+            g.world_lo[:] = geometry.world_lo
+            g.world_hi[:] = geometry.world_hi
+            g.world_material = int(geometry.world_material)
+            self.n_slabs = len(self.mat) + 1  # deposit columns: boxes, then the world
+        else:
+            self.z = np.ascontiguousarray(geometry.z_mm, dtype=np.float64)
+            g.n_slabs = len(self.mat)
+            g.z_mm = self.z.ctypes.data_as(C.POINTER(C.c_double))
+            g.material = self.mat.ctypes.data_as(C.POINTER(C.c_uint32))
+            g.half_xy_mm = float(geometry.half_xy_mm)
+            self.n_slabs = len(self.mat)
         g.n_materials = len(geometry.materials)
         g.materials = self.mats
-        g.half_xy_mm = float(geometry.half_xy_mm)
         self.g = g
-        self.n_slabs = len(self.mat)
 
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,

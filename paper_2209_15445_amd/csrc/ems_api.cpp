@@ -33,6 +33,27 @@ ems_status fail(ems_status code, const std::string& msg) {
 }
 }  // namespace ems
 
+namespace ems {
+uint32_t n_cols(const ems_geometry* g) { return g->n_boxes ? g->n_boxes + 1 : g->n_slabs; }
+uint32_t vol_bits(const ems_geometry* g) {
+  uint32_t b = kSlabBits;
+  while (((1ull << b) - 1) <= n_cols(g)) ++b;  // the all-ones field is never a volume
+  return b;
+}
+BoxNav host_nav(const ems_geometry* g, const BvhHost& h) {
+  BoxNav n{};
+  n.node = h.node.data();
+  n.leaf = h.leaf.data();
+  n.box = h.box.data();
+  for (int k = 0; k < 3; ++k) {
+    n.wlo[k] = g->world_lo[k];
+    n.whi[k] = g->world_hi[k];
+  }
+  n.n_boxes = g->n_boxes;
+  return n;
+}
+}  // namespace ems
+
 namespace {
 
 constexpr uint64_t kAlign = 256;
@@ -41,19 +62,60 @@ constexpr uint32_t kInjectChunk = 1u << 18;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 
+// box geometry: finite boxes inside the world, known materials, no two
+// boxes sharing interior points (sweep over x), no field, step counts that
+// fit beside the volume index
+ems_status check_boxes(const ems_config* c, const ems_geometry* g) {
+  if (g->n_slabs != 0) return fail(EMS_E_INVALID, "a box geometry has no slabs (n_slabs = 0)");
+  if (g->n_boxes > kMaxBoxes || !g->box_lo || !g->box_hi || !g->box_material)
+    return fail(EMS_E_INVALID, "box geometry needs 1..2^24 boxes with bounds and materials");
+  if (g->world_material >= g->n_materials) return fail(EMS_E_INVALID, "world material index out of range");
+  for (int k = 0; k < 3; ++k)
+    if (!(g->world_lo[k] < g->world_hi[k]) || !isfinite(g->world_lo[k]) || !isfinite(g->world_hi[k]))
+      return fail(EMS_E_INVALID, "world box must be finite with lo < hi");
+  const double *lo = g->box_lo, *hi = g->box_hi;
+  for (uint32_t i = 0; i < g->n_boxes; ++i) {
+    if (g->box_material[i] >= g->n_materials) return fail(EMS_E_INVALID, "box material index out of range");
+    for (int k = 0; k < 3; ++k)
+      if (!(lo[3 * i + k] < hi[3 * i + k]) || !(lo[3 * i + k] >= g->world_lo[k]) || !(hi[3 * i + k] <= g->world_hi[k]))
+        return fail(EMS_E_INVALID, "box " + std::to_string(i) + " is empty or outside the world");
+  }
+  std::vector<uint32_t> order(g->n_boxes);
+  for (uint32_t i = 0; i < g->n_boxes; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lo[3 * a] < lo[3 * b]; });
+  for (uint32_t x = 0; x < g->n_boxes; ++x) {
+    const uint32_t i = order[x];
+    for (uint32_t y = x + 1; y < g->n_boxes && lo[3 * order[y]] < hi[3 * i]; ++y) {
+      const uint32_t j = order[y];
+      if (lo[3 * j + 1] < hi[3 * i + 1] && lo[3 * i + 1] < hi[3 * j + 1] && lo[3 * j + 2] < hi[3 * i + 2] &&
+          lo[3 * i + 2] < hi[3 * j + 2])
+        return fail(EMS_E_INVALID, "boxes " + std::to_string(i) + " and " + std::to_string(j) + " overlap");
+    }
+  }
+  if (c->bz_tesla != 0.0) return fail(EMS_E_INVALID, "box geometries take no magnetic field");
+  if ((uint64_t)c->max_steps_per_track >= (1ull << (32 - vol_bits(g))))
+    return fail(EMS_E_INVALID, "max_steps_per_track too large for this many boxes");
+  return EMS_OK;
+}
+
 ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (!c || !g) return fail(EMS_E_INVALID, "null config or geometry");
   if (c->abi_version != EMS_ABI_VERSION) return fail(EMS_E_VERSION, "abi_version mismatch");
   if (c->precision != EMS_FP64 && c->precision != EMS_MIXED) return fail(EMS_E_INVALID, "precision must be EMS_FP64 or EMS_MIXED");
-  if (g->n_slabs < 1 || g->n_slabs > kMaxSlabs || !g->z_mm || !g->material)
-    return fail(EMS_E_INVALID, "geometry needs 1..4095 slabs with planes and materials");
   if (g->n_materials < 1 || g->n_materials > 4 || !g->materials)
     return fail(EMS_E_INVALID, "geometry needs 1..4 materials");
-  if (!(g->half_xy_mm > 0.0) || !isfinite(g->half_xy_mm)) return fail(EMS_E_INVALID, "half_xy_mm must be > 0");
-  for (uint32_t i = 0; i < g->n_slabs; ++i) {
-    if (!(g->z_mm[i + 1] > g->z_mm[i]) || !isfinite(g->z_mm[i + 1]) || !isfinite(g->z_mm[i]))
-      return fail(EMS_E_INVALID, "z planes must be finite and strictly increasing");
-    if (g->material[i] >= g->n_materials) return fail(EMS_E_INVALID, "slab material index out of range");
+  if (g->n_boxes) {
+    ems_status bs = check_boxes(c, g);
+    if (bs) return bs;
+  } else {
+    if (g->n_slabs < 1 || g->n_slabs > kMaxSlabs || !g->z_mm || !g->material)
+      return fail(EMS_E_INVALID, "geometry needs 1..4095 slabs with planes and materials");
+    if (!(g->half_xy_mm > 0.0) || !isfinite(g->half_xy_mm)) return fail(EMS_E_INVALID, "half_xy_mm must be > 0");
+    for (uint32_t i = 0; i < g->n_slabs; ++i) {
+      if (!(g->z_mm[i + 1] > g->z_mm[i]) || !isfinite(g->z_mm[i + 1]) || !isfinite(g->z_mm[i]))
+        return fail(EMS_E_INVALID, "z planes must be finite and strictly increasing");
+      if (g->material[i] >= g->n_materials) return fail(EMS_E_INVALID, "slab material index out of range");
+    }
   }
   for (uint32_t i = 0; i < g->n_materials; ++i) {
     const ems_material& m = g->materials[i];
@@ -120,16 +182,20 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   // photon block, then lepton block (8-byte aligned between them)
   L.tab = take((g->n_materials * kGammaTables * nodes * real_bytes(c) + 7) / 8 * 8 +
                g->n_materials * kLeptonTables * nodes * real_bytes(c));
-  L.zp = take((g->n_slabs + 1) * 8ull);
-  L.smat = take(g->n_slabs * 4ull);
+  L.zp = take(g->n_boxes ? 0 : (g->n_slabs + 1) * 8ull);
+  L.smat = take(n_cols(g) * 4ull);  // material per volume
+  // box hierarchy: at most 2 n - 1 nodes, leaf ids, bounds by box
+  L.bvh = take(g->n_boxes ? (2ull * g->n_boxes) * sizeof(BvhNode) : 0);
+  L.bleaf = take(g->n_boxes * 4ull);
+  L.bbox = take(g->n_boxes * 48ull);
   L.mat = take(g->n_materials * sizeof(MatRT));
   L.elem = take(elem_bytes(c, g));
-  L.edep = take((uint64_t)c->max_events * g->n_slabs * 8);
+  L.edep = take((uint64_t)c->max_events * n_cols(g) * 8);
   L.ledger = take((uint64_t)c->max_events * sizeof(LedgerDev));
   L.live = take((uint64_t)c->max_events * 4);
   const bool server = (c->flags & EMS_F_EVENT_LIVE) != 0;
   L.rows = take(server ? (uint64_t)c->max_events * 4 : 0);
-  L.gather = take(server ? (uint64_t)c->max_events * (g->n_slabs * 8ull + sizeof(LedgerDev)) : 0);
+  L.gather = take(server ? (uint64_t)c->max_events * (n_cols(g) * 8ull + sizeof(LedgerDev)) : 0);
   L.exits = take(c->exit_capacity * sizeof(ExitRec));
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
@@ -164,7 +230,7 @@ TableSet tables_for(const ems_config* c, const ems_geometry* g) {
 StepEnv<double> env_for(const ems_config* c, const ems_geometry* g, const TableSet& ts) {
   StepEnv<double> e{};
   e.nodes = ts.nodes;
-  e.n_slabs = g->n_slabs;
+  e.n_slabs = n_cols(g);  // deposit columns (slabs, or boxes + world)
   e.lnemin = ts.lnemin;
   e.dlog = ts.dlog;
   e.inv_dlog = 1.0 / ts.dlog;
@@ -197,14 +263,19 @@ int32_t locate(const double* z, uint32_t n, double zz, double uz) {
 
 // validate and convert primaries; ids are running indices per row, keys
 // the rows' event keys
-ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary* p, uint64_t n,
+ems_status prepare(const ems_geometry& g, const BoxNav* nav, uint32_t max_events, const ems_primary* p, uint64_t n,
                    std::vector<uint64_t>& row_count, const std::vector<uint32_t>& keys, std::vector<InjRec>& out) {
   for (uint64_t i = 0; i < n; ++i) {
     const ems_primary& q = p[i];
     const double d2 = q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2];
-    const bool ok = q.event < max_events && q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && isfinite(q.ekin_MeV) &&
-                    d2 > 0.0 && isfinite(d2) && q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] &&
-                    fabs(q.pos_mm[0]) <= g.half_xy_mm && fabs(q.pos_mm[1]) <= g.half_xy_mm;
+    bool ok = q.event < max_events && q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && isfinite(q.ekin_MeV) &&
+              d2 > 0.0 && isfinite(d2);
+    if (ok && g.n_boxes)
+      ok = isfinite(q.pos_mm[0]) && isfinite(q.pos_mm[1]) && isfinite(q.pos_mm[2]) &&
+           bvh_locate(*nav, q.pos_mm, q.dir) >= 0;
+    else if (ok)
+      ok = q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] && fabs(q.pos_mm[0]) <= g.half_xy_mm &&
+           fabs(q.pos_mm[1]) <= g.half_xy_mm;
     if (!ok) return fail(EMS_E_INVALID, "invalid primary #" + std::to_string(i));
   }
   out.resize(n);
@@ -221,7 +292,12 @@ ems_status prepare(const ems_geometry& g, uint32_t max_events, const ems_primary
     r.E = q.ekin_MeV;
     r.ev = q.event;
     r.sp = q.species;
-    r.slab = locate(g.z_mm, g.n_slabs, r.z, r.uz);
+    if (g.n_boxes) {
+      const double pp[3] = {r.x, r.y, r.z}, uu[3] = {r.ux, r.uy, r.uz};
+      r.slab = bvh_locate(*nav, pp, uu);
+    } else {
+      r.slab = locate(g.z_mm, g.n_slabs, r.z, r.uz);
+    }
     r.id = row_count[q.event]++;
     r.key = keys[q.event];
   }
@@ -272,7 +348,7 @@ void pack_elements(const TableSet& ts, std::vector<char>& out) {
   for (size_t i = 0; i < ts.el.size(); ++i) t[i] = (R)ts.el[i];
 }
 
-template <class R>
+template <class R, int GEO>
 ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const ems_primary* prim, uint64_t n,
                           uint32_t n_events, const uint32_t* keys, double* edep, ems_ledger* ledger,
                           ems_step_record* log, uint64_t log_cap, uint64_t* log_n);
@@ -317,13 +393,32 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   if (bytes < L.total) return fail(EMS_E_CAPACITY, "workspace smaller than ems_workspace_bytes");
   ems_ctx* c = new ems_ctx();
   c->cfg = *cfg;
-  c->z.assign(geo->z_mm, geo->z_mm + geo->n_slabs + 1);
-  c->smat.assign(geo->material, geo->material + geo->n_slabs);
   c->mats.assign(geo->materials, geo->materials + geo->n_materials);
   c->geo = *geo;
-  c->geo.z_mm = c->z.data();
-  c->geo.material = c->smat.data();
+  if (geo->n_boxes) {
+    c->blo.assign(geo->box_lo, geo->box_lo + 3ull * geo->n_boxes);
+    c->bhi.assign(geo->box_hi, geo->box_hi + 3ull * geo->n_boxes);
+    c->smat.assign(geo->box_material, geo->box_material + geo->n_boxes);
+    c->smat.push_back(geo->world_material);  // material per volume, the world last
+    c->geo.box_lo = c->blo.data();
+    c->geo.box_hi = c->bhi.data();
+    c->geo.box_material = c->smat.data();
+    c->geo.z_mm = nullptr;
+    c->geo.material = nullptr;
+    std::string err;
+    if (!build_bvh(c->blo.data(), c->bhi.data(), geo->n_boxes, c->bvh, err)) {
+      delete c;
+      return fail(EMS_E_INVALID, err);
+    }
+    c->nav = host_nav(&c->geo, c->bvh);
+  } else {
+    c->z.assign(geo->z_mm, geo->z_mm + geo->n_slabs + 1);
+    c->smat.assign(geo->material, geo->material + geo->n_slabs);
+    c->geo.z_mm = c->z.data();
+    c->geo.material = c->smat.data();
+  }
   c->geo.materials = c->mats.data();
+  c->ncols = n_cols(geo);
   c->ts = tables_for(cfg, geo);
   c->L = L;
   c->ws = static_cast<char*>(d_ws);
@@ -339,7 +434,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
     return bad(fail(EMS_E_DEVICE, "no HIP device"));
   c->device = dev;
   const uint64_t nodes = cfg->n_bins + 1;
-  const uint32_t common = (uint32_t)((geo->n_slabs + 1) * 8 + geo->n_materials * sizeof(MatRT) + geo->n_slabs * 4 + 64);
+  const uint32_t staged = geo->n_boxes ? 0u : geo->n_slabs;  // box geometries keep planes and materials global
+  const uint32_t common = (uint32_t)((geo->n_boxes ? 0u : staged + 1) * 8 + geo->n_materials * sizeof(MatRT) + staged * 4 + 64);
   const uint64_t rb = real_bytes(cfg);
   const uint64_t gbytes = (geo->n_materials * kGammaTables * nodes * rb + 7) / 8 * 8;
   const uint64_t lbytes = (geo->n_materials * kLeptonTables * nodes * rb + 7) / 8 * 8;
@@ -376,6 +472,15 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.refill_below = cfg->refill_below;
   a.precision = cfg->precision == EMS_MIXED ? 1u : 0u;
   a.env = env_for(cfg, geo, c->ts);
+  a.geo = geo->n_boxes ? 1u : 0u;
+  a.vol_bits = vol_bits(geo);
+  if (geo->n_boxes) {
+    // device view of the hierarchy (same layout as the host one)
+    a.env.nav = c->nav;
+    a.env.nav.node = reinterpret_cast<const BvhNode*>(c->ws + L.bvh);
+    a.env.nav.leaf = reinterpret_cast<const uint32_t*>(c->ws + L.bleaf);
+    a.env.nav.box = reinterpret_cast<const double*>(c->ws + L.bbox);
+  }
   int per_g = 0, per_l = 0;
   if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
     return bad(fail(EMS_E_DEVICE, "cannot configure the visit kernels"));
@@ -405,7 +510,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   c->keys.resize(cfg->max_events);
   for (uint32_t i = 0; i < cfg->max_events; ++i) c->keys[i] = i;
   if (cfg->flags & EMS_F_EVENT_LIVE) {
-    const uint64_t gb = (uint64_t)cfg->max_events * (geo->n_slabs * 8ull + sizeof(LedgerDev));
+    const uint64_t gb = (uint64_t)cfg->max_events * (n_cols(geo) * 8ull + sizeof(LedgerDev));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_rows), cfg->max_events * 4ull) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->pin_gather), gb) != hipSuccess)
       return bad(fail(EMS_E_DEVICE, "pinned host allocation failed"));
@@ -413,7 +518,15 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   hipStream_t s = c->stream;
   bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
-            hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+            (c->z.empty() ||
+             hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess) &&
+            (c->bvh.node.empty() ||
+             (hipMemcpyAsync(c->ws + L.bvh, c->bvh.node.data(), c->bvh.node.size() * sizeof(BvhNode),
+                             hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ws + L.bleaf, c->bvh.leaf.data(), c->bvh.leaf.size() * 4, hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(c->ws + L.bbox, c->bvh.box.data(), c->bvh.box.size() * 8, hipMemcpyHostToDevice, s) ==
+                  hipSuccess)) &&
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
@@ -484,7 +597,7 @@ ems_status ems_read_edep(ems_ctx* c, uint32_t first, uint32_t n, double* out) {
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   if (!out || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
-  const uint64_t row = c->geo.n_slabs * 8ull;
+  const uint64_t row = c->ncols * 8ull;
   HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.edep + first * row, n * row, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return EMS_OK;
@@ -496,13 +609,13 @@ ems_status ems_read_ledger(ems_ctx* c, uint32_t first, uint32_t n, ems_ledger* o
   if (!out || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
   HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.ledger + first * sizeof(LedgerDev), n * sizeof(LedgerDev),
                            hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> ed((size_t)n * c->geo.n_slabs);
-  const uint64_t row = c->geo.n_slabs * 8ull;
+  std::vector<double> ed((size_t)n * c->ncols);
+  const uint64_t row = c->ncols * 8ull;
   HIPCHK(c, hipMemcpyAsync(ed.data(), c->ws + c->L.edep + first * row, n * row, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (uint32_t i = 0; i < n; ++i) {
     double s = 0.0;
-    for (uint32_t k = 0; k < c->geo.n_slabs; ++k) s += ed[(size_t)i * c->geo.n_slabs + k];
+    for (uint32_t k = 0; k < c->ncols; ++k) s += ed[(size_t)i * c->ncols + k];
     out[i].edep = s;
   }
   return EMS_OK;
@@ -512,7 +625,7 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   const Layout& L = c->L;
-  HIPCHK(c, hipMemsetAsync(c->ws + L.edep, 0, (uint64_t)c->cfg.max_events * c->geo.n_slabs * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ws + L.edep, 0, (uint64_t)c->cfg.max_events * c->ncols * 8, c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + L.ledger, 0, (uint64_t)c->cfg.max_events * sizeof(LedgerDev), c->stream));
   HIPCHK(c, hipMemsetAsync(c->ws + L.live, 0, (uint64_t)c->cfg.max_events * 4, c->stream));
   if (c->args.profile_cap)
@@ -596,9 +709,14 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
   ems_status st = check_inputs(&c2, geo);
   if (st) return st;
   if (!edep || !ledger || (n && !prim)) return fail(EMS_E_INVALID, "null buffers");
+  if (geo->n_boxes) {
+    if (c2.precision == EMS_MIXED)
+      return host_transport<float, 1>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+    return host_transport<double, 1>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+  }
   if (c2.precision == EMS_MIXED)
-    return host_transport<float>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
-  return host_transport<double>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+    return host_transport<float, 0>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
+  return host_transport<double, 0>(c2, geo, prim, n, n_events, keys, edep, ledger, log, log_cap, log_n);
 }
 
 }  // extern "C"
@@ -606,7 +724,7 @@ ems_status ems_debug_host_transport(const ems_config* cfg, const ems_geometry* g
 namespace {
 
 // Breadth-first host loop over the same step code as the kernels (test hook).
-template <class R>
+template <class R, int GEO>
 ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const ems_primary* prim, uint64_t n,
                           uint32_t n_events, const uint32_t* keys, double* edep, ems_ledger* ledger,
                           ems_step_record* log, uint64_t log_cap, uint64_t* log_n) {
@@ -620,8 +738,20 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
   const size_t gb = (geo->n_materials * kGammaTables * ts.nodes * sizeof(R) + 7) / 8 * 8;
   env.tg = reinterpret_cast<const R*>(packed.data());
   env.tl = reinterpret_cast<const R*>(packed.data() + gb);
-  env.zplane = geo->z_mm;
-  env.slab_mat = geo->material;
+  std::vector<uint32_t> vmat;
+  BvhHost bvh;
+  if (geo->n_boxes) {
+    std::string err;
+    if (!build_bvh(geo->box_lo, geo->box_hi, geo->n_boxes, bvh, err)) return fail(EMS_E_INVALID, err);
+    env.nav = host_nav(geo, bvh);
+    vmat.assign(geo->box_material, geo->box_material + geo->n_boxes);
+    vmat.push_back(geo->world_material);
+    env.zplane = nullptr;
+    env.slab_mat = vmat.data();
+  } else {
+    env.zplane = geo->z_mm;
+    env.slab_mat = geo->material;
+  }
   env.mat = rt.data();
   std::vector<char> elem;
   pack_elements<R>(ts, elem);
@@ -631,9 +761,10 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
   std::vector<uint32_t> row_keys(n_events);
   for (uint32_t e = 0; e < n_events; ++e) row_keys[e] = keys ? keys[e] : e;
   std::vector<InjRec> recs;
-  ems_status st = prepare(*geo, n_events, prim, n, rows, row_keys, recs);
+  ems_status st = prepare(*geo, &env.nav, n_events, prim, n, rows, row_keys, recs);
   if (st) return st;
-  memset(edep, 0, sizeof(double) * n_events * geo->n_slabs);
+  const uint32_t nc = n_cols(geo);
+  memset(edep, 0, sizeof(double) * n_events * nc);
   memset(ledger, 0, sizeof(ems_ledger) * n_events);
   std::vector<Trk<R>> cur[3], nxt[3];
   for (const InjRec& r : recs) {
@@ -648,7 +779,7 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
     uint64_t log_cap, nlog;
     void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e0) {
       ems_ledger& L = ledger[t.ev];
-      edep[(size_t)t.ev * geo->n_slabs + o.slab] += o.dep;
+      edep[(size_t)t.ev * n_cols(geo) + o.slab] += o.dep;
       L.escaped[sp] += o.escaped;
       L.killed += o.killed;
       L.charged_len += o.clen;
@@ -687,7 +818,7 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
         visit_begin<2>(env, sp, t, vs);
         for (;;) {
           const double e0 = t.E;
-          const bool end = visit_step<2>(env, sp, vs, t, o, max_visit);
+          const bool end = visit_step<2, R, GEO>(env, sp, vs, t, o, max_visit);
           if (o.pending) interact<2>(env, t, o);
           sink.apply(sp, t, o, e0);
           if (end) break;
@@ -707,7 +838,7 @@ ems_status host_transport(const ems_config& c2, const ems_geometry* geo, const e
   const uint64_t nlog = sink.nlog;
   for (uint32_t e = 0; e < n_events; ++e) {
     double s = 0.0;
-    for (uint32_t k = 0; k < geo->n_slabs; ++k) s += edep[(size_t)e * geo->n_slabs + k];
+    for (uint32_t k = 0; k < nc; ++k) s += edep[(size_t)e * nc + k];
     ledger[e].edep = s;
   }
   if (log_n) *log_n = nlog;
@@ -728,7 +859,7 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
     if (c->pending[s] + add[s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
   std::vector<uint64_t> rows = c->row_count;
   std::vector<InjRec> recs;
-  ems_status st = prepare(c->geo, c->cfg.max_events, p, n, rows, c->keys, recs);
+  ems_status st = prepare(c->geo, &c->nav, c->cfg.max_events, p, n, rows, c->keys, recs);
   if (st) return st;
   for (uint64_t done = 0; done < n; done += kInjectChunk) {
     const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
@@ -865,18 +996,18 @@ ems_status rt_gather_rows(ems_ctx* c, const uint32_t* rows, uint32_t n, double* 
   HIPCHK(c, hipStreamSynchronize(c->stream));
   memcpy(c->pin_rows, rows, n * 4ull);
   uint32_t* d = reinterpret_cast<uint32_t*>(c->ws + c->L.rows);
-  const size_t stride = c->geo.n_slabs * 8ull + sizeof(LedgerDev);
+  const size_t stride = c->ncols * 8ull + sizeof(LedgerDev);
   HIPCHK(c, hipMemcpyAsync(d, c->pin_rows, n * 4ull, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_gather_rows(c->args, d, n, c->ws + c->L.gather, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->pin_gather, c->ws + c->L.gather, n * stride, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (uint32_t i = 0; i < n; ++i) {
     const char* src = c->pin_gather + i * stride;
-    double* e = edep + (size_t)i * c->geo.n_slabs;
-    memcpy(e, src, c->geo.n_slabs * 8ull);
-    memcpy(&ledger[i], src + c->geo.n_slabs * 8ull, sizeof(LedgerDev));
+    double* e = edep + (size_t)i * c->ncols;
+    memcpy(e, src, c->ncols * 8ull);
+    memcpy(&ledger[i], src + c->ncols * 8ull, sizeof(LedgerDev));
     double sum = 0.0;
-    for (uint32_t k = 0; k < c->geo.n_slabs; ++k) sum += e[k];
+    for (uint32_t k = 0; k < c->ncols; ++k) sum += e[k];
     ledger[i].edep = sum;
   }
   return EMS_OK;

@@ -7,12 +7,14 @@ namespace ems {
 
 // One species queue buffer, structure of arrays: position and energy in
 // FP64, 64-bit id, direction in the arithmetic type R, then event row, RNG
-// event key, and step count and slab packed in one word (n << 12 | slab;
-// all ones marks a dead slot).  76 bytes per track in the FP64 form, 64 in
-// the mixed form.  The six buffers (2 x 3 species) are consecutive blocks of
-// cap * track_bytes.
+// event key, and step count and volume packed in one word (n << b | volume,
+// b = 12 for the slab stack, more for a large box geometry; all ones marks a
+// dead slot).  76 bytes per track in the FP64 form, 64 in the mixed form.
+// The six buffers (2 x 3 species) are consecutive blocks of cap *
+// track_bytes.
 constexpr uint32_t kSlabBits = 12, kSlabMask = (1u << kSlabBits) - 1;
 constexpr uint32_t kMaxSlabs = kSlabMask;                 // slab indices 0..4094
+constexpr uint32_t kMaxBoxes = 1u << 24;
 constexpr uint32_t kMaxStepsPerTrack = (1u << 20) - 1;    // step counts fit 20 bits
 constexpr uint32_t kDeadRecord = 0xFFFFFFFFu;
 template <class R>
@@ -142,6 +144,8 @@ struct KArgs {
   uint32_t waves_g, waves_l;  // waves of the photon and of the e-/e+ launch
   ExitRec* exits;             // outgoing tracks (exit_cap records)
   uint64_t exit_cap;
+  uint32_t geo;               // geometry kind: 0 slab stack, 1 boxes
+  uint32_t vol_bits;          // low bits of the packed word that hold the volume
   StepEnv<double> env;  // scalars; its pointers are set per block
 };
 

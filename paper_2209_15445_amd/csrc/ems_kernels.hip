@@ -184,7 +184,7 @@ __device__ inline void wave_count(uint32_t* counter, uint32_t v) {
 }
 
 template <class R>
-__device__ inline void store_track(const Queue<R>& q, uint32_t i, const Trk<R>& t) {
+__device__ inline void store_track(const Queue<R>& q, uint32_t i, const Trk<R>& t, uint32_t vb) {
   q.x[i] = t.x;
   q.y[i] = t.y;
   q.z[i] = t.z;
@@ -195,7 +195,7 @@ __device__ inline void store_track(const Queue<R>& q, uint32_t i, const Trk<R>& 
   q.id[i] = t.id;
   q.ev[i] = t.ev;
   q.key[i] = t.key;
-  q.ns[i] = (t.n << kSlabBits) | (uint32_t)t.slab;
+  q.ns[i] = (t.n << vb) | (uint32_t)t.slab;
 }
 
 // position of the idx-th track of a queue with `home` tracks in the bottom
@@ -293,7 +293,7 @@ struct DevSink {
 
 // Stage a table block, the slab planes, slab materials and material
 // constants in LDS; returns the environment pointing there.
-template <class R>
+template <class R, int GEO>
 __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
   const uint32_t nt = photons ? kGammaTables : kLeptonTables;
   const uint32_t ntab = a.n_mat * nt * a.env.nodes;
@@ -301,20 +301,22 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
   R* lds = reinterpret_cast<R*>(lds_bytes);
   for (uint32_t i = threadIdx.x; i < ntab; i += kBlock) lds[i] = src[i];
   double* zp = reinterpret_cast<double*>(lds_bytes + (ntab * sizeof(R) + 7) / 8 * 8);
-  for (uint32_t i = threadIdx.x; i <= a.env.n_slabs; i += kBlock) zp[i] = a.zplane[i];
-  MatRT* mr = reinterpret_cast<MatRT*>(zp + a.env.n_slabs + 1);
+  // a box geometry reads its volume materials from global memory
+  const uint32_t nz = GEO == 1 ? 0u : a.env.n_slabs + 1, nsm = GEO == 1 ? 0u : a.env.n_slabs;
+  for (uint32_t i = threadIdx.x; i < nz; i += kBlock) zp[i] = a.zplane[i];
+  MatRT* mr = reinterpret_cast<MatRT*>(zp + nz);
   if (threadIdx.x < a.n_mat) mr[threadIdx.x] = a.mat[threadIdx.x];
   uint32_t* sm = reinterpret_cast<uint32_t*>(mr + a.n_mat);
-  for (uint32_t i = threadIdx.x; i < a.env.n_slabs; i += kBlock) sm[i] = a.slab_mat[i];
+  for (uint32_t i = threadIdx.x; i < nsm; i += kBlock) sm[i] = a.slab_mat[i];
   __syncthreads();
   StepEnv<R> env = retype<R>(a.env);
   env.tg = photons ? lds : nullptr;
   env.tl = photons ? nullptr : lds;
-  env.zplane = zp;
+  env.zplane = GEO == 1 ? nullptr : zp;
   env.mat = mr;
   env.elc = a.el_c;
   env.elt = static_cast<const R*>(a.el_tab);
-  env.slab_mat = sm;
+  env.slab_mat = GEO == 1 ? a.slab_mat : sm;
   return env;
 }
 
@@ -348,7 +350,7 @@ constexpr int visit_waves() {
   return sizeof(R) == 8 ? (PHOTONS ? EMS_WAVES_F64_PHOTON : EMS_WAVES_F64_LEPTON)
                         : (PHOTONS ? EMS_WAVES_F32_PHOTON : EMS_WAVES_F32_LEPTON);
 }
-template <bool PHOTONS, class R>
+template <bool PHOTONS, class R, int GEO>
 __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(KArgs a) {
   extern __shared__ double lds_words[];
   char* lds = reinterpret_cast<char*>(lds_words);
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
   constexpr int KIND = PHOTONS ? 0 : 1;
 
   if (work) {
-    const StepEnv<R> env = stage<R>(a, lds, PHOTONS);
+    const StepEnv<R> env = stage<R, GEO>(a, lds, PHOTONS);
     const uint32_t nxt = cur ^ 1u;
     const int max_visit = (int)a.steps_per_visit;
     // secondary slots per species that leave room for all survivors
@@ -438,8 +440,8 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
         // from waiting on those stores (vector memory completes in order)
         __builtin_amdgcn_s_waitcnt(kWaitVmem);
         bool take = got && nw != kDeadRecord;  // dead: refused secondary or unused chunk end
-        nt.slab = (int32_t)(nw & kSlabMask);
-        nt.n = nw >> kSlabBits;
+        nt.slab = (int32_t)(nw & ((1u << a.vol_bits) - 1u));
+        nt.n = nw >> a.vol_bits;
         // a record that would index outside the tallies or the slab stack
         // is reported, never used
         if (take && (nt.slab >= (int32_t)a.env.n_slabs || nt.ev >= a.max_events)) {
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
                   c.key = t.key;
                   c.n = 0;
                   c.slab = o.slab;
-                  store_track(dq, ps, c);
+                  store_track(dq, ps, c, a.vol_bits);
                 } else {
                   dq.ns[ps] = kDeadRecord;  // refused: the next iteration skips this slot
                 }
@@ -534,8 +536,8 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
             if (hs >= a.cap) {
               atomicOr(&ctl->error, kErrOverflow);
             } else {
-              if (carry) store_track(dq, hs, before);
-              else store_track(dq, hs, t);
+              if (carry) store_track(dq, hs, before, a.vol_bits);
+              else store_track(dq, hs, t, a.vol_bits);
               if (sp == 2) ++kept_b;
               else ++kept_a;
             }
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
       if (has && !fin) {
         before = t;
         const double e0 = t.E;
-        fin = visit_step<KIND>(env, sp, vs, t, o, max_visit);
+        fin = visit_step<KIND, R, GEO>(env, sp, vs, t, o, max_visit);
         held = o.pending;
         if (!held) {
           sink.apply(sp, t, o, e0);
@@ -714,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_inject(KArgs a, const InjRec* rec, u
       t.key = r.key;
       t.n = 0;
       t.slab = r.slab;
-      store_track(queue_view<R>(a.qbase, a.cap, cur, (uint32_t)qs), slot, t);
+      store_track(queue_view<R>(a.qbase, a.cap, cur, (uint32_t)qs), slot, t, a.vol_bits);
       if (a.flags & kFlagEventLive) atomicAdd(&a.live_ev[r.ev], 1);
     }
   }
@@ -765,14 +767,19 @@ __global__ void k_census(KArgs a) {
 }
 
 // one iteration is the photon launch followed by the e-/e+ launch
-hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
+template <int GEO>
+void launch_visit_g(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
   if (photons) {
-    if (a.precision) hipLaunchKernelGGL((k_visit<true, float>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
-    else hipLaunchKernelGGL((k_visit<true, double>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
+    if (a.precision) hipLaunchKernelGGL((k_visit<true, float, GEO>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
+    else hipLaunchKernelGGL((k_visit<true, double, GEO>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
   } else {
-    if (a.precision) hipLaunchKernelGGL((k_visit<false, float>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
-    else hipLaunchKernelGGL((k_visit<false, double>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
+    if (a.precision) hipLaunchKernelGGL((k_visit<false, float, GEO>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
+    else hipLaunchKernelGGL((k_visit<false, double, GEO>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
   }
+}
+hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
+  if (a.geo == 1) launch_visit_g<1>(a, photons, blocks, s);
+  else launch_visit_g<0>(a, photons, blocks, s);
   return hipGetLastError();
 }
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
@@ -797,21 +804,24 @@ hipError_t launch_census(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 // blocks of each visit kernel that fit on one CU (registers and LDS)
-template <class R>
+template <class R, int GEO>
 hipError_t visit_occupancy_r(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true, R>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true, R, GEO>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false, R>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false, R, GEO>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true, R>, kBlock, a.lds_g);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true, R, GEO>, kBlock, a.lds_g);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false, R>, kBlock, a.lds_l);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false, R, GEO>, kBlock, a.lds_l);
 }
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  return a.precision ? visit_occupancy_r<float>(a, per_cu_g, per_cu_l)
-                     : visit_occupancy_r<double>(a, per_cu_g, per_cu_l);
+  if (a.geo == 1)
+    return a.precision ? visit_occupancy_r<float, 1>(a, per_cu_g, per_cu_l)
+                       : visit_occupancy_r<double, 1>(a, per_cu_g, per_cu_l);
+  return a.precision ? visit_occupancy_r<float, 0>(a, per_cu_g, per_cu_l)
+                     : visit_occupancy_r<double, 0>(a, per_cu_g, per_cu_l);
 }
 
 }  // namespace ems

@@ -8,6 +8,7 @@
 
 #include "../../include/ems.h"
 #include "ems_device.hpp"
+#include "ems_geometry.hpp"
 
 namespace ems {
 
@@ -20,12 +21,18 @@ hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
-  uint64_t ctl, tab, zp, smat, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
+  uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t cap;
 };
 
 // bytes of one queued track in the configured form
 uint64_t queue_track_bytes(const ems_config* c);
+// deposit columns of a geometry (slabs, or boxes + world) and the bits of
+// the packed queue word that hold the volume
+uint32_t n_cols(const ems_geometry* g);
+uint32_t vol_bits(const ems_geometry* g);
+// host view of a box hierarchy
+BoxNav host_nav(const ems_geometry* g, const BvhHost& h);
 
 // sets the calling thread's error text and returns code
 ems_status fail(ems_status code, const std::string& msg);
@@ -41,7 +48,11 @@ struct ems_ctx {
   int device = 0;
   ems_config cfg;
   std::vector<double> z;
-  std::vector<uint32_t> smat;
+  std::vector<uint32_t> smat;   // material per volume
+  std::vector<double> blo, bhi;  // box geometry bounds
+  ems::BvhHost bvh;
+  ems::BoxNav nav{};             // host view of bvh
+  uint32_t ncols = 0;            // deposit columns
   std::vector<ems_material> mats;
   ems_geometry geo;
   TableSet ts;

@@ -182,15 +182,15 @@ void ems_server::run() {
       const uint32_t nf = (uint32_t)finished.size();
       std::vector<uint32_t> rows(nf);
       for (uint32_t i = 0; i < nf; ++i) rows[i] = (uint32_t)finished[i]->slot;
-      std::vector<double> edep((size_t)nf * ctx->geo.n_slabs);
+      std::vector<double> edep((size_t)nf * ctx->ncols);
       std::vector<ems_ledger> led(nf);
       if (rt_gather_rows(ctx, rows.data(), nf, edep.data(), led.data())) {
         fail_all(std::string("result read-back failed: ") + ems_last_error());
         return;
       }
       for (uint32_t i = 0; i < nf; ++i) {
-        finished[i]->edep.assign(edep.begin() + (size_t)i * ctx->geo.n_slabs,
-                                 edep.begin() + (size_t)(i + 1) * ctx->geo.n_slabs);
+        finished[i]->edep.assign(edep.begin() + (size_t)i * ctx->ncols,
+                                 edep.begin() + (size_t)(i + 1) * ctx->ncols);
         finished[i]->ledger = led[i];
       }
     }
@@ -248,9 +248,14 @@ ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t 
     ems_primary& q = r->tracks[i];
     q.event = 0;
     const double d2 = q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2];
-    const bool ok = q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && std::isfinite(q.ekin_MeV) && d2 > 0.0 &&
-                    std::isfinite(d2) && q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] &&
-                    std::fabs(q.pos_mm[0]) <= g.half_xy_mm && std::fabs(q.pos_mm[1]) <= g.half_xy_mm;
+    bool ok = q.species <= EMS_POSITRON && q.ekin_MeV > 0.0 && std::isfinite(q.ekin_MeV) && d2 > 0.0 &&
+              std::isfinite(d2);
+    if (ok && g.n_boxes)
+      ok = std::isfinite(q.pos_mm[0]) && std::isfinite(q.pos_mm[1]) && std::isfinite(q.pos_mm[2]) &&
+           bvh_locate(s->ctx->nav, q.pos_mm, q.dir) >= 0;
+    else if (ok)
+      ok = q.pos_mm[2] >= g.z_mm[0] && q.pos_mm[2] <= g.z_mm[g.n_slabs] && std::fabs(q.pos_mm[0]) <= g.half_xy_mm &&
+           std::fabs(q.pos_mm[1]) <= g.half_xy_mm;
     if (!ok) return fail(EMS_E_INVALID, "invalid track #" + std::to_string(i));
     r->add[q.species] += 1;
     etot += q.ekin_MeV;

@@ -14,6 +14,7 @@
 // helix and every energy (track, deposit, secondaries) stay FP64, so energy
 // bookkeeping is exact in both forms.
 #pragma once
+#include "ems_geometry.hpp"
 #include "ems_models.hpp"
 #include "ems_tables.hpp"
 
@@ -33,6 +34,7 @@ struct StepEnv {
   const double* zplane;      // n_slabs + 1
   const uint32_t* slab_mat;  // n_slabs
   const MatRT* mat;
+  BoxNav nav;                // box geometry (geometry kind 1)
   const double* elc;         // element screening constants [mat][4][2]
   const R* elt;              // partial pair / brems totals [mat][4][2][nodes]
   uint32_t nodes, n_slabs;
@@ -58,6 +60,7 @@ EMS_HD StepEnv<R> retype(const StepEnv<S>& a) {
   e.zplane = a.zplane;
   e.slab_mat = a.slab_mat;
   e.mat = a.mat;
+  e.nav = a.nav;
   e.elc = a.elc;
   e.elt = nullptr;
   e.nodes = a.nodes;
@@ -191,6 +194,31 @@ EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o, bool up
   }
 }
 
+// Geometry kinds: 0 = the slab stack, 1 = boxes (see ems_geometry.hpp).
+// Box geometry: distance to the next boundary and the face reached.
+template <class R>
+EMS_HD double box_dist(const StepEnv<R>& e, const Trk<R>& t, Face& fc) {
+  const double p[3] = {t.x, t.y, t.z}, u[3] = {(double)t.ux, (double)t.uy, (double)t.uz};
+  return box_distance(e.nav, t.slab, p, u, fc);
+}
+// on the face reached, into the volume the track moves into, or out
+template <class R>
+EMS_HD void box_land(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o, const Face& fc) {
+  double p[3] = {t.x, t.y, t.z};
+  const double u[3] = {(double)t.ux, (double)t.uy, (double)t.uz};
+  const int v = box_cross(e.nav, p, u, fc);
+  t.x = p[0];
+  t.y = p[1];
+  t.z = p[2];
+  if (v < 0) {
+    o.escaped += t.E;
+    t.E = 0.0;
+    t.slab = -1;
+  } else {
+    t.slab = v;
+  }
+}
+
 template <class R>
 EMS_HD double dist_to_planes(const StepEnv<R>& e, const Trk<R>& t) {
   const double uz = t.uz;
@@ -250,7 +278,7 @@ EMS_HD void gamma_select(R sc, R sp, R sig, Draws& r, StepOut<R>& o) {
   o.pending = true;
 }
 
-template <class R>
+template <class R, int GEO = 0>
 EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   if (t.E < e.ecut) {
     o.dep += t.E;
@@ -266,7 +294,14 @@ EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   const R sp = lerp(e.T(m, tPhot), b);
   const R sv = E > 2.0 * kMe ? lerp(e.T(m, tConv), b) : R(0);
   const R sig = sc + sp + sv;
-  const double sz = dist_to_planes(e, t), sw = dist_to_walls(e, t);
+  Face fc{0, 0.0};
+  double sz, sw = kInf;
+  if constexpr (GEO == 1) {
+    sz = box_dist(e, t, fc);
+  } else {
+    sz = dist_to_planes(e, t);
+    sw = dist_to_walls(e, t);
+  }
   const double sg = sz <= sw ? sz : sw;
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
@@ -278,7 +313,8 @@ EMS_HD void gamma_step(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
     o.step_len = sg;
     if (sz <= sw) {
       o.limiter = kLimZ;
-      land_on_plane(e, t, o, t.uz > R(0));
+      if constexpr (GEO == 1) box_land(e, t, o, fc);
+      else land_on_plane(e, t, o, t.uz > R(0));
     } else {
       o.limiter = kLimWall;
       o.escaped += t.E;
@@ -442,7 +478,7 @@ EMS_HD R gamma_loss(R mean, R var, Draws& r) {
   return x * theta;
 }
 
-template <class R>
+template <class R, int GEO = 0>
 EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
@@ -459,8 +495,11 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     }
     return;
   }
-  const bool field = e.bz != 0.0;
-  const double sz = dist_to_planes(e, t);
+  const bool field = GEO == 0 && e.bz != 0.0;  // box geometries take no field
+  Face fc{0, 0.0};
+  double sz;
+  if constexpr (GEO == 1) sz = box_dist(e, t, fc);
+  else sz = dist_to_planes(e, t);
   double sg;
   bool zlim;
   if (field) {
@@ -476,7 +515,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     zlim = sz <= dw;
     sg = zlim ? sz : dw;
   } else {
-    const double sw = dist_to_walls(e, t);
+    const double sw = GEO == 1 ? kInf : dist_to_walls(e, t);
     zlim = sz <= sw;
     sg = zlim ? sz : sw;
   }
@@ -567,7 +606,8 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   const bool up = t.uz > R(0);  // the plane reached, fixed before any deflection
   if ((e.mask & kPMsc) && s > 0.0) msc_deflect(highland_width<R>(T, s, e.mat[m].x0), r, t);
   if (lim == kLimZ) {
-    land_on_plane(e, t, o, up);
+    if constexpr (GEO == 1) box_land(e, t, o, fc);
+    else land_on_plane(e, t, o, up);
     return;
   }
   if (lim == kLimWall) {
@@ -699,17 +739,17 @@ EMS_HD void watchdog(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
 
 // One full step of a track of species sp: dispatch, step counter, watchdog.
 // KIND: 0 = photons only, 1 = e-/e+ only, 2 = any species (host use).
-template <int KIND, class R>
+template <int KIND, class R, int GEO = 0>
 EMS_HD void take_step_k(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
   clear_out(t, o);
-  if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step(e, t, o);
-  else lepton_step(e, sp == kPositron, t, o);
+  if (KIND == 0 || (KIND == 2 && sp == kGamma)) gamma_step<R, GEO>(e, t, o);
+  else lepton_step<R, GEO>(e, sp == kPositron, t, o);
   if (o.pending) interact<KIND>(e, t, o);
   else watchdog(e, t, o);
 }
-template <class R>
+template <class R, int GEO = 0>
 EMS_HD void take_step(const StepEnv<R>& e, int sp, Trk<R>& t, StepOut<R>& o) {
-  take_step_k<2>(e, sp, t, o);
+  take_step_k<2, R, GEO>(e, sp, t, o);
 }
 
 // Photon visit state: between interactions a photon keeps its energy and
@@ -735,7 +775,7 @@ EMS_HD void photon_begin(const StepEnv<R>& e, const Trk<R>& t, PhotonCache<R>& p
 // One photon step with the visit cache: exactly gamma_step followed by the
 // step count and watchdog of take_step.  Returns true when the visit must
 // end after it (the photon interacted or is gone).
-template <class R>
+template <class R, int GEO = 0>
 EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>& t, StepOut<R>& o) {
   clear_out(t, o);
   const double E = t.E;
@@ -750,13 +790,19 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
     const R sp = lerp(e.T(m, tPhot), pc.b);
     const R sv = pc.conv ? lerp(e.T(m, tConv), pc.b) : R(0);
     const R sig = sc + sp + sv;
-    const double h = e.half_xy;
     const double ux = t.ux, uy = t.uy, uz = t.uz;
-    const double sz = uz > 0.0 ? (e.zplane[t.slab + 1] - t.z) * pc.iuz
-                               : (uz < 0.0 ? (e.zplane[t.slab] - t.z) * pc.iuz : kInf);
-    const double sx = ux > 0.0 ? (h - t.x) * pc.iux : (ux < 0.0 ? (-h - t.x) * pc.iux : kInf);
-    const double sy = uy > 0.0 ? (h - t.y) * pc.iuy : (uy < 0.0 ? (-h - t.y) * pc.iuy : kInf);
-    const double sw = sx < sy ? sx : sy;
+    Face fc{0, 0.0};
+    double sz, sw;
+    if constexpr (GEO == 1) {
+      sz = box_dist(e, t, fc);
+      sw = kInf;
+    } else {
+      const double h = e.half_xy;
+      sz = uz > 0.0 ? (e.zplane[t.slab + 1] - t.z) * pc.iuz : (uz < 0.0 ? (e.zplane[t.slab] - t.z) * pc.iuz : kInf);
+      const double sx = ux > 0.0 ? (h - t.x) * pc.iux : (ux < 0.0 ? (-h - t.x) * pc.iux : kInf);
+      const double sy = uy > 0.0 ? (h - t.y) * pc.iuy : (uy < 0.0 ? (-h - t.y) * pc.iuy : kInf);
+      sw = sx < sy ? sx : sy;
+    }
     const double sg = sz <= sw ? sz : sw;
     Draws r;
     r.init(e.seed, t.key, t.id, t.n);
@@ -768,7 +814,8 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
       o.step_len = sg;
       if (sz <= sw) {
         o.limiter = kLimZ;
-        land_on_plane(e, t, o, t.uz > R(0));
+        if constexpr (GEO == 1) box_land(e, t, o, fc);
+        else land_on_plane(e, t, o, t.uz > R(0));
       } else {
         o.limiter = kLimWall;
         o.escaped += t.E;
@@ -811,14 +858,14 @@ EMS_HD void visit_begin(const StepEnv<R>& e, int sp, const Trk<R>& t, VisitState
 // run of visits is step for step the one-step-at-a-time loop.  The step's
 // interaction is left pending (o.pending) for the caller to run with
 // interact(), so that a wave samples its interactions together.
-template <int KIND, class R>
+template <int KIND, class R, int GEO = 0>
 EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps) {
   bool end;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
-    end = photon_substep(e, vs.pc, t, o);
+    end = photon_substep<R, GEO>(e, vs.pc, t, o);
   } else {
     clear_out(t, o);
-    lepton_step(e, sp == kPositron, t, o);
+    lepton_step<R, GEO>(e, sp == kPositron, t, o);
     if (!o.pending) watchdog(e, t, o);
     end = t.slab < 0 || o.pending;
   }

@@ -150,6 +150,41 @@ def test_msc_fluct_1gev_32_events(E, oracle_mod):
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
 
 
+@pytest.mark.parametrize("mask", [I.P_ALL, I.P_ALL | I.P_MSC | I.P_FLUCT])
+def test_box_geometry_history_parity(E, oracle_mod, mask):
+    """towers of boxes with cracks of world material: the kernels walking the
+    hierarchy against the oracle walking all boxes, step by step"""
+    print(f"box history parity mask={mask}", flush=True)
+    geo = I.towers(cells=5, n_layers=10)
+    cfg = I.RunConfig(seed=23, process_mask=mask)
+    prim = tiny_mixed_primaries()
+    prim["ekin"] *= 20.0
+    rng = np.random.default_rng(2)
+    prim["pos"][:, 0] = rng.uniform(-70, 70, len(prim))
+    prim["pos"][:, 1] = rng.uniform(-70, 70, len(prim))
+    g = run_gpu(E, geo, cfg, prim, 48, flags=E.F_STEPLOG | E.F_FULL_LEDGER, log_cap=400000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, log_cap=400000)
+    assert g["n_log"] == r["n_log"]
+    tol = 1e-8 if mask & I.P_FLUCT else 1e-9
+    compare_logs(g["log"], r["log"], e_rtol=tol, pos_atol=1e-7)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(g["ledger"][f], r["ledger"][f]), f
+    assert np.allclose(g["edep"], r["edep"], rtol=tol, atol=tol)
+    assert g["edep"][:, -1].sum() > 0.0
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
+def test_box_towers_1gev_32_events(E, oracle_mod):
+    print("towers 1 GeV x 32", flush=True)
+    geo, cfg, prim = I.workload("towers_1GeV_e-_x32")
+    g = run_gpu(E, geo, cfg, prim, 32, flags=E.F_FULL_LEDGER)
+    r = oracle_mod.Oracle(geo, cfg).run(prim)
+    assert np.array_equal(g["ledger"]["n_steps"], r["ledger"]["n_steps"])
+    assert np.array_equal(g["ledger"]["n_created"], r["ledger"]["n_created"])
+    assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+    assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
 @pytest.mark.parametrize("visit", [2, 16, 1024])
 def test_visit_length_does_not_change_results(E, visit):
     print(f"visit length {visit}", flush=True)
@@ -255,7 +290,7 @@ def test_empty_run_and_edges(E):
 
 
 @pytest.mark.parametrize("name", ["cal_10GeV_e-_x10k", "cal_mixed_1-100GeV_bz3.8_x10k", "calPbWO4_10GeV_e-_x10k",
-                                  "cal_10GeV_e-_x10k_msc_fluct"])
+                                  "cal_10GeV_e-_x10k_msc_fluct", "towers_10GeV_e-_x10k"])
 def test_full_size_workload_sampled(E, oracle_mod, name):
     """Full-size workloads in the benchmark's launch configuration: every
     event conserves energy, oracle-sampled events agree exactly, per-layer
@@ -274,9 +309,12 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     assert np.allclose(g["edep"][sample], r["edep"], rtol=1e-7 if "fluct" in name else 1e-8, atol=1e-8)
     for f in ("n_pair", "n_annih"):
         assert np.array_equal(g["ledger"][f][sample], r["ledger"][f]), f
-    # per-layer statistics
-    gl = g["edep"].reshape(n, 50, 2).sum(axis=2)
-    ol = r["edep"].reshape(len(sample), 50, 2).sum(axis=2)
+    # per-layer statistics (towers: summed over the towers, cracks left out)
+    def layers(ed):
+        if hasattr(geo, "world_lo"):
+            ed = ed[:, :-1].reshape(len(ed), -1, 100).sum(axis=1)
+        return ed.reshape(len(ed), 50, 2).sum(axis=2)
+    gl, ol = layers(g["edep"]), layers(r["edep"])
     mg, mo = gl.mean(axis=0), ol.mean(axis=0)
     sig = np.sqrt(gl.var(axis=0) / n + ol.var(axis=0) / len(sample))
     assert np.all(np.abs(mg - mo) <= 3 * sig + 0.005 * np.abs(mo) + 1e-9)

@@ -240,3 +240,79 @@ def test_unknown_process_bits_rejected(E):
     assert _bad(E, c, I.calorimeter()) == E.OK
     c = E.make_config(I.RunConfig(process_mask=I.P_ALL | (1 << 9)), 4)
     assert _bad(E, c, I.calorimeter()) == E.E_INVALID
+
+
+# ---------------------------------------------------------------- box geometry
+def _box_parity(E, oracle_mod, geo, cfg, prim, n_events, e_rtol=1e-10):
+    h = E.debug_host_transport(E.make_config(cfg, n_events), geo, prim, n_events, log_cap=1_000_000)
+    r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=n_events, log_cap=1_000_000)
+    st = compare_logs(h["log"], r["log"], e_rtol=e_rtol, pos_atol=1e-8)
+    assert st["n"] == r["n_log"]
+    assert np.allclose(h["edep"], r["edep"], rtol=e_rtol, atol=e_rtol)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(h["ledger"][f], r["ledger"][f]), f
+    assert ledger_residual(h["edep"], h["ledger"], prim).max() < 1e-12
+    return h, r
+
+
+@pytest.mark.parametrize("mask", [I.P_ALL, I.P_ALL | I.P_MSC | I.P_FLUCT])
+def test_host_box_navigation_matches_brute_force_oracle(E, oracle_mod, mask):
+    """the step code walking the hierarchy (towers with cracks of world
+    material) against the oracle's walk over all boxes, step by step"""
+    geo = I.towers(cells=5, n_layers=10)
+    cfg = I.RunConfig(seed=23, process_mask=mask)
+    prim = tiny_mixed_primaries()
+    prim["ekin"] *= 20.0
+    rng = np.random.default_rng(2)
+    prim["pos"][:, 0] = rng.uniform(-70, 70, len(prim))
+    prim["pos"][:, 1] = rng.uniform(-70, 70, len(prim))
+    h, r = _box_parity(E, oracle_mod, geo, cfg, prim, 48, e_rtol=1e-9 if mask & I.P_FLUCT else 1e-10)
+    assert h["edep"][:, -1].sum() > 0.0  # the cracks were crossed
+
+
+def test_host_box_random_tracks(E, oracle_mod):
+    geo = I.towers(cells=5, n_layers=10)
+    cfg = I.RunConfig(seed=24)
+    rng = np.random.default_rng(5)
+    n = 300
+    prim = I.primaries(n)
+    prim["event"] = rng.integers(0, 20, n)
+    prim["species"] = rng.integers(0, 3, n)
+    prim["ekin"] = np.exp(rng.uniform(np.log(1e-3), np.log(50.0), n))
+    prim["pos"] = rng.uniform(np.array(geo.world_lo) * 0.999, np.array(geo.world_hi) * 0.999 + [0, 0, 0.0], (n, 3))
+    prim["pos"][:, 2] = rng.uniform(0.0, geo.world_hi[2], n)
+    d = rng.normal(size=(n, 3))
+    prim["dir"] = d / np.linalg.norm(d, axis=1)[:, None]
+    _box_parity(E, oracle_mod, geo, cfg, prim, 20)
+
+
+def test_host_box_9x9_towers_showers(E, oracle_mod):
+    """8100 boxes (13-bit volume indices): 1 GeV showers equal to the oracle's"""
+    geo = I.towers()
+    assert geo.n_boxes == 8100
+    cfg = I.RunConfig(seed=25)
+    prim = I.beam(4, I.ELECTRON, 1000.0, smear_rad=1e-3, seed=3)
+    prim["pos"][:, 0] = [0.0, 19.7, -19.9, 5.0]
+    _box_parity(E, oracle_mod, geo, cfg, prim, 4)
+
+
+def test_box_validation(E):
+    good = E.make_config(I.RunConfig(), 4)
+    geo = I.towers(cells=3, n_layers=2)
+    assert _bad(E, good, geo) == E.OK
+    g = I.towers(cells=3, n_layers=2)
+    g.hi = g.hi.copy()
+    g.hi[0, 0] += 50.0
+    assert _bad(E, good, g) == E.E_INVALID
+    g = I.towers(cells=3, n_layers=2)
+    g.material = g.material.copy()
+    g.material[1] = 5
+    assert _bad(E, good, g) == E.E_INVALID
+    assert _bad(E, E.make_config(I.RunConfig(bz_tesla=1.0), 4), geo) == E.E_INVALID
+    big = I.towers(cells=9, n_layers=50)
+    assert _bad(E, E.make_config(I.RunConfig(max_steps_per_track=(1 << 19) - 1), 4), big) == E.OK
+    assert _bad(E, E.make_config(I.RunConfig(max_steps_per_track=1 << 19), 4), big) == E.E_INVALID
+    p = I.beam(2, I.ELECTRON, 10.0)
+    p["pos"][1] = (1e4, 0.0, 0.0)
+    with pytest.raises(E.EmsError):
+        E.debug_host_transport(good, geo, p, 2)
