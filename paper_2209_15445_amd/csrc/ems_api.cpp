@@ -40,11 +40,22 @@ uint32_t vol_bits(const ems_geometry* g) {
   while (((1ull << b) - 1) <= n_cols(g)) ++b;  // the all-ones field is never a volume
   return b;
 }
+// entries of the per-face neighbour lists of a box geometry (built once per
+// geometry and remembered, since the workspace plan needs the count)
+uint64_t nbr_entries(const ems_geometry* g) {
+  BvhHost h;
+  std::string err;
+  build_bvh(g->box_lo, g->box_hi, g->n_boxes, h, err);
+  return h.nbr.size();
+}
 BoxNav host_nav(const ems_geometry* g, const BvhHost& h) {
   BoxNav n{};
   n.node = h.node.data();
   n.leaf = h.leaf.data();
   n.box = h.box.data();
+  n.rec = h.rec.data();
+  n.nbr_off = h.nbr_off.data();
+  n.nbr = h.nbr.data();
   for (int k = 0; k < 3; ++k) {
     n.wlo[k] = g->world_lo[k];
     n.whi[k] = g->world_hi[k];
@@ -188,6 +199,9 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.bvh = take(g->n_boxes ? (2ull * g->n_boxes) * sizeof(BvhNode) : 0);
   L.bleaf = take(g->n_boxes * 4ull);
   L.bbox = take(g->n_boxes * 48ull);
+  L.brec = take(g->n_boxes * sizeof(BoxRec));
+  L.nbr_off = take(g->n_boxes ? (6ull * g->n_boxes + 1) * 4 : 0);
+  L.nbr = take(g->n_boxes ? nbr_entries(g) * 4 : 0);
   L.mat = take(g->n_materials * sizeof(MatRT));
   L.elem = take(elem_bytes(c, g));
   L.edep = take((uint64_t)c->max_events * n_cols(g) * 8);
@@ -480,6 +494,9 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
     a.env.nav.node = reinterpret_cast<const BvhNode*>(c->ws + L.bvh);
     a.env.nav.leaf = reinterpret_cast<const uint32_t*>(c->ws + L.bleaf);
     a.env.nav.box = reinterpret_cast<const double*>(c->ws + L.bbox);
+    a.env.nav.rec = reinterpret_cast<const BoxRec*>(c->ws + L.brec);
+    a.env.nav.nbr_off = reinterpret_cast<const uint32_t*>(c->ws + L.nbr_off);
+    a.env.nav.nbr = reinterpret_cast<const uint32_t*>(c->ws + L.nbr);
   }
   int per_g = 0, per_l = 0;
   if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
@@ -526,7 +543,13 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
               hipMemcpyAsync(c->ws + L.bleaf, c->bvh.leaf.data(), c->bvh.leaf.size() * 4, hipMemcpyHostToDevice, s) ==
                   hipSuccess &&
               hipMemcpyAsync(c->ws + L.bbox, c->bvh.box.data(), c->bvh.box.size() * 8, hipMemcpyHostToDevice, s) ==
-                  hipSuccess)) &&
+                  hipSuccess &&
+              hipMemcpyAsync(c->ws + L.nbr_off, c->bvh.nbr_off.data(), c->bvh.nbr_off.size() * 4,
+                             hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ws + L.brec, c->bvh.rec.data(), c->bvh.rec.size() * sizeof(BoxRec),
+                             hipMemcpyHostToDevice, s) == hipSuccess &&
+              (c->bvh.nbr.empty() || hipMemcpyAsync(c->ws + L.nbr, c->bvh.nbr.data(), c->bvh.nbr.size() * 4,
+                                                    hipMemcpyHostToDevice, s) == hipSuccess))) &&
             hipMemcpyAsync(c->ws + L.smat, c->smat.data(), c->smat.size() * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&

@@ -21,7 +21,7 @@ hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
-  uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
+  uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, brec, nbr_off, nbr, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t cap;
 };
 
@@ -31,6 +31,8 @@ uint64_t queue_track_bytes(const ems_config* c);
 // the packed queue word that hold the volume
 uint32_t n_cols(const ems_geometry* g);
 uint32_t vol_bits(const ems_geometry* g);
+// entries of the per-face neighbour lists of a box geometry
+uint64_t nbr_entries(const ems_geometry* g);
 // host view of a box hierarchy
 BoxNav host_nav(const ems_geometry* g, const BvhHost& h);
 

@@ -197,9 +197,9 @@ EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o, bool up
 // Geometry kinds: 0 = the slab stack, 1 = boxes (see ems_geometry.hpp).
 // Box geometry: distance to the next boundary and the face reached.
 template <class R>
-EMS_HD double box_dist(const StepEnv<R>& e, const Trk<R>& t, Face& fc) {
+EMS_HD double box_dist(const StepEnv<R>& e, const Trk<R>& t, Face& fc, const double* iu = nullptr) {
   const double p[3] = {t.x, t.y, t.z}, u[3] = {(double)t.ux, (double)t.uy, (double)t.uz};
-  return box_distance(e.nav, t.slab, p, u, fc);
+  return box_distance(e.nav, t.slab, p, u, fc, iu);
 }
 // on the face reached, into the volume the track moves into, or out
 template <class R>
@@ -794,7 +794,8 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
     Face fc{0, 0.0};
     double sz, sw;
     if constexpr (GEO == 1) {
-      sz = box_dist(e, t, fc);
+      const double iu[3] = {pc.iux, pc.iuy, pc.iuz};
+      sz = box_dist(e, t, fc, iu);
       sw = kInf;
     } else {
       const double h = e.half_xy;
