@@ -347,7 +347,9 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         import torch
-        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        # the source is never written on the device, so none of it sits in a
+        # cache when the copy reads it; the copy is the probe's only kernel
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)

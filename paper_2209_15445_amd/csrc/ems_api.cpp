@@ -40,8 +40,8 @@ uint32_t vol_bits(const ems_geometry* g) {
   while (((1ull << b) - 1) <= n_cols(g)) ++b;  // the all-ones field is never a volume
   return b;
 }
-// entries of the per-face neighbour lists of a box geometry (built once per
-// geometry and remembered, since the workspace plan needs the count)
+// entries of the per-face neighbour lists of a box geometry (the workspace
+// plan needs the count, so the lists are built here for it)
 uint64_t nbr_entries(const ems_geometry* g) {
   BvhHost h;
   std::string err;
