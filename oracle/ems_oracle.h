@@ -13,11 +13,14 @@
  * the paper describes in its "Stepping workflow" section (one thread follows
  * one track, secondaries are pushed on a stack, events are independent).
  * The paper delegates physics to G4HepEm (section 2.2) and gives no formulas;
- * the physics below is the set of textbook readings recorded in the design doc
- * (Klein-Nishina Compton, Heitler K-shell photo-effect, Bethe-Heitler pair
- * production with Thomas-Fermi screening, screened 1/k bremsstrahlung,
- * Moller/Bhabha ionisation with restricted Berger-Seltzer loss, Heitler
- * two-photon annihilation).  Every random number is addressed by
+ * the physics below is a set of textbook models: Klein-Nishina Compton,
+ * Heitler K-shell photo-effect, Bethe-Heitler pair production with
+ * Thomas-Fermi screening, screened 1/k bremsstrahlung, Moller/Bhabha
+ * ionisation with restricted Berger-Seltzer loss, Heitler two-photon
+ * annihilation; optionally Highland-width multiple scattering and gamma-law
+ * loss fluctuations; compounds by Bragg additivity with a sampled target
+ * element.  Geometry is a slab stack or a set of boxes navigated by brute
+ * force.  Every random number is addressed by
  * (seed, event key, track id, step, draw index) through Philox4x32-10, so a
  * breadth-first GPU loop that uses the same addressing reaches the same
  * per-track histories.
