@@ -239,6 +239,34 @@ def transport_leg(E, I, workload, precision, capacity, args):
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
 
 
+def atomic_probe(E, n_cells, n_ops=1 << 28, reps=3):
+    """Ceiling of the tallies' FP64 atomic rate: the library's probe (the
+    deposit instruction, uniform over as many cells as the run's tallies),
+    best of a few repetitions, in G atomics/s."""
+    import torch
+    cells = torch.zeros(n_cells, dtype=torch.float64, device="cuda")
+    best = min(E.probe_atomics(cells, n_ops) for _ in range(reps))
+    assert float(cells.sum().item()) == float(n_ops)  # every add landed
+    return n_ops / (best / 1e3) / 1e9
+
+
+def atomics_report(leg, workload, peak):
+    """Atomic rate of each visit kernel against the probe: atomic requests
+    per launch counted by rocprofv3 (TCC_ATOMIC_sum, committed in
+    profiles/atomics.txt with the digest of the kernels measured) over the
+    kernel's live average launch time; null while the kernels differ from
+    the measured ones."""
+    kern = leg["roofline"]["kernels"]
+    out = {"unit": "G atomics/s", "probe_peak": peak,
+           "probe": "2^28 FP64 atomic adds, uniform over the run's [events][columns] tally cells"}
+    for k, v in kern.items():
+        n = counted_for(k, workload, "atomics.txt")
+        ach = n / (v["avg_launch_us"] * 1e-6) / 1e9 if n is not None and v["avg_launch_us"] > 0 else None
+        out[k] = {"atomic_requests_per_launch": n, "achieved": ach,
+                  "frac": ach / peak if ach is not None and peak else None}
+    return out
+
+
 def kernel_source_digest():
     """SHA-256 over the kernel sources: HBM traffic figures taken with
     counters are valid only for the kernels they were measured on."""
@@ -251,13 +279,15 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def traffic_for(kernel, workload):
-    """Counter-measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled
-    by a plain-copy calibration) from the committed profile summary of the
-    same kernel and workload, or None when the kernels changed since."""
+def counted_for(kernel, workload, name="traffic.txt"):
+    """A counter-measured per-launch figure of a kernel on a workload from a
+    committed profile table (profiles/traffic.txt: HBM bytes from
+    FETCH_SIZE + WRITE_SIZE scaled by a plain-copy calibration;
+    profiles/atomics.txt: TCC atomic requests), or None when the kernels
+    changed since it was measured."""
     if workload is None:
         return None
-    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -269,6 +299,10 @@ def traffic_for(kernel, workload):
     if hit is None or hit[0] != kernel_source_digest():
         return None
     return hit[1]
+
+
+def traffic_for(kernel, workload):
+    return counted_for(kernel, workload, "traffic.txt")
 
 
 def layer_error(leg, n_events):
@@ -342,9 +376,19 @@ def main():
     ap.add_argument("--serve-steps-per-launch", type=int, default=1, help="iterations between host polls")
     ap.add_argument("--serve-steps-per-visit", type=int, default=16)
     ap.add_argument("--no-fp64-serve", action="store_true")
+    ap.add_argument("--atomic-probe", type=int, default=0,
+                    help="only run the library's FP64 atomic probe with this many adds (calibrates atomic counters)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.atomic_probe:
+        import torch
+
+        import paper_2209_15445_amd as E
+        cells = torch.zeros(10**6, dtype=torch.float64, device="cuda")
+        ms = E.probe_atomics(cells, args.atomic_probe)
+        print(json.dumps({"atomic_probe_ops": args.atomic_probe, "ms": ms}), flush=True)
+        return
     if args.copy_probe:
         import torch
         # the source is never written on the device, so none of it sits in a
@@ -391,6 +435,7 @@ def main():
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
     }
+    out["atomics"] = atomics_report(fp, args.workload, atomic_probe(E, n * geo.n_cols))
     if not args.no_mixed:
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
@@ -398,7 +443,8 @@ def main():
                         "value_graph_replay": mx["value_graph"],
                         "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
                         "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
-                        "capacity": args.mixed_capacity, "roofline": mx["roofline"]}
+                        "capacity": args.mixed_capacity, "roofline": mx["roofline"],
+                        "atomics": atomics_report(mx, None, atomic_probe(E, len(mx["prim"]) * mx["geo"].n_cols))}
         if not args.no_cpu:
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
     if args.extra_workload:

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 4u
+#define EMS_ABI_VERSION 5u
 
 typedef int32_t ems_status;
 enum {
@@ -236,6 +236,16 @@ typedef struct {
 } ems_run_stats;
 
 typedef struct ems_ctx ems_ctx;
+
+/* Measures the device's FP64 atomic-add throughput on a tally-like scatter:
+ * n_ops adds of 1.0 by the instruction the deposit tallies use, each to a
+ * cell drawn uniformly (fixed hash of the op index) from the n_cells
+ * doubles at d_cells (device, zeroed here, left holding the counts).  The
+ * adds run on hip_stream (NULL: the null stream) between two HIP events;
+ * *ms receives their elapsed time.  A ceiling for the tallies' atomic rate,
+ * against which bench.py reports the kernels' achieved rate.
+ * EMS_E_INVALID for null pointers or zero sizes. */
+ems_status ems_probe_atomics(void* d_cells, uint64_t n_cells, uint64_t n_ops, void* hip_stream, double* ms);
 
 /* Device workspace needed for (cfg, geo), in bytes (host outputs). */
 ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo,

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
@@ -129,6 +129,7 @@ def lib():
             "ems_server_stats": [vp, C.POINTER(ServerInfo)],
             "ems_server_reset_stats": [vp],
             "ems_server_destroy": [vp],
+            "ems_probe_atomics": [vp, u64, u64, vp, C.POINTER(C.c_double)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -343,6 +344,20 @@ class Transport:
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
                     run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits),
                     made_by=list(s.made_by), kernel_ms=list(s.kernel_ms), graph_launches=s.graph_launches)
+
+
+def probe_atomics(cells, n_ops, stream=None):
+    """FP64 atomic-add throughput: n_ops adds spread uniformly over the
+    cells of `cells` (a float64 CUDA tensor, zeroed and left holding the
+    counts); returns the device time in ms."""
+    import torch
+    if not (cells.is_cuda and cells.dtype == torch.float64 and cells.is_contiguous()):
+        raise ValueError("cells must be a contiguous float64 device tensor")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ms = C.c_double()
+    _check(lib().ems_probe_atomics(C.c_void_p(cells.data_ptr()), cells.numel(), int(n_ops),
+                                   C.c_void_p(s.cuda_stream), C.byref(ms)))
+    return ms.value
 
 
 class Server:

@@ -374,6 +374,26 @@ extern "C" {
 
 uint32_t ems_abi_version(void) { return EMS_ABI_VERSION; }
 
+ems_status ems_probe_atomics(void* d_cells, uint64_t n_cells, uint64_t n_ops, void* stream, double* ms) {
+  if (!d_cells || !n_cells || !n_ops || !ms) return fail(EMS_E_INVALID, "null pointer or zero size");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(EMS_E_DEVICE, "event creation failed");
+  }
+  float t = 0.0f;
+  const bool ok = hipMemsetAsync(d_cells, 0, n_cells * 8, s) == hipSuccess && hipEventRecord(e0, s) == hipSuccess &&
+                  launch_atomic_probe(static_cast<double*>(d_cells), n_cells, n_ops, s) == hipSuccess &&
+                  hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                  hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok) return fail(EMS_E_DEVICE, "atomic probe failed");
+  *ms = t;
+  return EMS_OK;
+}
+
 const char* ems_last_error(void) { return g_err.c_str(); }
 
 ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo, uint64_t* bytes) {

@@ -214,7 +214,6 @@ struct DevSink {
   unsigned long long log_cap;
   uint32_t n_slabs;
   bool full, logging;
-  uint32_t applied;  // steps applied by this lane in the current visit
   // deposits of consecutive steps into the same (event, slab) add up in the
   // lane and reach the tally with one atomic when the cell changes or the
   // lane finishes (summation order of FP64 atomics is unordered anyway)
@@ -230,7 +229,6 @@ struct DevSink {
 
   template <class R>
   __device__ void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e_before) {
-    ++applied;
     if (o.dep != 0.0) {
       const size_t cell = (size_t)t.ev * n_slabs + o.slab;
       if (cell != acc_cell) {
@@ -373,7 +371,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
     // wave-private append ranges (uniform): secondaries and home, per species
     uint32_t slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, hlo[3] = {0, 0, 0}, hhi[3] = {0, 0, 0};
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
-                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0u, 0, 0.0,
+                 (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0, 0.0,
                  a.exits, a.exit_cap};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
     const bool track_live = (a.flags & kFlagEventLive) != 0;
@@ -682,6 +680,19 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R>())) void k_visit(K
   }
 }
 
+// Atomic-throughput probe: FP64 adds of 1.0, the instruction of the deposit
+// tallies, to cells drawn by a fixed hash of the op index (grid-stride).
+__global__ __launch_bounds__(kBlock) void k_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n_ops; i += stride) {
+    uint64_t h = i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    atomicAdd(&cells[h % n_cells], 1.0);
+  }
+}
+
 // Injection: prepared tracks appended to the home regions of the current
 // queues.
 template <class R>
@@ -797,6 +808,12 @@ hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, h
 hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s) {
   const uint32_t blocks = n == 0 ? 1 : (n < 1024 ? n : 1024);
   hipLaunchKernelGGL(k_gather_rows, dim3(blocks), dim3(kBlock), 0, s, a, rows, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, hipStream_t s) {
+  const uint64_t want = (n_ops + kBlock - 1) / kBlock;
+  const uint32_t blocks = (uint32_t)(want < 16384 ? (want ? want : 1) : 16384);
+  hipLaunchKernelGGL(k_atomic_probe, dim3(blocks), dim3(kBlock), 0, s, cells, n_cells, n_ops);
   return hipGetLastError();
 }
 hipError_t launch_census(const KArgs& a, hipStream_t s) {

@@ -15,6 +15,7 @@ namespace ems {
 hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s);
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s);
 hipError_t launch_census(const KArgs& a, hipStream_t s);
+hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, hipStream_t s);
 hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s);
 hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s);
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);

@@ -468,3 +468,14 @@ def test_exit_capacity_overflow_counts_all(E):
     ex2, n2 = t.exits()
     t.close()
     assert len(ex) == 10 and n > 10 and n2 == 0 and len(ex2) == 0
+
+
+def test_atomic_probe_lands_every_add(E):
+    """the atomic probe: exact integer counts, summing to the adds issued
+    and spread over all cells"""
+    import torch
+    cells = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    ms = E.probe_atomics(cells, 1 << 22)
+    assert ms > 0.0
+    c = cells.cpu().numpy()
+    assert c.sum() == float(1 << 22) and np.all(c == np.round(c)) and c.min() > 0
