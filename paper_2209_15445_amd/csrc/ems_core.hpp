@@ -89,6 +89,10 @@ EMS_HD float xsin(float v) { return sinf(v); }
 EMS_HD double xsin(double v) { return sin(v); }
 EMS_HD float xcos(float v) { return cosf(v); }
 EMS_HD double xcos(double v) { return cos(v); }
+// sine and cosine of one angle with one argument reduction (the compiler
+// does not merge separate sin and cos calls; about half the instructions)
+EMS_HD void xsincos(float v, float* s, float* c) { sincosf(v, s, c); }
+EMS_HD void xsincos(double v, double* s, double* c) { sincos(v, s, c); }
 EMS_HD float xfloor(float v) { return floorf(v); }
 EMS_HD double xfloor(double v) { return floor(v); }
 EMS_HD float xceil(float v) { return ceilf(v); }
@@ -174,7 +178,9 @@ EMS_HD V3T<R> unit(V3T<R> v) {
 // u = +-z^ uses e1 = (+-1, 0, 0), e2 = (0, 1, 0).
 template <class R>
 EMS_HD V3T<R> about_axis(V3T<R> u, R cost, R sint, R phi) {
-  const R a = sint * xcos(phi), b = sint * xsin(phi);
+  R sp, cp;
+  xsincos(phi, &sp, &cp);
+  const R a = sint * cp, b = sint * sp;
   const R t2 = u.x * u.x + u.y * u.y;
   if (t2 > R(0)) {
     const R t = xsqrt(t2);

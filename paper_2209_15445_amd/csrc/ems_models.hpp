@@ -277,7 +277,9 @@ EMS_HD void annihilate_at_rest(Draws& r, Outcome<R>& o) {
   const R phi = R(kTwoPi) * r.u_at<R>(2);
   const R s2 = R(1) - c * c;
   const R sn = xsqrt(s2 > R(0) ? s2 : R(0));
-  const V3T<R> a{sn * xcos(phi), sn * xsin(phi), c};
+  R sp, cp;
+  xsincos(phi, &sp, &cp);
+  const V3T<R> a{sn * cp, sn * sp, c};
   o.survives = false;
   o.n = 2;
   o.sp[0] = kGamma;

@@ -435,7 +435,9 @@ EMS_HD void msc_deflect(R th0, Draws& r, Trk<R>& t) {
   if (!(th0 > R(0))) return;
   R th = th0 * xsqrt(R(-2) * xlog(u1));
   th = th > R(kPi) ? R(kPi) : th;
-  const V3T<R> d = about_axis(V3T<R>{t.ux, t.uy, t.uz}, xcos(th), xsin(th), R(kTwoPi) * u2);
+  R st, ct;
+  xsincos(th, &st, &ct);
+  const V3T<R> d = about_axis(V3T<R>{t.ux, t.uy, t.uz}, ct, st, R(kTwoPi) * u2);
   t.ux = d.x;
   t.uy = d.y;
   t.uz = d.z;
@@ -565,8 +567,11 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     const double p = sqrt(T * (T + 2.0 * kMe));
     const double kap = (positron ? kKB : -kKB) * e.bz / p;
     const double ph = kap * s;
-    const double sp = sin(ph), cp = cos(ph), h = sin(0.5 * ph);
-    const double omc = 2.0 * h * h;
+    // sin and cos of the turn from those of its half (one reduction):
+    // sin = 2 sh ch, 1 - cos = 2 sh^2 (no cancellation for small turns)
+    double sh, ch;
+    sincos(0.5 * ph, &sh, &ch);
+    const double sp = 2.0 * sh * ch, omc = 2.0 * sh * sh, cp = 1.0 - omc;
     const double ux = t.ux, uy = t.uy;
     t.x += (ux * sp + uy * omc) / kap;
     t.y += (uy * sp - ux * omc) / kap;
