@@ -55,8 +55,16 @@ def cpu_baseline(geo, cfg, prim, n_events, threads):
     dt = time.perf_counter() - t0
     if errors:
         raise errors[0]
-    return dict(value=n_events / dt, unit="primaries/s", cores=len(ts), kind="oracle",
-                sample=f"first {n_events} events of the workload, {len(ts)} threads, {dt:.1f} s wall")
+    # one core: the first events on a single thread
+    n1 = max(1, min(n_events, 128))
+    t1 = time.perf_counter()
+    work(np.arange(n1))
+    dt1 = time.perf_counter() - t1
+    if errors:
+        raise errors[0]
+    return dict(value=n_events / dt, unit="primaries/s", cores=len(ts), kind="oracle", value_1core=n1 / dt1,
+                sample=f"first {n_events} events of the workload, {len(ts)} threads, {dt:.1f} s wall; "
+                       f"1 core: first {n1} events, {dt1:.1f} s")
 
 
 def serving(E, I, args, precision):
@@ -237,6 +245,24 @@ def transport_leg(E, I, workload, precision, capacity, args):
                 value_graph=value_graph,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
+
+
+def copy_bandwidth(n_bytes=1 << 31, reps=5):
+    """Achievable HBM bandwidth of a device-to-device copy (read + write
+    bytes over the copy time), GB/s."""
+    import torch
+    a = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n_bytes / (ms / 1e3) / 1e9
 
 
 def atomic_probe(E, n_cells, n_ops=1 << 28, reps=3):
@@ -436,6 +462,16 @@ def main():
         "value_graph_replay": fp["value_graph"],
     }
     out["atomics"] = atomics_report(fp, args.workload, atomic_probe(E, n * geo.n_cols))
+    # counter-measured HBM bytes over the live launch time, against the
+    # peak and against an achievable copy
+    roof = out["roofline"]
+    copy_gbs = copy_bandwidth()
+    roof["copy_GB_per_s"] = copy_gbs
+    if roof["traffic"] is not None:
+        tg = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+        roof["traffic_GB_per_s"] = tg
+        roof["traffic_frac"] = tg / HBM_PEAK_GBS
+        roof["traffic_frac_of_copy"] = tg / copy_gbs
     if not args.no_mixed:
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
