@@ -371,8 +371,8 @@ def layer_error(leg, n_events):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cal_10GeV_e-_x10k")
     ap.add_argument("--capacity", type=int, default=1 << 25)
     ap.add_argument("--blocks", type=int, default=0)
