@@ -171,8 +171,9 @@ def transport_leg(E, I, workload, precision, capacity, args):
     import torch
     geo, cfg, prim = I.workload(workload)
     n = len(prim)
+    visit = args.steps_per_visit if precision == E.FP64 else args.steps_per_visit_mixed
     c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
-                      launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit,
+                      launch_blocks=args.blocks, steps_per_visit=visit,
                       refill_below=args.refill_below, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
 
@@ -221,15 +222,16 @@ def transport_leg(E, I, workload, precision, capacity, args):
                           kms[i] / max(sum(kms), 1e-12)}
     dom = names[1] if kms[1] >= kms[0] else names[0]
     d = kern[dom]
+    key = counter_key(workload, precision == E.FP64, visit, args.refill_below)
     roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": d["frac"], "traffic": traffic_for(dom, args.workload if precision == E.FP64 else None),
+            "frac": d["frac"], "traffic": traffic_for(dom, key),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
             "launches": launches, "kernels": kern}
     # the same steps replayed from captured graphs (no per-kernel events)
     value_graph = None
     if args.graph_check:
         cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
-                           launch_blocks=args.blocks, steps_per_visit=args.steps_per_visit,
+                           launch_blocks=args.blocks, steps_per_visit=visit,
                            refill_below=args.refill_below, precision=precision)
         eng = E.Transport(cg, geo)
         one_step()
@@ -241,7 +243,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
         value_graph = n * args.steps / (time.perf_counter() - t0)
         assert eng.stats()["graph_launches"] > 0
         eng.close()
-    return dict(geo=geo, cfg=cfg, prim=prim, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+    return dict(geo=geo, cfg=cfg, prim=prim, key=key, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
                 value_graph=value_graph,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
@@ -305,6 +307,12 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
+def counter_key(workload, fp64, visit, refill):
+    """Rows of the counter tables are keyed by workload, form and the two
+    launch parameters that change how many records a launch moves."""
+    return f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}"
+
+
 def counted_for(kernel, workload, name="traffic.txt"):
     """A counter-measured per-launch figure of a kernel on a workload from a
     committed profile table (profiles/traffic.txt: HBM bytes from
@@ -329,6 +337,17 @@ def counted_for(kernel, workload, name="traffic.txt"):
 
 def traffic_for(kernel, workload):
     return counted_for(kernel, workload, "traffic.txt")
+
+
+def with_traffic_rate(roof, copy_gbs):
+    """Counter-measured HBM bytes over the live launch time, against the
+    peak and against an achievable copy."""
+    roof["copy_GB_per_s"] = copy_gbs
+    if roof["traffic"] is not None:
+        tg = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+        roof["traffic_GB_per_s"] = tg
+        roof["traffic_frac"] = tg / HBM_PEAK_GBS
+        roof["traffic_frac_of_copy"] = tg / copy_gbs
 
 
 def layer_error(leg, n_events):
@@ -377,7 +396,8 @@ def main():
     ap.add_argument("--capacity", type=int, default=1 << 25)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=16)
-    ap.add_argument("--steps-per-visit", type=int, default=16)
+    ap.add_argument("--steps-per-visit", type=int, default=16, help="FP64 legs")
+    ap.add_argument("--steps-per-visit-mixed", type=int, default=32, help="mixed legs")
     ap.add_argument("--refill-below", type=int, default=32)
     ap.add_argument("--cpu-events", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
@@ -461,17 +481,9 @@ def main():
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
     }
-    out["atomics"] = atomics_report(fp, args.workload, atomic_probe(E, n * geo.n_cols))
-    # counter-measured HBM bytes over the live launch time, against the
-    # peak and against an achievable copy
-    roof = out["roofline"]
+    out["atomics"] = atomics_report(fp, fp["key"], atomic_probe(E, n * geo.n_cols))
     copy_gbs = copy_bandwidth()
-    roof["copy_GB_per_s"] = copy_gbs
-    if roof["traffic"] is not None:
-        tg = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
-        roof["traffic_GB_per_s"] = tg
-        roof["traffic_frac"] = tg / HBM_PEAK_GBS
-        roof["traffic_frac_of_copy"] = tg / copy_gbs
+    with_traffic_rate(out["roofline"], copy_gbs)
     if not args.no_mixed:
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
@@ -479,8 +491,10 @@ def main():
                         "value_graph_replay": mx["value_graph"],
                         "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
                         "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
-                        "capacity": args.mixed_capacity, "roofline": mx["roofline"],
-                        "atomics": atomics_report(mx, None, atomic_probe(E, len(mx["prim"]) * mx["geo"].n_cols))}
+                        "capacity": args.mixed_capacity, "steps_per_visit": args.steps_per_visit_mixed,
+                        "roofline": mx["roofline"],
+                        "atomics": atomics_report(mx, mx["key"], atomic_probe(E, len(mx["prim"]) * mx["geo"].n_cols))}
+        with_traffic_rate(out["mixed"]["roofline"], copy_gbs)
         if not args.no_cpu:
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.cpu_events)
     if args.extra_workload:
