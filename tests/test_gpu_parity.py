@@ -185,12 +185,13 @@ def test_box_towers_1gev_32_events(E, oracle_mod):
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
 
 
-@pytest.mark.parametrize("visit", [2, 16, 1024])
-def test_visit_length_does_not_change_results(E, visit):
-    print(f"visit length {visit}", flush=True)
+@pytest.mark.parametrize("visit,mixed", [(2, False), (16, False), (1024, False), (32, True)])
+def test_visit_length_does_not_change_results(E, visit, mixed):
+    print(f"visit length {visit} mixed={mixed}", flush=True)
     geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
-    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, flags=E.F_FULL_LEDGER)
-    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=visit, flags=E.F_FULL_LEDGER)
+    prec = E.MIXED if mixed else E.FP64
+    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, flags=E.F_FULL_LEDGER, precision=prec)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=visit, flags=E.F_FULL_LEDGER, precision=prec)
     assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
     for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
         assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
@@ -298,8 +299,10 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     print(f"full size {name}", flush=True)
     geo, cfg, prim = I.workload(name)
     n = len(prim)
-    # the capacities bench.py uses for these workloads
-    g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 26) if "mixed" in name else (1 << 25))
+    # bench.py's launch configuration: FP64 visits of 16 steps, refill
+    # threshold 32, capacity 2^25 for the headline workload, 2^26 for the others
+    g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 25) if name == "cal_10GeV_e-_x10k" else (1 << 26),
+                visit=16, refill=32)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -356,7 +359,8 @@ def test_full_size_mixed_workload(E, oracle_mod):
     print("full size mixed cal_10GeV_e-_x100k", flush=True)
     geo, cfg, prim = I.workload("cal_10GeV_e-_x100k")
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 28, precision=E.MIXED)  # as bench.py
+    # as bench.py: capacity 2^28, visits of 32 steps, refill threshold 32
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 28, precision=E.MIXED, visit=32, refill=32)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -380,7 +384,8 @@ def test_full_size_mixed_species_workload_mixed_form(E, oracle_mod):
     print("full size mixed form cal_mixed_1-100GeV_bz3.8_x10k", flush=True)
     geo, cfg, prim = I.workload("cal_mixed_1-100GeV_bz3.8_x10k")
     n = len(prim)
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 26, precision=E.MIXED)  # as bench.py
+    # as bench.py's other workloads: capacity 2^26, visits of 32 steps, refill 32
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 26, precision=E.MIXED, visit=32, refill=32)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(2)
     sample = np.sort(rng.choice(n, 24, replace=False))
