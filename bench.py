@@ -84,7 +84,7 @@ def serving(E, I, args, precision):
         pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
     c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity,
                       steps_per_launch=args.serve_steps_per_launch, steps_per_visit=args.serve_steps_per_visit,
-                      refill_below=args.refill_below, precision=precision)
+                      refill_below=args.refill_below, interact_min=args.interact_min, precision=precision)
     srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
     n_each = max(1, args.serve_requests // P)
     total = n_each * P
@@ -126,6 +126,7 @@ def serving(E, I, args, precision):
            "precision": "fp64" if precision == E.FP64 else "mixed",
            "slots": args.serve_slots, "producers": P, "window": args.serve_window,
            "iterations_per_poll": args.serve_steps_per_launch, "steps_per_visit": args.serve_steps_per_visit,
+           "interact_min": args.interact_min,
            "admit_cap_bytes": args.serve_admit_gib << 30,
            "saturated": {"requests": total, "primaries_per_s": prims / wall, "requests_per_s": sat_rps,
                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
@@ -173,8 +174,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
     n = len(prim)
     visit = args.steps_per_visit if precision == E.FP64 else args.steps_per_visit_mixed
     c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
-                      launch_blocks=args.blocks, steps_per_visit=visit,
-                      refill_below=args.refill_below, precision=precision, flags=E.F_KERNEL_TIMING)
+                      launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
+                      interact_min=args.interact_min, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -222,7 +223,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
                           kms[i] / max(sum(kms), 1e-12)}
     dom = names[1] if kms[1] >= kms[0] else names[0]
     d = kern[dom]
-    key = counter_key(workload, precision == E.FP64, visit, args.refill_below)
+    key = counter_key(workload, precision == E.FP64, visit, args.refill_below, args.interact_min)
     roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["frac"], "traffic": traffic_for(dom, key),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
@@ -236,8 +237,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
     value_graph = None
     if args.graph_check:
         cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
-                           launch_blocks=args.blocks, steps_per_visit=visit,
-                           refill_below=args.refill_below, precision=precision)
+                           launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
+                           interact_min=args.interact_min, precision=precision)
         eng = E.Transport(cg, geo)
         one_step()
         torch.cuda.synchronize()
@@ -312,10 +313,10 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def counter_key(workload, fp64, visit, refill):
-    """Rows of the counter tables are keyed by workload, form and the two
-    launch parameters that change how many records a launch moves."""
-    return f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}"
+def counter_key(workload, fp64, visit, refill, interact_min):
+    """Rows of the counter tables are keyed by workload, form and the launch
+    parameters that shape a launch's batches."""
+    return f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}i{interact_min}"
 
 
 def counted_for(kernel, workload, name="traffic.txt"):
@@ -404,6 +405,8 @@ def main():
     ap.add_argument("--steps-per-visit", type=int, default=16, help="FP64 legs")
     ap.add_argument("--steps-per-visit-mixed", type=int, default=32, help="mixed legs")
     ap.add_argument("--refill-below", type=int, default=32)
+    ap.add_argument("--interact-min", type=int, default=24,
+                    help="e-/e+ batches sample interactions once this many lanes wait for one")
     ap.add_argument("--cpu-events", type=int, default=2048, help="events of the timed oracle sample")
     ap.add_argument("--error-events", type=int, default=10000,
                     help="events of the mixed form compared with the FP64 oracle per layer")
@@ -484,7 +487,8 @@ def main():
                    "precision": "fp64", "track_steps_per_step": fp["track_steps"],
                    "visits_per_step": fp["visits"], "iterations": fp["iterations"],
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
-                   "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below},
+                   "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below,
+                   "interact_min": args.interact_min},
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
     }

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 5u
+#define EMS_ABI_VERSION 6u
 
 typedef int32_t ems_status;
 enum {
@@ -172,6 +172,13 @@ typedef struct {
                                     refills those lanes once at most this
                                     many of its 64 lanes are still stepping
                                     (0..63; results do not depend on it)    */
+  uint32_t interact_min;         /* e-/e+ kernel: a batch samples the
+                                    interactions its lanes selected only when
+                                    at least this many are waiting, or when
+                                    the queue is used up; until then those
+                                    lanes keep their tracks and wait (0..64;
+                                    0 = every batch; results do not depend
+                                    on it)                                  */
   uint64_t exit_capacity;        /* outgoing-track records kept per run
                                     (0 = none; see ems_read_exits)          */
 } ems_config;

@@ -338,7 +338,7 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 #define EMS_WAVES_F64_LEPTON 2
 #endif
 #ifndef EMS_WAVES_F32_PHOTON
-#define EMS_WAVES_F32_PHOTON 2
+#define EMS_WAVES_F32_PHOTON 3  // fits in 168 registers; at 169 it would drop to 2 waves, 22% slower
 #endif
 #ifndef EMS_WAVES_F32_LEPTON
 #define EMS_WAVES_F32_LEPTON 3  // 168 registers, a few spills: 8% faster than 2 waves of 205
@@ -410,15 +410,23 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     uint32_t kept_a = 0, kept_b = 0;  // home records written (own species; e+)
     for (;;) {
       const uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin));
-      const bool any_fin = __ballot(fin) != 0;
       // batch point: few lanes still stepping (or none, once the queue is drained)
       if (stepping <= (drained ? 0u : a.refill_below)) {
+        // (0) e-/e+: while the queue still has tracks, interactions are
+        // sampled only once at least interact_min lanes wait for one (each
+        // sampler costs the wave one pass however few lanes use it); until
+        // then those lanes are parked: they keep their tracks and take no
+        // part in this batch.  A wave whose lanes are all parked samples
+        // them, so every wave ends (interact_min <= 64).
+        const uint32_t npend = PHOTONS ? 0u : (uint32_t)__popcll(__ballot(fin && o.pending));
+        const bool parked = !PHOTONS && !drained && npend < a.interact_min && fin && o.pending;
+        const bool done = fin && !parked;  // visits this batch finishes
         // (1) prefetch the records of the tracks that the lanes free after
         // this batch will take; the loads are in flight during (2)
         // a parent that survives its interaction keeps its lane and goes on
         // stepping in this launch while it has steps left
-        const bool will_continue = fin && o.pending && parent_survives(o.process) && vs.steps < max_visit;
-        const bool want = (!has || (fin && !will_continue)) && !drained;
+        const bool will_continue = done && o.pending && parent_survives(o.process) && vs.steps < max_visit;
+        const bool want = (!has || (done && !will_continue)) && !drained;
         bool got = false;
         int nsp = PHOTONS ? 0 : 1;
         uint32_t nw = kDeadRecord;
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
         }
         // (2) the interactions selected by the lanes' last steps, sampled
         // together (one pass through each sampler the wave needs)
-        if (fin && o.pending) interact<KIND>(env, t, o);
+        if (done && o.pending) interact<KIND>(env, t, o);
         // (3) the prefetched records have arrived; waiting here, before any
         // store of this batch is issued, keeps later uses of their fields
         // from waiting on those stores (vector memory completes in order)
@@ -466,13 +474,13 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
           take = false;
         }
         // (4) commit the finished visits: reserve first, then write
-        if (any_fin) {
+        if (__ballot(done) != 0) {
           // secondaries into the top regions (a step commits only if all of
           // its secondaries fit), then survivors or carried tracks
           uint32_t d[3];
 #pragma unroll
           for (int q = 0; q < 3; ++q)
-            d[q] = (fin && o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (fin && o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
+            d[q] = (done && o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (done && o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
           uint32_t slot[3];
           Take tk[3];
           bool fits = true;
@@ -483,11 +491,11 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
             if (d[q] && slot_of(tk[q], slot[q] + d[q] - 1) >= lim) fits = false;
             if (d[q] > 1 && slot_of(tk[q], slot[q]) >= lim) fits = false;
           }
-          const bool pending = fin && o.nsec > 0;
+          const bool pending = done && o.nsec > 0;
           const bool commit = pending && fits;
-          const bool apply_now = commit || (fin && held && o.nsec == 0);
+          const bool apply_now = commit || (done && held && o.nsec == 0);
           const bool carry = pending && !commit;  // back to the state before the last step
-          const bool alive = fin && (carry ? before.slab >= 0 : t.slab >= 0);
+          const bool alive = done && (carry ? before.slab >= 0 : t.slab >= 0);
           const bool cont = alive && !carry && will_continue;  // stays in the lane
           const bool keep = alive && !cont;                    // written to the next queue
           // home slots (one counter per call: a wave may hold e- and e+)
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
             made2 += d[2];
           }
           if (carry) ++carried_n;
-          if (fin && track_live) {
+          if (done && track_live) {
             // net change of the event's live tracks: the visited track ends
             // or stays, committed secondaries join
             const int delta = (alive ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
@@ -559,7 +567,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
               else ++kept_a;
             }
           }
-          if (fin) {
+          if (done) {
             has = cont;
             fin = false;
             held = false;

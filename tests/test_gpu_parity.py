@@ -27,10 +27,10 @@ def E():
 
 
 def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
-            blocks=0, visit=16, refill=8, precision=0):
+            blocks=0, visit=16, refill=8, precision=0, interact_min=24):
     c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
                       profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit,
-                      refill_below=refill, precision=precision)
+                      refill_below=refill, precision=precision, interact_min=interact_min)
     t = E.Transport(c, geo)
     if keys is not None:
         t.set_event_keys(keys)
@@ -208,6 +208,23 @@ def test_refill_threshold_does_not_change_results(E, refill):
     assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
     for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
         assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
+
+
+@pytest.mark.parametrize("imin,mixed", [(1, False), (24, False), (64, False), (24, True)])
+def test_interaction_parking_does_not_change_results(E, imin, mixed):
+    """Lanes parked until interact_min interactions wait (64: until a wave's
+    lanes all wait or the queue is used up) give the results of sampling
+    every interaction at once, step for step."""
+    print(f"interact_min {imin} mixed={mixed}", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    prec = E.MIXED if mixed else E.FP64
+    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, refill=0, interact_min=0, flags=E.F_FULL_LEDGER, precision=prec)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=16, refill=32, interact_min=imin, flags=E.F_FULL_LEDGER,
+                precision=prec)
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
+    assert a["stats"]["steps"] == b["stats"]["steps"]
 
 
 def test_capacity_deferral_gives_identical_results(E):
