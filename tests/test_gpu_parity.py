@@ -227,6 +227,21 @@ def test_interaction_parking_does_not_change_results(E, imin, mixed):
     assert a["stats"]["steps"] == b["stats"]["steps"]
 
 
+def test_interaction_parking_extremes_at_full_size(E):
+    """10^4 x 10 GeV e- in bench.py's launch configuration with
+    interact_min 1 and 64 (parked until a wave's lanes all wait or its
+    queue is used up): the same tallies and counts as the default 24."""
+    print("interact_min extremes, cal_10GeV_e-_x10k", flush=True)
+    geo, cfg, prim = I.workload("cal_10GeV_e-_x10k")
+    n = len(prim)
+    runs = {m: run_gpu(E, geo, cfg, prim, n, capacity=1 << 25, visit=16, refill=32, interact_min=m,
+                       flags=E.F_FULL_LEDGER) for m in (24, 1, 64)}
+    for m in (1, 64):
+        assert np.allclose(runs[m]["edep"], runs[24]["edep"], rtol=1e-12, atol=1e-9), m
+        for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+            assert np.array_equal(runs[m]["ledger"][f], runs[24]["ledger"][f]), (m, f)
+
+
 def test_capacity_deferral_gives_identical_results(E):
     print("deferral", flush=True)
     geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
