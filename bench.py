@@ -301,15 +301,21 @@ def atomics_report(leg, workload, peak):
     return out
 
 
-def kernel_source_digest():
-    """SHA-256 over the kernel sources: HBM traffic figures taken with
-    counters are valid only for the kernels they were measured on."""
+def kernel_source_digest(csrc=None):
+    """SHA-256 over the kernel sources with their comments and blank space
+    removed: counter figures are valid only for the code they were measured
+    on, and a comment does not change the code."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2209_15445_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2209_15445_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+            text = open(os.path.join(csrc, name), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(" ".join(line.split()) for line in text.splitlines() if line.strip())
+            h.update(name.encode() + b"\0" + code.encode() + b"\0")
     return h.hexdigest()
 
 

@@ -1,8 +1,7 @@
 // ems_tables.hpp -- host-built log-energy tables and their device layout.
 //
-// The paper ships physics data to the GPU once at initialisation (section 2.2,
-// G4HepEm "directly interfaces with CUDA to transfer the required physics
-// data").  Here the host builds, per material, 13 tables on the grid
+// The paper copies its physics data to the GPU once, at initialisation
+// (section 2.2).  Here the host builds, per material, 13 tables on the grid
 // E_j = E_min exp(j D), j = 0..n_bins, interpolated linearly in ln E; the step
 // kernel stages them into LDS.
 #pragma once
