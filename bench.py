@@ -175,7 +175,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
     visit = args.steps_per_visit if precision == E.FP64 else args.steps_per_visit_mixed
     c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                       launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                      interact_min=args.interact_min, precision=precision, flags=E.F_KERNEL_TIMING)
+                      interact_min=args.interact_min, photon_steps_per_visit=args.photon_steps_per_visit,
+                      photon_refill_below=args.photon_refill_below, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -223,7 +224,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
                           kms[i] / max(sum(kms), 1e-12)}
     dom = names[1] if kms[1] >= kms[0] else names[0]
     d = kern[dom]
-    key = counter_key(workload, precision == E.FP64, visit, args.refill_below, args.interact_min)
+    key = counter_key(workload, precision == E.FP64, visit, args.refill_below, args.interact_min,
+                      args.photon_steps_per_visit, args.photon_refill_below)
     roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["frac"], "traffic": traffic_for(dom, key),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
@@ -238,7 +240,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
     if args.graph_check:
         cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                            launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                           interact_min=args.interact_min, precision=precision)
+                           interact_min=args.interact_min, photon_steps_per_visit=args.photon_steps_per_visit,
+                           photon_refill_below=args.photon_refill_below, precision=precision)
         eng = E.Transport(cg, geo)
         one_step()
         torch.cuda.synchronize()
@@ -319,10 +322,11 @@ def kernel_source_digest(csrc=None):
     return h.hexdigest()
 
 
-def counter_key(workload, fp64, visit, refill, interact_min):
+def counter_key(workload, fp64, visit, refill, interact_min, photon_visit, photon_refill):
     """Rows of the counter tables are keyed by workload, form and the launch
     parameters that shape a launch's batches."""
-    return f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}i{interact_min}"
+    return (f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}i{interact_min}"
+            f"pv{photon_visit}pr{photon_refill}")
 
 
 def counted_for(kernel, workload, name="traffic.txt"):
@@ -413,6 +417,8 @@ def main():
     ap.add_argument("--refill-below", type=int, default=32)
     ap.add_argument("--interact-min", type=int, default=24,
                     help="e-/e+ batches sample interactions once this many lanes wait for one")
+    ap.add_argument("--photon-steps-per-visit", type=int, default=32, help="photon kernel, both forms")
+    ap.add_argument("--photon-refill-below", type=int, default=24, help="photon kernel, both forms")
     ap.add_argument("--cpu-events", type=int, default=2048, help="events of the timed oracle sample")
     ap.add_argument("--error-events", type=int, default=10000,
                     help="events of the mixed form compared with the FP64 oracle per layer")
@@ -494,7 +500,8 @@ def main():
                    "visits_per_step": fp["visits"], "iterations": fp["iterations"],
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below,
-                   "interact_min": args.interact_min},
+                   "interact_min": args.interact_min, "photon_steps_per_visit": args.photon_steps_per_visit,
+                   "photon_refill_below": args.photon_refill_below},
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
     }

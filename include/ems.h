@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 6u
+#define EMS_ABI_VERSION 7u
 
 typedef int32_t ems_status;
 enum {
@@ -179,6 +179,8 @@ typedef struct {
                                     lanes keep their tracks and wait (0..64;
                                     0 = every batch; results do not depend
                                     on it)                                  */
+  uint32_t photon_steps_per_visit; /* the same two for the photon kernel     */
+  uint32_t photon_refill_below;    /* (1..1024 and 0..63)                    */
   uint64_t exit_capacity;        /* outgoing-track records kept per run
                                     (0 = none; see ems_read_exits)          */
 } ems_config;

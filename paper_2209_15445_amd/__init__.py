@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
@@ -61,6 +61,7 @@ class Config(C.Structure):
                 ("max_events", C.c_uint32), ("track_capacity", C.c_uint64), ("steps_per_launch", C.c_uint32),
                 ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
                 ("steps_per_visit", C.c_uint32), ("refill_below", C.c_uint32), ("interact_min", C.c_uint32),
+                ("photon_steps_per_visit", C.c_uint32), ("photon_refill_below", C.c_uint32),
                 ("exit_capacity", C.c_uint64)]
 
 
@@ -184,7 +185,7 @@ class _GeoHolder:
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
                 launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=32,
-                interact_min=24, exit_capacity=0):
+                interact_min=24, exit_capacity=0, photon_steps_per_visit=None, photon_refill_below=None):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
     c = Config()
@@ -203,6 +204,10 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
     c.steps_per_visit = steps_per_visit
     c.refill_below = refill_below
     c.interact_min = interact_min
+    # the photon kernel's visit length and refill threshold: the shared ones
+    # unless given
+    c.photon_steps_per_visit = steps_per_visit if photon_steps_per_visit is None else photon_steps_per_visit
+    c.photon_refill_below = refill_below if photon_refill_below is None else photon_refill_below
     c.exit_capacity = exit_capacity
     return c
 

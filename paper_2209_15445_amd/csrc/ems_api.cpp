@@ -154,6 +154,9 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
   if (c->steps_per_visit < 1 || c->steps_per_visit > 1024) return fail(EMS_E_INVALID, "steps_per_visit in [1, 1024]");
   if (c->refill_below > 63) return fail(EMS_E_INVALID, "refill_below in [0, 63]");
   if (c->interact_min > 64) return fail(EMS_E_INVALID, "interact_min in [0, 64]");
+  if (c->photon_steps_per_visit < 1 || c->photon_steps_per_visit > 1024)
+    return fail(EMS_E_INVALID, "photon_steps_per_visit in [1, 1024]");
+  if (c->photon_refill_below > 63) return fail(EMS_E_INVALID, "photon_refill_below in [0, 63]");
   if (c->exit_capacity > (1ull << 32)) return fail(EMS_E_INVALID, "exit_capacity above 2^32");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
     return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
@@ -506,6 +509,8 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.steps_per_visit = cfg->steps_per_visit;
   a.refill_below = cfg->refill_below;
   a.interact_min = cfg->interact_min;
+  a.photon_steps_per_visit = cfg->photon_steps_per_visit;
+  a.photon_refill_below = cfg->photon_refill_below;
   a.precision = cfg->precision == EMS_MIXED ? 1u : 0u;
   a.env = env_for(cfg, geo, c->ts);
   a.geo = geo->n_boxes ? 1u : 0u;

@@ -141,6 +141,7 @@ struct KArgs {
   uint32_t steps_per_visit;   // steps a thread may take per launch
   uint32_t refill_below;      // batch commit/refill when at most this many lanes still step
   uint32_t interact_min;      // e-/e+: sample a batch's interactions once this many wait
+  uint32_t photon_steps_per_visit, photon_refill_below;  // the photon kernel's own two
   uint32_t precision;  // 0: FP64 kernels, 1: mixed kernels
   uint32_t waves_g, waves_l;  // waves of the photon and of the e-/e+ launch
   ExitRec* exits;             // outgoing tracks (exit_cap records)

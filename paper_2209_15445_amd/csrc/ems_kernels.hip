@@ -383,7 +383,8 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
   if (work) {
     const StepEnv<R> env = stage<R, GEO>(a, lds, PHOTONS);
     const uint32_t nxt = cur ^ 1u;
-    const int max_visit = (int)a.steps_per_visit;
+    const int max_visit = (int)(PHOTONS ? a.photon_steps_per_visit : a.steps_per_visit);
+    const uint32_t refill_below = PHOTONS ? a.photon_refill_below : a.refill_below;
     // secondary slots per species that leave room for all survivors
     const Plan plan = append_plan(a, n0, n1, n2);
     const uint32_t lim0 = plan.lim[0], lim1 = plan.lim[1], lim2 = plan.lim[2];
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     for (;;) {
       const uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin));
       // batch point: few lanes still stepping (or none, once the queue is drained)
-      if (stepping <= (drained ? 0u : a.refill_below)) {
+      if (stepping <= (drained ? 0u : refill_below)) {
         // (0) e-/e+: while the queue still has tracks, interactions are
         // sampled only once at least interact_min lanes wait for one (each
         // sampler costs the wave one pass however few lanes use it); until

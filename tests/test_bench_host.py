@@ -21,10 +21,12 @@ def default_keys():
     assert '"--steps-per-visit-mixed", type=int, default=32' in src
     assert '"--refill-below", type=int, default=32' in src
     assert '"--interact-min", type=int, default=24' in src
+    assert '"--photon-steps-per-visit", type=int, default=32' in src
+    assert '"--photon-refill-below", type=int, default=24' in src
     assert '"--workload", default="cal_10GeV_e-_x10k"' in src
     assert '"--mixed-workload", default="cal_10GeV_e-_x100k"' in src
-    return [bench.counter_key("cal_10GeV_e-_x10k", True, 16, 32, 24),
-            bench.counter_key("cal_10GeV_e-_x100k", False, 32, 32, 24)]
+    return [bench.counter_key("cal_10GeV_e-_x10k", True, 16, 32, 24, 32, 24),
+            bench.counter_key("cal_10GeV_e-_x100k", False, 32, 32, 24, 32, 24)]
 
 
 @pytest.mark.parametrize("table", ["traffic.txt", "atomics.txt"])
@@ -36,8 +38,8 @@ def test_counter_tables_match_the_kernel_sources(table):
 
 
 def test_counter_key_names_form_and_launch():
-    assert bench.counter_key("w", True, 16, 32, 24) == "w/fp64/v16r32i24"
-    assert bench.counter_key("w", False, 32, 8, 0) == "w/mixed/v32r8i0"
+    assert bench.counter_key("w", True, 16, 32, 24, 32, 24) == "w/fp64/v16r32i24pv32pr24"
+    assert bench.counter_key("w", False, 32, 8, 0, 1, 0) == "w/mixed/v32r8i0pv1pr0"
 
 
 def test_more_than_one_gpu_is_refused():

@@ -27,10 +27,11 @@ def E():
 
 
 def run_gpu(E, geo, cfg, prim, n_events, flags=0, keys=None, capacity=1 << 20, log_cap=0, profile_cap=0,
-            blocks=0, visit=16, refill=8, precision=0, interact_min=24):
+            blocks=0, visit=16, refill=8, precision=0, interact_min=24, pvisit=None, prefill=None):
     c = E.make_config(cfg, n_events, track_capacity=capacity, flags=flags, steplog_capacity=log_cap,
                       profile_capacity=profile_cap, launch_blocks=blocks, steps_per_visit=visit,
-                      refill_below=refill, precision=precision, interact_min=interact_min)
+                      refill_below=refill, precision=precision, interact_min=interact_min,
+                      photon_steps_per_visit=pvisit, photon_refill_below=prefill)
     t = E.Transport(c, geo)
     if keys is not None:
         t.set_event_keys(keys)
@@ -235,11 +236,27 @@ def test_interaction_parking_extremes_at_full_size(E):
     geo, cfg, prim = I.workload("cal_10GeV_e-_x10k")
     n = len(prim)
     runs = {m: run_gpu(E, geo, cfg, prim, n, capacity=1 << 25, visit=16, refill=32, interact_min=m,
-                       flags=E.F_FULL_LEDGER) for m in (24, 1, 64)}
+                       pvisit=32, prefill=24, flags=E.F_FULL_LEDGER) for m in (24, 1, 64)}
     for m in (1, 64):
         assert np.allclose(runs[m]["edep"], runs[24]["edep"], rtol=1e-12, atol=1e-9), m
         for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
             assert np.array_equal(runs[m]["ledger"][f], runs[24]["ledger"][f]), (m, f)
+
+
+@pytest.mark.parametrize("pvisit,prefill,mixed", [(1, 0, False), (32, 24, False), (1024, 63, False), (32, 24, True)])
+def test_photon_launch_parameters_do_not_change_results(E, pvisit, prefill, mixed):
+    """The photon kernel's own visit length and refill threshold, against
+    one step per launch for every track."""
+    print(f"photon visit {pvisit} refill {prefill} mixed={mixed}", flush=True)
+    geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+    prec = E.MIXED if mixed else E.FP64
+    a = run_gpu(E, geo, cfg, prim[:8], 8, visit=1, refill=0, interact_min=0, flags=E.F_FULL_LEDGER, precision=prec)
+    b = run_gpu(E, geo, cfg, prim[:8], 8, visit=16, refill=32, pvisit=pvisit, prefill=prefill,
+                flags=E.F_FULL_LEDGER, precision=prec)
+    assert np.allclose(a["edep"], b["edep"], rtol=1e-12, atol=1e-12)
+    for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+        assert np.array_equal(a["ledger"][f], b["ledger"][f]), f
+    assert a["stats"]["steps"] == b["stats"]["steps"]
 
 
 def test_capacity_deferral_gives_identical_results(E):
@@ -332,9 +349,10 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     geo, cfg, prim = I.workload(name)
     n = len(prim)
     # bench.py's launch configuration: FP64 visits of 16 steps, refill
-    # threshold 32, capacity 2^25 for the headline workload, 2^26 for the others
+    # threshold 32 (photons: 32 and 24), capacity 2^25 for the headline
+    # workload, 2^26 for the others
     g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 25) if name == "cal_10GeV_e-_x10k" else (1 << 26),
-                visit=16, refill=32)
+                visit=16, refill=32, pvisit=32, prefill=24)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -391,8 +409,9 @@ def test_full_size_mixed_workload(E, oracle_mod):
     print("full size mixed cal_10GeV_e-_x100k", flush=True)
     geo, cfg, prim = I.workload("cal_10GeV_e-_x100k")
     n = len(prim)
-    # as bench.py: capacity 2^28, visits of 32 steps, refill threshold 32
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 28, precision=E.MIXED, visit=32, refill=32)
+    # as bench.py: capacity 2^28, visits of 32 steps, refill threshold 32 (photons 24)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 28, precision=E.MIXED, visit=32, refill=32, pvisit=32,
+                prefill=24)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(n, 24, replace=False))
@@ -416,8 +435,9 @@ def test_full_size_mixed_species_workload_mixed_form(E, oracle_mod):
     print("full size mixed form cal_mixed_1-100GeV_bz3.8_x10k", flush=True)
     geo, cfg, prim = I.workload("cal_mixed_1-100GeV_bz3.8_x10k")
     n = len(prim)
-    # as bench.py's other workloads: capacity 2^26, visits of 32 steps, refill 32
-    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 26, precision=E.MIXED, visit=32, refill=32)
+    # as bench.py's other workloads: capacity 2^26, visits of 32 steps, refill 32 (photons 24)
+    g = run_gpu(E, geo, cfg, prim, n, capacity=1 << 26, precision=E.MIXED, visit=32, refill=32, pvisit=32,
+                prefill=24)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
     rng = np.random.default_rng(2)
     sample = np.sort(rng.choice(n, 24, replace=False))

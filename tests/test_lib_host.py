@@ -62,7 +62,8 @@ def test_config_and_geometry_validation(E):
     assert _bad(E, c, geo) == E.E_VERSION
     for field, val in (("n_bins", 1), ("emin_MeV", -1.0), ("max_events", 0), ("track_capacity", 3),
                        ("max_steps_per_track", 0), ("lin_loss_limit", 1.5), ("precision", 7),
-                       ("refill_below", 64), ("interact_min", 65)):
+                       ("refill_below", 64), ("interact_min", 65), ("photon_steps_per_visit", 0),
+                       ("photon_refill_below", 64)):
         c = E.make_config(I.RunConfig(), 4)
         setattr(c, field, val)
         assert _bad(E, c, geo) == E.E_INVALID, field
