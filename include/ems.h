@@ -166,7 +166,8 @@ typedef struct {
   uint32_t steps_per_visit;      /* steps one thread may take of one track per
                                     launch, through interactions its track
                                     survives (results do not depend on it);
-                                    1 = strictly one step of the whole
+                                    1 here and in photon_steps_per_visit =
+                                    strictly one step of the whole
                                     population per iteration               */
   uint32_t refill_below;         /* a wave commits the visits that ended and
                                     refills those lanes once at most this
@@ -179,8 +180,11 @@ typedef struct {
                                     lanes keep their tracks and wait (0..64;
                                     0 = every batch; results do not depend
                                     on it)                                  */
-  uint32_t photon_steps_per_visit; /* the same two for the photon kernel     */
-  uint32_t photon_refill_below;    /* (1..1024 and 0..63)                    */
+  uint32_t photon_steps_per_visit; /* steps_per_visit and refill_below of
+                                      the photon kernel (1..1024, 0..63); the
+                                      two above then apply to the e-/e+
+                                      kernel.  Results do not depend on them */
+  uint32_t photon_refill_below;
   uint64_t exit_capacity;        /* outgoing-track records kept per run
                                     (0 = none; see ems_read_exits)          */
 } ems_config;
