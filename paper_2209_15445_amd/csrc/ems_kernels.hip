@@ -323,12 +323,14 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 // One iteration for the photons (PHOTONS) or for the e-/e+ (otherwise).
 //
 // Batched lane refill: the lanes of a wave keep stepping their tracks while
-// more than refill_below of them are still inside a visit.  Then the lanes
-// whose visit ended commit together (secondaries, survivors, carried tracks:
-// a few atomics for the whole batch) and empty lanes take the next tracks of
-// the queue from a per-launch cursor.  Lanes thus stay busy instead of
-// waiting for the wave's longest visit, without paying one atomic per track.
-// The order in which tracks are visited does not change any result.
+// more than refill_below (photons: photon_refill_below) of them are still
+// inside a visit.  Then the lanes whose visit ended commit together
+// (secondaries, survivors, carried tracks: a few atomics for the whole
+// batch) and empty lanes take the next tracks of the queue from a
+// per-launch cursor.  Lanes thus stay busy instead of waiting for the
+// wave's longest visit, without paying one atomic per track.  The order in
+// which tracks are visited does not change any result.
+
 // Minimum resident waves per SIMD the register allocation must allow, per
 // kernel, arithmetic type and geometry kind.
 #ifndef EMS_WAVES_F64_PHOTON
