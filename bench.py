@@ -84,7 +84,9 @@ def serving(E, I, args, precision):
         pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
     c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity,
                       steps_per_launch=args.serve_steps_per_launch, steps_per_visit=args.serve_steps_per_visit,
-                      refill_below=args.refill_below, interact_min=args.interact_min, precision=precision)
+                      refill_below=args.refill_below, interact_min=args.interact_min, precision=precision,
+                      photon_steps_per_visit=args.serve_photon_steps_per_visit,
+                      photon_refill_below=args.serve_photon_refill_below)
     srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
     n_each = max(1, args.serve_requests // P)
     total = n_each * P
@@ -126,7 +128,8 @@ def serving(E, I, args, precision):
            "precision": "fp64" if precision == E.FP64 else "mixed",
            "slots": args.serve_slots, "producers": P, "window": args.serve_window,
            "iterations_per_poll": args.serve_steps_per_launch, "steps_per_visit": args.serve_steps_per_visit,
-           "interact_min": args.interact_min,
+           "interact_min": args.interact_min, "photon_steps_per_visit": args.serve_photon_steps_per_visit,
+           "photon_refill_below": args.serve_photon_refill_below,
            "admit_cap_bytes": args.serve_admit_gib << 30,
            "saturated": {"requests": total, "primaries_per_s": prims / wall, "requests_per_s": sat_rps,
                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
@@ -443,6 +446,8 @@ def main():
     ap.add_argument("--serve-admit-gib", type=int, default=8)
     ap.add_argument("--serve-steps-per-launch", type=int, default=1, help="iterations between host polls")
     ap.add_argument("--serve-steps-per-visit", type=int, default=16)
+    ap.add_argument("--serve-photon-steps-per-visit", type=int, default=32)
+    ap.add_argument("--serve-photon-refill-below", type=int, default=24)
     ap.add_argument("--no-fp64-serve", action="store_true")
     ap.add_argument("--atomic-probe", type=int, default=0,
                     help="only run the library's FP64 atomic probe with this many adds (calibrates atomic counters)")
