@@ -318,3 +318,42 @@ def test_box_validation(E):
     p["pos"][1] = (1e4, 0.0, 0.0)
     with pytest.raises(E.EmsError):
         E.debug_host_transport(good, geo, p, 2)
+
+
+def test_ctypes_structs_match_the_header(E, tmp_path):
+    """Every field of the binding's structs sits at the offset the C header
+    gives it (a C program built against include/ems.h prints them)."""
+    import ctypes as C
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"ems_material": E.Material, "ems_geometry": E.Geometry, "ems_config": E.Config,
+               "ems_run_stats": E.RunStats, "ems_server_info": E.ServerInfo}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ems.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    # the numpy record types of the read-back calls: C struct, dtype, C field
+    # name of each dtype field in order
+    records = {"ems_ledger": (E.LEDGER_DTYPE, [n for n in E.LEDGER_DTYPE.names]),
+               "ems_primary": (E.PRIMARY_DTYPE, ["event", "species", "ekin_MeV", "pos_mm", "dir"]),
+               "ems_step_record": (E.STEP_DTYPE, [n for n in E.STEP_DTYPE.names])}
+    for cname, (dt, cfields) in records.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for cf in cfields:
+            lines.append(f'  printf("{cname} {cf} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+    for cname, (dt, cfields) in records.items():
+        assert got[(cname, "sizeof")] == dt.itemsize, cname
+        for name, cf in zip(dt.names, cfields):
+            assert got[(cname, cf)] == dt.fields[name][1], (cname, cf)
