@@ -170,16 +170,30 @@ def serving(E, I, args, precision):
     return res
 
 
+# the photon kernel's visit length and refill threshold per geometry kind
+# (measured best): slab stacks favour long visits and an early refill, box
+# geometries, whose photon steps wait on box records, the opposite
+PHOTON_LAUNCH = {"slab": (32, 24), "boxes": (16, 40)}
+
+
+def photon_launch(args, geo):
+    kind = "boxes" if hasattr(geo, "world_lo") else "slab"
+    pv, pr = PHOTON_LAUNCH[kind]
+    return (pv if args.photon_steps_per_visit is None else args.photon_steps_per_visit,
+            pr if args.photon_refill_below is None else args.photon_refill_below)
+
+
 def transport_leg(E, I, workload, precision, capacity, args):
     """W warm-up steps, then K timed steps of one workload in one form."""
     import torch
     geo, cfg, prim = I.workload(workload)
     n = len(prim)
     visit = args.steps_per_visit if precision == E.FP64 else args.steps_per_visit_mixed
+    pvisit, prefill = photon_launch(args, geo)
     c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                       launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                      interact_min=args.interact_min, photon_steps_per_visit=args.photon_steps_per_visit,
-                      photon_refill_below=args.photon_refill_below, precision=precision, flags=E.F_KERNEL_TIMING)
+                      interact_min=args.interact_min, photon_steps_per_visit=pvisit,
+                      photon_refill_below=prefill, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
 
     def one_step():
@@ -228,7 +242,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
     dom = names[1] if kms[1] >= kms[0] else names[0]
     d = kern[dom]
     key = counter_key(workload, precision == E.FP64, visit, args.refill_below, args.interact_min,
-                      args.photon_steps_per_visit, args.photon_refill_below)
+                      pvisit, prefill)
     roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["frac"], "traffic": traffic_for(dom, key),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
@@ -243,8 +257,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
     if args.graph_check:
         cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                            launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                           interact_min=args.interact_min, photon_steps_per_visit=args.photon_steps_per_visit,
-                           photon_refill_below=args.photon_refill_below, precision=precision)
+                           interact_min=args.interact_min, photon_steps_per_visit=pvisit,
+                           photon_refill_below=prefill, precision=precision)
         eng = E.Transport(cg, geo)
         one_step()
         torch.cuda.synchronize()
@@ -255,7 +269,8 @@ def transport_leg(E, I, workload, precision, capacity, args):
         value_graph = n * args.steps / (time.perf_counter() - t0)
         assert eng.stats()["graph_launches"] > 0
         eng.close()
-    return dict(geo=geo, cfg=cfg, prim=prim, key=key, value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+    return dict(geo=geo, cfg=cfg, prim=prim, key=key, photon_launch=[pvisit, prefill],
+                value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
                 value_graph=value_graph,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
@@ -420,8 +435,10 @@ def main():
     ap.add_argument("--refill-below", type=int, default=32)
     ap.add_argument("--interact-min", type=int, default=24,
                     help="e-/e+ batches sample interactions once this many lanes wait for one")
-    ap.add_argument("--photon-steps-per-visit", type=int, default=32, help="photon kernel, both forms")
-    ap.add_argument("--photon-refill-below", type=int, default=24, help="photon kernel, both forms")
+    ap.add_argument("--photon-steps-per-visit", type=int, default=None,
+                    help="photon kernel, both forms (default: per geometry kind, PHOTON_LAUNCH)")
+    ap.add_argument("--photon-refill-below", type=int, default=None,
+                    help="photon kernel, both forms (default: per geometry kind, PHOTON_LAUNCH)")
     ap.add_argument("--cpu-events", type=int, default=2048, help="events of the timed oracle sample")
     ap.add_argument("--error-events", type=int, default=10000,
                     help="events of the mixed form compared with the FP64 oracle per layer")
@@ -505,8 +522,8 @@ def main():
                    "visits_per_step": fp["visits"], "iterations": fp["iterations"],
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below,
-                   "interact_min": args.interact_min, "photon_steps_per_visit": args.photon_steps_per_visit,
-                   "photon_refill_below": args.photon_refill_below},
+                   "interact_min": args.interact_min, "photon_steps_per_visit": fp["photon_launch"][0],
+                   "photon_refill_below": fp["photon_launch"][1]},
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
     }
@@ -533,6 +550,7 @@ def main():
             leg = transport_leg(E, I, wl, prec, args.extra_capacity, args)
             out["other_workloads"][f"{wl}/{tag}"] = {
                 "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
+                "photon_launch": leg["photon_launch"],
                 "track_steps_per_step": leg["track_steps"],
                 "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in leg["roofline"]["kernels"].items()}}
     if not args.no_serve and not args.no_fp64_serve:

@@ -349,10 +349,11 @@ def test_full_size_workload_sampled(E, oracle_mod, name):
     geo, cfg, prim = I.workload(name)
     n = len(prim)
     # bench.py's launch configuration: FP64 visits of 16 steps, refill
-    # threshold 32 (photons: 32 and 24), capacity 2^25 for the headline
-    # workload, 2^26 for the others
+    # threshold 32 (photons: 32 and 24 in slab stacks, 16 and 40 in box
+    # geometries), capacity 2^25 for the headline workload, 2^26 for the others
+    pv, pr = (16, 40) if hasattr(geo, "world_lo") else (32, 24)
     g = run_gpu(E, geo, cfg, prim, n, capacity=(1 << 25) if name == "cal_10GeV_e-_x10k" else (1 << 26),
-                visit=16, refill=32, pvisit=32, prefill=24)
+                visit=16, refill=32, pvisit=pv, prefill=pr)
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(n, 24, replace=False))
