@@ -187,7 +187,10 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
                 launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=32,
                 interact_min=24, exit_capacity=0, photon_steps_per_visit=None, photon_refill_below=None):
     """Config struct from a run description (any object with the physics
-    fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed)."""
+    fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed).  The
+    launch parameters (steps_per_visit, refill_below, interact_min and the
+    photon kernel's photon_steps_per_visit and photon_refill_below) shape
+    the kernels' batches and change no result."""
     c = Config()
     c.abi_version = ABI_VERSION
     c.precision = precision
