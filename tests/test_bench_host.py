@@ -21,8 +21,9 @@ def default_keys():
     assert '"--steps-per-visit-mixed", type=int, default=32' in src
     assert '"--refill-below", type=int, default=32' in src
     assert '"--interact-min", type=int, default=24' in src
-    assert '"--photon-steps-per-visit", type=int, default=32' in src
-    assert '"--photon-refill-below", type=int, default=24' in src
+    assert '"--photon-steps-per-visit", type=int, default=None' in src
+    assert '"--photon-refill-below", type=int, default=None' in src
+    assert bench.PHOTON_LAUNCH["slab"] == (32, 24)
     assert '"--workload", default="cal_10GeV_e-_x10k"' in src
     assert '"--mixed-workload", default="cal_10GeV_e-_x100k"' in src
     return [bench.counter_key("cal_10GeV_e-_x10k", True, 16, 32, 24, 32, 24),
