@@ -125,6 +125,10 @@ def lib():
         L.or_table_lookup.restype = C.c_double
         L.or_inverse_range.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_double]
         L.or_inverse_range.restype = C.c_double
+        L.or_sigma_bound.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_double, C.c_double]
+        L.or_sigma_bound.restype = C.c_double
+        L.or_sigma_total.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_double]
+        L.or_sigma_total.restype = C.c_double
         L.or_formula.argtypes = [C.c_int, C.POINTER(Material), C.c_double, C.c_double, C.c_double]
         L.or_formula.restype = C.c_double
         L.or_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
@@ -244,6 +248,14 @@ class Oracle:
 
     def inverse_range(self, material, species, r):
         return lib().or_inverse_range(self._h, material, species, r)
+
+    def sigma_bound(self, material, species, a, b):
+        """null-collision bound of an e-/e+ step spanning [a, b] MeV"""
+        return lib().or_sigma_bound(self._h, material, species, a, b)
+
+    def sigma_total(self, material, species, E):
+        """right-continuous interpolated discrete total of e-/e+ at E"""
+        return lib().or_sigma_total(self._h, material, species, E)
 
     def sample(self, which, material, E, key, track_id, step, direction=(0.0, 0.0, 1.0)):
         out = (C.c_double * 16)()

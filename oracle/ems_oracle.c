@@ -1812,6 +1812,16 @@ double or_inverse_range(const or_ctx* c, uint32_t m, uint32_t species, double r)
   return inv_range(c, tab_ptr(c, m, species == OR_POSITRON ? T_R_EP : T_R_EM), r);
 }
 
+double or_sigma_bound(const or_ctx* c, uint32_t m, uint32_t species, double a, double b) {
+  or_proclist pl = lepton_procs(c, species == OR_POSITRON);
+  return sigma_bound(c, m, &pl, a, b);
+}
+
+double or_sigma_total(const or_ctx* c, uint32_t m, uint32_t species, double E) {
+  or_proclist pl = lepton_procs(c, species == OR_POSITRON);
+  return sigtot_upper(c, m, &pl, E);
+}
+
 double or_formula(int which, const or_material* in, double cut, double E, double arg2) {
   or_mat m;
   derive_material(in, &m);

@@ -213,6 +213,14 @@ double or_table_lookup(const or_ctx* c, uint32_t m, uint32_t t, double E);
 /* Inverse range of species (1 e-, 2 e+) in material m. */
 double or_inverse_range(const or_ctx* c, uint32_t m, uint32_t species, double r);
 
+/* Null-collision bound of an e- (species 1) or e+ (2) step in material m
+ * whose energy spans [a, b]: the largest value of the interpolated discrete
+ * total cross section (1/mm) on the interval, each process counted from its
+ * threshold on (right-continuous). */
+double or_sigma_bound(const or_ctx* c, uint32_t m, uint32_t species, double a, double b);
+/* That discrete total at energy E (the same right-continuous convention). */
+double or_sigma_total(const or_ctx* c, uint32_t m, uint32_t species, double E);
+
 /* Direct formula evaluation (no tables) for pins. */
 enum {
   OR_F_SIGMA_KN = 0,      /* per-electron Klein-Nishina sigma (mm^2)      */
