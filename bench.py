@@ -323,7 +323,8 @@ def atomics_report(leg, workload, peak):
 
 
 def kernel_source_digest(csrc=None):
-    """SHA-256 over the kernel sources with their comments and blank space
+    """SHA-256 over the sources the visit kernels are built from
+    (ems_kernels.hip and the headers) with their comments and blank space
     removed: counter figures are valid only for the code they were measured
     on, and a comment does not change the code."""
     import hashlib
@@ -331,7 +332,7 @@ def kernel_source_digest(csrc=None):
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2209_15445_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name == "ems_kernels.hip" or name.endswith(".hpp"):
             text = open(os.path.join(csrc, name), encoding="utf-8").read()
             text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
             text = re.sub(r"//[^\n]*", "", text)

@@ -250,7 +250,9 @@ typedef struct {
 
 typedef struct ems_ctx ems_ctx;
 
-/* Measures the device's FP64 atomic-add throughput on a tally-like scatter:
+/* Measurement (section 5, where the paper profiles its kernels against the
+ * device's limits): the device's FP64 atomic-add throughput on a tally-like
+ * scatter:
  * n_ops adds of 1.0 by the instruction the deposit tallies use, each to a
  * cell drawn uniformly (fixed hash of the op index) from the n_cells
  * doubles at d_cells (device, zeroed here, left holding the counts).  The
@@ -260,46 +262,64 @@ typedef struct ems_ctx ems_ctx;
  * EMS_E_INVALID for null pointers or zero sizes. */
 ems_status ems_probe_atomics(void* d_cells, uint64_t n_cells, uint64_t n_ops, void* hip_stream, double* ms);
 
-/* Device workspace needed for (cfg, geo), in bytes (host outputs). */
+/* Initialisation (section 2.2: physics data built once and transferred to
+ * the GPU; section 3: per-species track arrays).  Device workspace needed
+ * for (cfg, geo), in bytes (host output): loop-control block, tables,
+ * geometry, tallies and the two track queues per species.  EMS_E_INVALID
+ * for an invalid configuration or geometry. */
 ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo,
                                uint64_t* bytes);
 
-/* Builds the tables on the host, uploads tables and geometry into the
- * caller's device workspace (d_workspace, >= ems_workspace_bytes, 256-byte
+/* Initialisation (section 2.2 for the physics tables, section 2.1 for the
+ * geometry, section 3 for the track arrays): builds the tables on the host,
+ * uploads tables and geometry into the caller's device workspace (d_workspace, >= ems_workspace_bytes, 256-byte
  * aligned) and binds the caller's HIP stream (hipStream_t; NULL = the null
- * stream).  Workspace and stream must outlive the context.  Tallies start at
- * zero and event key of row r is r. */
+ * stream).  Workspace and stream must outlive the context; the context
+ * owns only host memory, two pinned staging buffers and HIP events.
+ * Tallies start at zero and event key of row r is r.  EMS_E_INVALID for bad
+ * arguments, EMS_E_CAPACITY when bytes < ems_workspace_bytes, EMS_E_DEVICE
+ * on a HIP error; *out is untouched on error. */
 ems_status ems_create(const ems_config* cfg, const ems_geometry* geo,
                       void* d_workspace, uint64_t bytes, void* hip_stream,
                       ems_ctx** out);
 
-/* Sets the RNG event key of tally rows [first_row, first_row + n) for the
+/* Counter-based random numbers (section 2.2: the physics functions take an
+ * abstracted random-number engine): sets the RNG event key of tally rows
+ * [first_row, first_row + n) for the
  * primaries enqueued from now on (each track carries its key). Results of a
  * row depend only on (seed, key, its primaries), never on the row. Host
  * only: no device work, no synchronisation. */
 ems_status ems_set_event_keys(ems_ctx* ctx, uint32_t first_row, uint32_t n,
                               const uint32_t* host_keys);
 
-/* Validates and copies n primaries (host) into the current queues.  All or
+/* Particles in (section 4: the tracks handed to the GPU library; section
+ * 3: they enter the species' current arrays).  Validates and copies n
+ * primaries (host, 64-byte records, read before return) into the current
+ * queues.  All or
  * nothing: EMS_E_INVALID (NaN or <= 0 energy, zero direction, position
  * outside the stack, bad species, event >= max_events) or EMS_E_CAPACITY
  * leaves the context unchanged.  Asynchronous on the bound stream. */
 ems_status ems_enqueue(ems_ctx* ctx, const ems_primary* host, uint64_t n);
 
-/* Steps the whole population until no track is left.  Returns after the
- * bound stream has drained.  EMS_E_CAPACITY if the queues cannot make
+/* The stepping loop (section 3): every live track takes its steps, the
+ * secondaries are appended to the next arrays, the arrays are swapped,
+ * until no track is left; physics of section 2.2, field propagation of
+ * section 2.3.  Returns after the bound stream has drained.  EMS_E_CAPACITY if the queues cannot make
  * progress; EMS_E_DEVICE on a HIP error. */
 ems_status ems_run(ems_ctx* ctx);
 
-/* Copies deposits of rows [first, first+n) to host_out[n][n_slabs]. */
+/* Hits out (section 4: per-event hit arrays copied to the host).  Copies
+ * the FP64 deposits of rows [first, first+n) to host_out[n][n_slabs]
+ * (row-major, caller-owned); EMS_E_INVALID for rows out of range. */
 ems_status ems_read_edep(ems_ctx* ctx, uint32_t first, uint32_t n, double* host_out);
-/* Copies ledgers of rows [first, first+n) to host_out[n]. */
+/* Hits out (section 4), with the energy accounting of killed tracks that
+ * section 2.3 requires: copies the ledgers of rows [first, first+n) to
+ * host_out[n]; EMS_E_INVALID for rows out of range. */
 ems_status ems_read_ledger(ems_ctx* ctx, uint32_t first, uint32_t n, ems_ledger* host_out);
-/* Zeroes deposits, ledgers, the step log, the profile and per-row track-id
+/* Between batches (section 4: one synchronous batch after another): zeroes
+ * deposits, ledgers, the step log, the profile and per-row track-id
  * counters (asynchronous on the bound stream). */
 ems_status ems_reset_tallies(ems_ctx* ctx);
-/* Copies up to cap step records (host_out) and returns the number taken in
- * *n (may exceed cap; records beyond the configured capacity are dropped). */
 /* Tracks that left the stack since the last ems_reset_tallies (the paper's
  * hybrid contract, section 4: particles in, hits and outgoing particles
  * out): one record per track in the primary layout -- event row, species,
@@ -310,14 +330,38 @@ ems_status ems_reset_tallies(ems_ctx* ctx);
  * *n_total counts every exit, including those beyond exit_capacity. */
 ems_status ems_read_exits(ems_ctx* ctx, ems_primary* host_out, uint64_t cap, uint64_t* n_total);
 
+/* Step-by-step record of the stepping loop (section 3; tests, with
+ * EMS_F_STEPLOG): copies up to cap step records (host_out) and returns the
+ * number of steps taken in *n (may exceed cap; records beyond the
+ * configured capacity are dropped). */
 ems_status ems_read_steplog(ems_ctx* ctx, ems_step_record* host_out, uint64_t cap,
                             uint64_t* n);
-/* Live tracks per species per iteration of the last run: host_out[cap][3]. */
+/* Population per iteration of the stepping loop (section 3; with
+ * EMS_F_PROFILE; section 5 discusses how the live population sets the
+ * device's occupancy): live tracks per species per iteration of the last
+ * run, host_out[cap][3]; *n = iterations run. */
 ems_status ems_read_profile(ems_ctx* ctx, uint32_t* host_out, uint32_t cap, uint32_t* n);
+/* Counts and timings of the last run (section 5: kernel time, steps and
+ * launches of the stepping loop); host copy, no device work. */
 ems_status ems_stats(ems_ctx* ctx, ems_run_stats* out);
+/* Waits for the bound stream and frees the context's host memory, pinned
+ * buffers and events; workspace and stream stay the caller's.  NULL is
+ * accepted. */
 ems_status ems_destroy(ems_ctx* ctx);
+/* Thread-local text of the last error of the calling thread. */
 const char* ems_last_error(void);
+/* EMS_ABI_VERSION of the built library. */
 uint32_t ems_abi_version(void);
+
+/* Physics data as transferred to the GPU (section 2.2): copies the tables
+ * this context uploaded back from its device workspace, in the layout of
+ * ems_host_tables ([n_materials][11][n_bins + 1]: Compton, photo, pair
+ * (1/mm), S e- (MeV/mm), R e- (mm), Moller, brems, S e+, R e+, Bhabha,
+ * annihilation), widened to FP64 in the mixed form, so the device copy can
+ * be compared with an independent implementation.  n_doubles is the size
+ * of host_out; EMS_E_INVALID when it is too small; synchronises the bound
+ * stream. */
+ems_status ems_export_tables(ems_ctx* ctx, double* host_out, uint64_t n_doubles);
 
 /* ---------------------------------------------------------------------
  * Offload server: a device-resident continuous-batching loop in front of one
@@ -349,7 +393,10 @@ typedef struct {
                                    exit_capacity (lost to their requests)   */
 } ems_server_info;
 
-/* cfg->max_events is the number of tally slots (events in flight);
+/* Continuous batching in front of the stepping loop (section 4: particles
+ * of a region handed over, hits back per event; section 5: staggered
+ * injection).  cfg->max_events is the number of tally slots (events in
+ * flight);
  * EMS_F_STEPLOG and EMS_F_PROFILE are not available in a server.  The
  * server runs its context with EMS_F_EVENT_LIVE set: the workspace must hold
  * ems_workspace_bytes of cfg with that flag (it adds the row lists and the
@@ -361,15 +408,19 @@ typedef struct {
 ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, void* d_workspace,
                              uint64_t bytes, void* hip_stream, uint64_t admit_cap_bytes,
                              ems_server** out);
-/* Thread-safe.  Copies n (1..65536) tracks (their event field is ignored);
+/* Particles in (section 4), thread-safe.  Copies n (1..65536) tracks
+ * (host, read before return; their event field is ignored);
  * EMS_E_INVALID as for ems_enqueue; EMS_E_BUSY when 2^20 requests wait. */
 ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t n,
                              uint32_t event_key, uint64_t* ticket);
-/* Thread-safe.  Waits up to timeout_us (< 0: forever) for the ticket and
+/* Hits out per event (section 4), thread-safe.  Waits up to timeout_us
+ * (< 0: forever) for the ticket and
  * copies its deposits (edep_out[n_slabs], may be NULL) and ledger (may be
  * NULL); the ticket is released.  EMS_E_TIMEOUT, EMS_E_INVALID (unknown
  * ticket), EMS_E_STATE (the device loop failed). */
-/* As ems_server_wait, and also copies the request's outgoing tracks (with
+/* Hits and particles out (section 4: the GPU region returns its outgoing
+ * particles).  As ems_server_wait, and also copies the request's outgoing
+ * tracks (with
  * cfg->exit_capacity > 0: the capacity of exits gathered per poll) into
  * exits_out (event field = 0; *n_exits = all of the request's exits, at
  * most exits_cap copied). */
@@ -378,19 +429,23 @@ ems_status ems_server_wait_exits(ems_server* s, uint64_t ticket, int64_t timeout
                                  uint64_t* n_exits);
 ems_status ems_server_wait(ems_server* s, uint64_t ticket, int64_t timeout_us,
                            double* edep_out, ems_ledger* ledger_out);
-/* Thread-safe.  *done = 1 when the ticket's result is ready. */
+/* Thread-safe, non-blocking (section 4): *done = 1 when the ticket's
+ * result is ready; EMS_E_INVALID for an unknown ticket. */
 ems_status ems_server_poll(ems_server* s, uint64_t ticket, int* done);
 /* Blocks until every request submitted before the call has completed (the
  * paper's Flush, section 4). */
 ems_status ems_server_flush(ems_server* s);
+/* Latency and throughput of the offload loop (section 5: the batch-size
+ * and idle-time effects the paper measures); thread-safe. */
 ems_status ems_server_stats(ems_server* s, ems_server_info* out);
-/* Restarts the latency and throughput statistics. */
+/* Restarts the latency and throughput statistics (thread-safe). */
 ems_status ems_server_reset_stats(ems_server* s);
 /* Stops the driver thread (pending requests are dropped) and frees the
  * server; workspace and stream remain the caller's. */
 ems_status ems_server_destroy(ems_server* s);
 
-/* Host-only table export (no device needed), layout
+/* Physics data (section 2.2), host only (no device needed): the tables the
+ * library would upload, layout
  * [n_materials][11][n_bins+1] with tables in the order: Compton, photo, pair
  * (1/mm), S e- (MeV/mm), R e- (mm), Moller, brems, S e+, R e+, Bhabha,
  * annihilation.  Used to compare the library's tables with an independent
@@ -398,8 +453,8 @@ ems_status ems_server_destroy(ems_server* s);
 ems_status ems_host_tables(const ems_config* cfg, const ems_geometry* geo, double* host_out,
                            uint64_t n_doubles);
 
-/* Test hook, never used by ems_run: runs the library's per-track step code
- * on the host, breadth-first over a queue, for CPU-side checking before any
+/* Test hook, never used by ems_run (section 3's loop on the host): runs the
+ * library's per-track step code on the host, breadth-first over a queue, for CPU-side checking before any
  * GPU is used.  Arguments as for a run: primaries (host), n_events rows,
  * optional keys (NULL: key = row), edep [n_events][n_slabs] and ledger
  * [n_events] are overwritten, optional step log. */

@@ -120,6 +120,7 @@ def lib():
             "ems_stats": [vp, C.POINTER(RunStats)],
             "ems_destroy": [vp],
             "ems_host_tables": [C.POINTER(Config), C.POINTER(Geometry), vp, u64],
+            "ems_export_tables": [vp, vp, u64],
             "ems_debug_host_transport": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, u32, vp, vp, vp, vp, u64,
                                          C.POINTER(u64)],
             "ems_server_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, u64, C.POINTER(vp)],
@@ -346,6 +347,15 @@ class Transport:
         if len(out):
             _check(lib().ems_read_exits(self._h, out.ctypes.data_as(C.c_void_p), len(out), C.byref(n)))
         return out, n.value
+
+    def export_tables(self):
+        """The tables this context uploaded, read back from the device:
+        [n_materials, 11, n_bins + 1] in the order of host_tables (FP32
+        values widened in the mixed form)."""
+        nm = self._gh.g.n_materials
+        out = np.empty(nm * 11 * (self.config.n_bins + 1))
+        _check(lib().ems_export_tables(self._h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out.reshape(nm, 11, self.config.n_bins + 1)
 
     def stats(self):
         s = RunStats()

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,7 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kInjectChunk = 1u << 18;
+constexpr uint32_t kInjectChunkNoAlloc = 1u << 14;  // static workspace: smaller staging
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -183,8 +185,9 @@ uint64_t queue_track_bytes(const ems_config* c) {
 
 namespace {
 
-Layout plan(const ems_config* c, const ems_geometry* g) {
+Layout plan(const ems_config* c, const ems_geometry* g, uint32_t inj_chunk = kInjectChunk) {
   Layout L{};
+  L.inj_chunk = inj_chunk;
   const uint64_t nodes = c->n_bins + 1;
   L.cap = (c->track_capacity + 63) / 64 * 64;
   uint64_t o = 0;
@@ -217,7 +220,7 @@ Layout plan(const ems_config* c, const ems_geometry* g) {
   L.exits = take(c->exit_capacity * sizeof(ExitRec));
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
-  L.inj = take((uint64_t)kInjectChunk * sizeof(InjRec));
+  L.inj = take((uint64_t)inj_chunk * sizeof(InjRec));
   L.queues = take(6 * L.cap * queue_track_bytes(c));
   L.total = o;
   return L;
@@ -401,11 +404,7 @@ ems_status ems_probe_atomics(void* d_cells, uint64_t n_cells, uint64_t n_ops, vo
 const char* ems_last_error(void) { return g_err.c_str(); }
 
 ems_status ems_workspace_bytes(const ems_config* cfg, const ems_geometry* geo, uint64_t* bytes) {
-  ems_status st = check_inputs(cfg, geo);
-  if (st) return st;
-  if (!bytes) return fail(EMS_E_INVALID, "null output");
-  *bytes = plan(cfg, geo).total;
-  return EMS_OK;
+  return rt_workspace_bytes(cfg, geo, false, bytes);
 }
 
 ems_status ems_host_tables(const ems_config* cfg, const ems_geometry* geo, double* out, uint64_t n) {
@@ -421,15 +420,87 @@ ems_status ems_host_tables(const ems_config* cfg, const ems_geometry* geo, doubl
   return EMS_OK;
 }
 
+ems_status ems_export_tables(ems_ctx* c, double* out, uint64_t n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  const uint64_t nodes = c->ts.nodes, nm = c->geo.n_materials;
+  const uint64_t need = nm * kNumExport * nodes;
+  if (!out || n < need) return fail(EMS_E_INVALID, "output buffer too small");
+  // the device copy as uploaded: photon block [mat][3][nodes] (padded to 8
+  // bytes), then the lepton block [mat][10][nodes], in the form's type
+  const uint64_t rb = real_bytes(&c->cfg);
+  const uint64_t gbytes = (nm * kGammaTables * nodes * rb + 7) / 8 * 8;
+  const uint64_t lbytes = nm * kLeptonTables * nodes * rb;
+  std::vector<char> dev(gbytes + lbytes);
+  HIPCHK(c, hipMemcpyAsync(dev.data(), c->ws + c->L.tab, dev.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  auto value = [&](uint64_t byte_off, uint64_t i) {
+    if (rb == 4) {
+      float f;
+      memcpy(&f, dev.data() + byte_off + i * 4, 4);
+      return (double)f;
+    }
+    double d;
+    memcpy(&d, dev.data() + byte_off + i * 8, 8);
+    return d;
+  };
+  for (uint64_t m = 0; m < nm; ++m)
+    for (int t = 0; t < kNumExport; ++t)
+      for (uint64_t j = 0; j < nodes; ++j)
+        out[(m * kNumExport + t) * nodes + j] =
+            t < kGammaTables ? value(0, (m * kGammaTables + t) * nodes + j)
+                             : value(gbytes, (m * kLeptonTables + (t - kGammaTables)) * nodes + j);
+  return EMS_OK;
+}
+
 ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws, uint64_t bytes, void* stream,
                       ems_ctx** out) {
+  return rt_create(cfg, geo, d_ws, bytes, stream, false, out);
+}
+
+}  // extern "C"
+
+namespace ems {
+
+namespace {
+std::mutex g_static_mu;
+bool g_static_held[kMaxStaticDevices];
+}  // namespace
+
+bool rt_hold_static(int dev) {
+  if (dev < 0 || dev >= kMaxStaticDevices) return false;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_held[dev]) return false;
+  g_static_held[dev] = true;
+  return true;
+}
+
+void rt_release_static(int dev) {
+  if (dev < 0 || dev >= kMaxStaticDevices) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  g_static_held[dev] = false;
+}
+
+ems_status rt_workspace_bytes(const ems_config* cfg, const ems_geometry* geo, bool no_alloc, uint64_t* bytes) {
+  ems_status st = check_inputs(cfg, geo);
+  if (st) return st;
+  if (!bytes) return fail(EMS_E_INVALID, "null output");
+  *bytes = plan(cfg, geo, no_alloc ? kInjectChunkNoAlloc : kInjectChunk).total;
+  return EMS_OK;
+}
+
+ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws, uint64_t bytes, void* stream,
+                     bool no_alloc, ems_ctx** out) {
   ems_status st = check_inputs(cfg, geo);
   if (st) return st;
   if (!out || !d_ws) return fail(EMS_E_INVALID, "null workspace or output");
   if (((uintptr_t)d_ws) % kAlign) return fail(EMS_E_INVALID, "workspace must be 256-byte aligned");
-  Layout L = plan(cfg, geo);
+  if (no_alloc && (cfg->flags & (EMS_F_KERNEL_TIMING | EMS_F_EVENT_LIVE)))
+    return fail(EMS_E_INVALID, "a context without allocations takes neither EMS_F_KERNEL_TIMING nor EMS_F_EVENT_LIVE");
+  Layout L = plan(cfg, geo, no_alloc ? kInjectChunkNoAlloc : kInjectChunk);
   if (bytes < L.total) return fail(EMS_E_CAPACITY, "workspace smaller than ems_workspace_bytes");
   ems_ctx* c = new ems_ctx();
+  c->no_alloc = no_alloc;
   c->cfg = *cfg;
   c->mats.assign(geo->materials, geo->materials + geo->n_materials);
   c->geo = *geo;
@@ -535,10 +606,19 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   a.waves_g = c->blocks_g * 4;  // 256-thread blocks of 64-lane waves
   a.waves_l = c->blocks_l * 4;
 
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_inj), kInjectChunk * sizeof(InjRec)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
-      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+  if (no_alloc) {
+    // ordinary host memory for the staging and the status block; no events,
+    // chunks launched directly (no graph)
+    c->host_inj.resize(L.inj_chunk);
+    c->pin_inj = c->host_inj.data();
+    c->pin_ctl = &c->host_ctl;
+    c->graph_off = true;
+  } else if (hipHostMalloc(reinterpret_cast<void**>(&c->pin_inj), (uint64_t)L.inj_chunk * sizeof(InjRec)) !=
+                 hipSuccess ||
+             hipHostMalloc(reinterpret_cast<void**>(&c->pin_ctl), sizeof(Ctl)) != hipSuccess ||
+             hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     return bad(fail(EMS_E_DEVICE, "pinned host allocation or event creation failed"));
+  }
   // device table layout: photon block [mat][3][nodes], then lepton block
   // [mat][10][nodes], in the arithmetic type of the chosen form
   std::vector<char> packed, elem;
@@ -560,7 +640,7 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
       return bad(fail(EMS_E_DEVICE, "pinned host allocation failed"));
   }
   hipStream_t s = c->stream;
-  bool ok = hipMemsetAsync(c->ws + L.ctl, 0, sizeof(Ctl), s) == hipSuccess &&
+  bool ok = launch_fill_zero(c->ws + L.ctl, sizeof(Ctl), s) == hipSuccess &&
             hipMemcpyAsync(c->ws + L.tab, packed.data(), packed.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
             (c->z.empty() ||
              hipMemcpyAsync(c->ws + L.zp, c->z.data(), c->z.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess) &&
@@ -581,21 +661,36 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
             hipMemcpyAsync(c->ws + L.mat, rt.data(), rt.size() * sizeof(MatRT), hipMemcpyHostToDevice, s) ==
                 hipSuccess &&
             hipMemcpyAsync(c->ws + L.elem, elem.data(), elem.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
-            hipMemsetAsync(c->ws + L.edep, 0, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
-            hipMemsetAsync(c->ws + L.queues, 0, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
+            launch_fill_zero(c->ws + L.edep, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
+            launch_fill_zero(c->ws + L.queues, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
-    (void)hipHostFree(c->pin_inj);
-    (void)hipHostFree(c->pin_ctl);
+    if (!no_alloc) {
+      (void)hipHostFree(c->pin_inj);
+      (void)hipHostFree(c->pin_ctl);
+      if (c->pin_rows) (void)hipHostFree(c->pin_rows);
+      if (c->pin_gather) (void)hipHostFree(c->pin_gather);
+      (void)hipEventDestroy(c->ev0);
+      (void)hipEventDestroy(c->ev1);
+    }
     return bad(fail(EMS_E_DEVICE, "workspace initialisation failed"));
   }
   *out = c;
   return EMS_OK;
 }
 
+}  // namespace ems
+
+extern "C" {
+
 ems_status ems_destroy(ems_ctx* c) {
   if (!c) return EMS_OK;
   (void)hipStreamSynchronize(c->stream);
+  if (c->no_alloc) {
+    rt_release_static(c->device);
+    delete c;
+    return EMS_OK;
+  }
   if (c->pin_inj) (void)hipHostFree(c->pin_inj);
   if (c->pin_ctl) (void)hipHostFree(c->pin_ctl);
   if (c->pin_rows) (void)hipHostFree(c->pin_rows);
@@ -675,11 +770,11 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   const Layout& L = c->L;
-  HIPCHK(c, hipMemsetAsync(c->ws + L.edep, 0, (uint64_t)c->cfg.max_events * c->ncols * 8, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->ws + L.ledger, 0, (uint64_t)c->cfg.max_events * sizeof(LedgerDev), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->ws + L.live, 0, (uint64_t)c->cfg.max_events * 4, c->stream));
+  HIPCHK(c, launch_fill_zero(c->ws + L.edep, (uint64_t)c->cfg.max_events * c->ncols * 8, c->stream));
+  HIPCHK(c, launch_fill_zero(c->ws + L.ledger, (uint64_t)c->cfg.max_events * sizeof(LedgerDev), c->stream));
+  HIPCHK(c, launch_fill_zero(c->ws + L.live, (uint64_t)c->cfg.max_events * 4, c->stream));
   if (c->args.profile_cap)
-    HIPCHK(c, hipMemsetAsync(c->ws + L.profile, 0, (uint64_t)c->args.profile_cap * 12, c->stream));
+    HIPCHK(c, launch_fill_zero(c->ws + L.profile, (uint64_t)c->args.profile_cap * 12, c->stream));
   // keep the queues (empty after a run) but restart counters and statistics
   HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -911,8 +1006,8 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   std::vector<InjRec> recs;
   ems_status st = prepare(c->geo, &c->nav, c->cfg.max_events, p, n, rows, c->keys, recs);
   if (st) return st;
-  for (uint64_t done = 0; done < n; done += kInjectChunk) {
-    const uint32_t k = (uint32_t)std::min<uint64_t>(kInjectChunk, n - done);
+  for (uint64_t done = 0; done < n; done += c->L.inj_chunk) {
+    const uint32_t k = (uint32_t)std::min<uint64_t>(c->L.inj_chunk, n - done);
     HIPCHK(c, hipStreamSynchronize(c->stream));  // pinned staging is free again
     memcpy(c->pin_inj, recs.data() + done, k * sizeof(InjRec));
     InjRec* d = reinterpret_cast<InjRec*>(c->ws + c->L.inj);
@@ -975,18 +1070,19 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
     c->graph_off = true;
     graph = false;
   }
-  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  const bool span = c->ev0 != nullptr;  // contexts without allocations keep no events
+  if (span) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   if (graph) {
     HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     c->stats.graph_launches += 1;
   } else {
     HIPCHK(c, enqueue_chunk(c, K, timing));
   }
-  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  if (span) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->pin_ctl, c->ws + c->L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   float ms = 0.0f;
-  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (span) HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const Ctl& s = *c->pin_ctl;
   ems_run_stats& st = c->stats;
   st.step_kernel_ms += ms;
@@ -1070,7 +1166,7 @@ ems_status rt_take_exits(ems_ctx* c, std::vector<ems_primary>& out, uint64_t* to
   if (*total == 0) return EMS_OK;
   out.resize(k);
   if (k) HIPCHK(c, hipMemcpyAsync(out.data(), c->ws + c->L.exits, k * sizeof(ExitRec), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->ws + c->L.ctl + offsetof(Ctl, exit_n), 0, sizeof(unsigned long long), c->stream));
+  HIPCHK(c, launch_fill_zero(c->ws + c->L.ctl + offsetof(Ctl, exit_n), sizeof(unsigned long long), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->pin_ctl->exit_n = 0;
   return EMS_OK;

@@ -710,6 +710,17 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
   }
 }
 
+// Zero `words` 8-byte words at p and then `ntail` single bytes at tail, with
+// plain vector stores (grid-stride).  The library clears its device memory
+// with this kernel instead of memset nodes, which a caller capturing the
+// stream into a graph could not rely on.
+__global__ __launch_bounds__(kBlock) void k_fill_zero(unsigned long long* p, uint64_t words, unsigned char* tail,
+                                                      uint32_t ntail) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) p[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
 // Atomic-throughput probe: FP64 adds of 1.0, the instruction of the deposit
 // tallies, to cells drawn by a fixed hash of the op index (grid-stride).
 __global__ __launch_bounds__(kBlock) void k_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops) {
@@ -844,6 +855,16 @@ hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, 
   const uint64_t want = (n_ops + kBlock - 1) / kBlock;
   const uint32_t blocks = (uint32_t)(want < 16384 ? (want ? want : 1) : 16384);
   hipLaunchKernelGGL(k_atomic_probe, dim3(blocks), dim3(kBlock), 0, s, cells, n_cells, n_ops);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (reinterpret_cast<uintptr_t>(p) % 8) return hipErrorInvalidValue;
+  const uint64_t words = bytes / 8;
+  const uint64_t want = (words + kBlock - 1) / kBlock;
+  const uint32_t blocks = (uint32_t)(want == 0 ? 1 : (want < 8192 ? want : 8192));
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(kBlock), 0, s, static_cast<unsigned long long*>(p), words,
+                     static_cast<unsigned char*>(p) + words * 8, (uint32_t)(bytes % 8));
   return hipGetLastError();
 }
 hipError_t launch_census(const KArgs& a, hipStream_t s) {

@@ -19,11 +19,14 @@ hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, 
 hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s);
 hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s);
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
+// zero bytes at p (8-byte aligned) with a kernel on stream s
+hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s);
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
   uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, brec, nbr_off, nbr, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t cap;
+  uint32_t inj_chunk;  // primaries staged per injection launch
 };
 
 // bytes of one queued track in the configured form
@@ -77,6 +80,11 @@ struct ems_ctx {
   uint32_t graph_k = 0;
   bool graph_off = false;  // capture failed once: direct launches
   bool failed = false;
+  // created by ems_create_static: the workspace is the library's static
+  // device array, host staging is ordinary memory, no events, no graphs
+  bool no_alloc = false;
+  std::vector<InjRec> host_inj;
+  Ctl host_ctl{};
   ems_run_stats stats{};
 };
 
@@ -90,6 +98,19 @@ struct ems_ctx {
   } while (0)
 
 namespace ems {
+// workspace bytes of (cfg, geo); no_alloc: the layout of a context without
+// allocations (smaller injection staging)
+ems_status rt_workspace_bytes(const ems_config* cfg, const ems_geometry* geo, bool no_alloc, uint64_t* bytes);
+// ems_create, with or without allocations of its own (pinned staging,
+// events, graphs); no_alloc refuses EMS_F_KERNEL_TIMING and EMS_F_EVENT_LIVE
+ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws, uint64_t bytes, void* stream,
+                     bool no_alloc, ems_ctx** out);
+// One context at a time may hold a device's static workspace (the
+// library's device array behind ems_create_static): rt_hold_static returns
+// false while another context holds it; ems_destroy releases it.
+constexpr int kMaxStaticDevices = 64;
+bool rt_hold_static(int dev);
+void rt_release_static(int dev);
 // validate, prepare and append n primaries to the current queues (all or
 // nothing); rows listed in fresh_rows restart their track ids at 0
 ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n);

@@ -157,3 +157,76 @@ def test_server_with_box_geometry(E, oracle_mod):
     p["event"] = 0
     r = oracle_mod.Oracle(geo, cfg).run(p, n_events=1, event_keys=np.array([4242], dtype=np.uint32))
     assert np.allclose(r["edep"][0], alone[0], rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_same_result_alone_and_in_the_64_producer_mix(E, oracle_mod, precision):
+    """The serving recipe at its producer count: 64 host threads each submit
+    requests of U{1..200} e-/e+/gamma tracks with lognormal(ln 5 GeV, 1)
+    total energy in Bz = 3.8 T, with four probe requests submitted from
+    different producers in the middle of the mix.  Each probe gives the
+    same deposits per slab (1e-12) and the same counts as when it ran alone
+    on an empty server, in both forms; every request conserves energy (1e-9
+    FP64, 1e-5 mixed); the FP64 probes equal the oracle's (1e-8)."""
+    print(f"64-producer mix, {precision}", flush=True)
+    prec = E.FP64 if precision == "fp64" else E.MIXED
+    geo = I.calorimeter()
+    cfg = I.RunConfig(seed=5, bz_tesla=3.8)
+    c = E.make_config(cfg, 512, track_capacity=1 << 22, steps_per_launch=1, precision=prec,
+                      flags=E.F_FULL_LEDGER, photon_steps_per_visit=32, photon_refill_below=24)
+    prng = np.random.Generator(np.random.Philox(4321))
+    probes = [(I.serving_request(prng), 900_000 + i) for i in range(4)]
+    srv = E.Server(c, geo, 8 << 30)
+    alone = [srv.wait(srv.submit(tr, k), timeout_s=120) for tr, k in probes]
+    srv.close()
+
+    srv = E.Server(c, geo, 8 << 30)
+    results, reqs = {}, {}
+    lock = threading.Lock()
+    per_producer = 6
+
+    def producer(p):
+        rng = np.random.Generator(np.random.Philox(5 + p))
+        mine = []
+        for i in range(per_producer):
+            tr = I.serving_request(rng)
+            mine.append((srv.submit(tr, p * 1000 + i), tr, p * 1000 + i))
+            if p % 16 == 3 and i == per_producer // 2:
+                tr, k = probes[p // 16]
+                mine.append((srv.submit(tr, k), tr, k))
+        for t, tr, k in mine:
+            r = srv.wait(t, timeout_s=300)
+            with lock:
+                results[t] = r
+                reqs[t] = (tr, k)
+
+    ths = [threading.Thread(target=producer, args=(p,)) for p in range(64)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    st = srv.stats()
+    srv.close()
+    assert len(results) == 64 * per_producer + 4 and st["completed"] == len(results)
+    print("peak admitted bytes", st["peak_admitted_bytes"], "chunks", st["chunks"], flush=True)
+    by_key = {k: results[t] for t, (tr, k) in reqs.items()}
+    worst = 0.0
+    for (tr, k), (a_edep, a_led) in zip(probes, alone):
+        m_edep, m_led = by_key[k]
+        scale = max(1.0, float(np.abs(a_edep).max()))
+        worst = max(worst, float(np.abs(m_edep - a_edep).max()) / scale)
+        for f in ("n_steps", "n_created", "n_null", "n_pair", "n_annih"):
+            assert np.array_equal(m_led[f], a_led[f]), (k, f)
+    print("largest alone-vs-mix deposit difference (relative)", worst, flush=True)
+    assert worst <= 1e-12
+    tol = 1e-9 if prec == E.FP64 else 1e-5
+    for t, (edep, led) in results.items():
+        assert residual(edep, led, reqs[t][0]) < tol
+    if prec == E.FP64:
+        o = oracle_mod.Oracle(geo, cfg)
+        for (tr, k), (a_edep, a_led) in zip(probes, alone):
+            p = tr.copy()
+            p["event"] = 0
+            r = o.run(p, n_events=1, event_keys=np.array([k], dtype=np.uint32))
+            assert np.allclose(a_edep, r["edep"][0], rtol=1e-8, atol=1e-8)
+            assert int(a_led["n_steps"]) == int(r["ledger"]["n_steps"][0])
