@@ -283,6 +283,34 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo,
                       void* d_workspace, uint64_t bytes, void* hip_stream,
                       ems_ctx** out);
 
+/* Bytes of the library's static device workspace: one copy per GPU the
+ * library runs on, held from the loading of the library until the process
+ * ends. */
+#define EMS_STATIC_WORKSPACE_BYTES (64ull << 20)
+
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): ems_create without a caller
+ * workspace.  The context runs in the library's static workspace of the
+ * current device (EMS_STATIC_WORKSPACE_BYTES) and binds hip_stream (NULL =
+ * the null stream).  Neither this call nor any later call on the context
+ * allocates device memory or pinned host memory (no hipMalloc, hipFree,
+ * hipHostMalloc, graphs or events): host staging is ordinary memory and
+ * every chunk of iterations is launched directly.  Inputs (primaries) and
+ * outputs (deposits, ledgers, exits) are passed as with ems_create; every
+ * other entry point works on the context as on one from ems_create.
+ * ems_create clears the control block, the tallies and the queues (the
+ * array keeps the contents of the previous context on that GPU).  One
+ * context at a time may hold a GPU's static workspace: two contexts on one
+ * GPU would race on it, so a second call before ems_destroy of the first
+ * returns EMS_E_BUSY.  EMS_E_CAPACITY when the configuration needs more than
+ * EMS_STATIC_WORKSPACE_BYTES (the message names the bytes needed; a smaller
+ * track_capacity or max_events fits); EMS_E_INVALID for a bad configuration
+ * or for the flags EMS_F_KERNEL_TIMING and EMS_F_EVENT_LIVE (they need
+ * events and pinned memory); EMS_E_DEVICE on a HIP error. *out is untouched
+ * on error. */
+ems_status ems_create_static(const ems_config* cfg, const ems_geometry* geo,
+                             void* hip_stream, ems_ctx** out);
+
 /* Counter-based random numbers (section 2.2: the physics functions take an
  * abstracted random-number engine): sets the RNG event key of tally rows
  * [first_row, first_row + n) for the

@@ -108,6 +108,7 @@ def lib():
         sig = {
             "ems_workspace_bytes": [C.POINTER(Config), C.POINTER(Geometry), C.POINTER(u64)],
             "ems_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, C.POINTER(vp)],
+            "ems_create_static": [C.POINTER(Config), C.POINTER(Geometry), vp, C.POINTER(vp)],
             "ems_set_event_keys": [vp, u32, u32, vp],
             "ems_enqueue": [vp, vp, u64],
             "ems_run": [vp],
@@ -264,23 +265,31 @@ class Transport:
     The workspace is a torch uint8 tensor on the device; the stream is the
     given torch stream, by default a stream of its own (default priority):
     chunks of iterations are replayed as captured graphs, which the null
-    stream does not allow."""
+    stream does not allow.  With static_workspace=True the context runs in
+    the library's static device workspace instead (ems_create_static: no
+    device allocation by the library or by this wrapper; one such context
+    per device at a time)."""
 
-    def __init__(self, config, geometry, stream=None, device="cuda"):
+    def __init__(self, config, geometry, stream=None, device="cuda", static_workspace=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the transport runs only on the GPU")
         self.config = config
         self._gh = _GeoHolder(geometry)
         self.n_slabs = self._gh.n_slabs
-        nbytes = workspace_bytes(config, geometry)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.Stream()
         h = C.c_void_p()
-        _check(lib().ems_create(C.byref(config), C.byref(self._gh.g), C.c_void_p(self._ws_ptr), nbytes,
-                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if static_workspace:
+            self.workspace = None
+            _check(lib().ems_create_static(C.byref(config), C.byref(self._gh.g),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            nbytes = workspace_bytes(config, geometry)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            _check(lib().ems_create(C.byref(config), C.byref(self._gh.g), C.c_void_p(self._ws_ptr), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
 
     def close(self):

@@ -458,6 +458,30 @@ ems_status ems_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws
   return rt_create(cfg, geo, d_ws, bytes, stream, false, out);
 }
 
+ems_status ems_create_static(const ems_config* cfg, const ems_geometry* geo, void* stream, ems_ctx** out) {
+  uint64_t need = 0;
+  ems_status st = rt_workspace_bytes(cfg, geo, true, &need);
+  if (st) return st;
+  if (!out) return fail(EMS_E_INVALID, "null output");
+  if (need > kStaticWorkspaceBytes)
+    return fail(EMS_E_CAPACITY, "the configuration needs " + std::to_string(need) +
+                                    " workspace bytes; the static workspace holds " +
+                                    std::to_string(kStaticWorkspaceBytes));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(EMS_E_DEVICE, "no HIP device");
+  if (dev < 0 || dev >= kMaxStaticDevices) return fail(EMS_E_INVALID, "device index beyond the static workspaces");
+  if (!rt_hold_static(dev)) return fail(EMS_E_BUSY, "another context holds this device's static workspace");
+  void* ws = nullptr;
+  const hipError_t e = static_workspace(dev, &ws);
+  if (e != hipSuccess) {
+    rt_release_static(dev);
+    return fail(EMS_E_DEVICE, std::string("static workspace address: ") + hipGetErrorString(e));
+  }
+  st = rt_create(cfg, geo, ws, kStaticWorkspaceBytes, stream, true, out);
+  if (st) rt_release_static(dev);
+  return st;
+}
+
 }  // extern "C"
 
 namespace ems {

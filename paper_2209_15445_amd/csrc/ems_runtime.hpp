@@ -111,6 +111,10 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
 constexpr int kMaxStaticDevices = 64;
 bool rt_hold_static(int dev);
 void rt_release_static(int dev);
+// size of the static workspace (one copy per GPU) and the device address of
+// device dev's copy, taken once per device with that device current
+constexpr uint64_t kStaticWorkspaceBytes = EMS_STATIC_WORKSPACE_BYTES;
+hipError_t static_workspace(int dev, void** p);
 // validate, prepare and append n primaries to the current queues (all or
 // nothing); rows listed in fresh_rows restart their track ids at 0
 ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n);

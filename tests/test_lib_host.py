@@ -357,3 +357,19 @@ def test_ctypes_structs_match_the_header(E, tmp_path):
         assert got[(cname, "sizeof")] == dt.itemsize, cname
         for name, cf in zip(dt.names, cfields):
             assert got[(cname, cf)] == dt.fields[name][1], (cname, cf)
+
+
+def test_static_workspace_refuses_a_configuration_beyond_its_size(E):
+    # checked before any HIP call: runs without a GPU
+    import ctypes as C
+    geo, cfg, _ = I.workload("cal_1GeV_e-_x32")
+    big = E.make_config(cfg, 32, track_capacity=1 << 20)
+    gh = E._GeoHolder(geo)
+    h = C.c_void_p()
+    rc = E.lib().ems_create_static(C.byref(big), C.byref(gh.g), None, C.byref(h))
+    assert rc == E.E_CAPACITY and h.value is None
+    msg = E.lib().ems_last_error().decode()
+    assert "static workspace holds" in msg and str(64 << 20) in msg
+    bad = E.make_config(cfg, 32, track_capacity=1 << 14)
+    bad.abi_version = 1
+    assert E.lib().ems_create_static(C.byref(bad), C.byref(gh.g), None, C.byref(h)) == E.E_VERSION
