@@ -70,11 +70,15 @@ def cpu_baseline(geo, cfg, prim, n_events, threads):
 def serving(E, I, args, precision):
     """Offload-server leg.  Requests: U{1..200} e-/e+/gamma tracks, total
     energy lognormal(ln 5 GeV, 1) clamped to [10 MeV, 2 TeV], Bz 3.8 T, from
-    P producer threads (a pool of distinct requests per producer, reused
-    with fresh event keys).  First the saturated closed loop (each producer
-    keeps a window of requests outstanding), then Poisson arrivals at 80% of
-    that request rate; latency is submission to completion, with the first
-    10% of the completions dropped."""
+    P producer threads (native threads of ems_server_drive, so the load is
+    not limited by the interpreter; a pool of distinct requests per
+    producer, reused with fresh event keys).  First the saturated closed
+    loop (each producer keeps a window of requests outstanding; latency
+    from submission), then Poisson arrivals at 80% of that request rate from
+    a schedule fixed in advance, latency counted from each request's
+    scheduled arrival, so a producer running late adds its delay to the
+    latency instead of hiding it.  The first 10% of the completions of each
+    leg are dropped from its statistics."""
     geo = I.calorimeter()
     cfg = I.RunConfig(seed=5, bz_tesla=3.8)
     P = args.serve_producers
@@ -94,39 +98,35 @@ def serving(E, I, args, precision):
     def req(p, i):
         return pools[p][i % len(pools[p])]
 
-    def drop_warmup(target):
+    def drop_warmup(target, stop):
         # clear the statistics once the first 10% of the requests are done
-        t_end = time.perf_counter() + 300
-        while srv.stats()["completed"] < target and time.perf_counter() < t_end:
+        while srv.stats()["completed"] < target and not stop.is_set():
             time.sleep(0.002)
         srv.reset_stats()
 
-    def closed(p, base):
-        pending = []
-        for i in range(n_each):
-            if len(pending) >= args.serve_window:
-                srv.wait(pending.pop(0), timeout_s=300)
-            pending.append(srv.submit(req(p, i), base + p * 1_000_000 + i))
-        for t in pending:
-            srv.wait(t, timeout_s=300)
+    def run_leg(producers, window):
+        srv.reset_stats()
+        stop = threading.Event()
+        mon = threading.Thread(target=drop_warmup, args=(total // 10, stop))
+        mon.start()
+        t0 = time.monotonic_ns()
+        try:
+            lag, last = srv.drive(producers, window)
+        finally:
+            stop.set()
+            mon.join()
+        return lag, last, t0, time.monotonic_ns()
 
-    srv.reset_stats()
-    mon = threading.Thread(target=drop_warmup, args=(total // 10,))
-    t0 = time.perf_counter()
-    mon.start()
-    ths = [threading.Thread(target=closed, args=(p, 0)) for p in range(P)]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
-    mon.join()
-    wall = time.perf_counter() - t0
+    prims = sum(len(req(p, i)) for p in range(P) for i in range(n_each))
+    closed = [[(req(p, i), p * 1_000_000 + i, 0) for i in range(n_each)] for p in range(P)]
+    _, _, t0, t1 = run_leg(closed, args.serve_window)
+    wall = (t1 - t0) / 1e9
     sat = srv.stats()
     sat_rps = total / wall
-    prims = sum(len(req(p, i)) for p in range(P) for i in range(n_each))
     res = {"workload": "serving: requests of U{1..200} e-/e+/gamma tracks, lognormal(ln 5 GeV, 1) total, Bz 3.8 T",
            "precision": "fp64" if precision == E.FP64 else "mixed",
-           "slots": args.serve_slots, "producers": P, "window": args.serve_window,
+           "producers": f"{P} native threads (ems_server_drive)",
+           "slots": args.serve_slots, "window": args.serve_window,
            "iterations_per_poll": args.serve_steps_per_launch, "steps_per_visit": args.serve_steps_per_visit,
            "interact_min": args.interact_min, "photon_steps_per_visit": args.serve_photon_steps_per_visit,
            "photon_refill_below": args.serve_photon_refill_below,
@@ -135,38 +135,29 @@ def serving(E, I, args, precision):
                          "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
                          "peak_admitted_bytes": sat["peak_admitted_bytes"]}}
     rate = 0.8 * sat_rps / P
-
-    def open_loop(p):
-        rng = np.random.default_rng(100 + p)
-        gaps = rng.exponential(1.0 / rate, n_each)
-        t_next = time.perf_counter()
-        ts = []
-        for i in range(n_each):
-            t_next += gaps[i]
-            d = t_next - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            ts.append(srv.submit(req(p, i), 500_000 + p * 1_000_000 + i))
-        for t in ts:
-            srv.wait(t, timeout_s=300)
-
-    srv.reset_stats()
-    mon = threading.Thread(target=drop_warmup, args=(total // 10,))
-    t0 = time.perf_counter()
-    mon.start()
-    ths = [threading.Thread(target=open_loop, args=(p,)) for p in range(P)]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
-    mon.join()
-    wall = time.perf_counter() - t0
+    # each producer's arrivals are fixed in advance: a Poisson process of
+    # rate/P from a seeded generator
+    t_start = time.monotonic_ns() + 100_000_000
+    sched = [t_start + np.cumsum(np.random.default_rng(100 + p).exponential(1e9 / rate, n_each)).astype(np.int64)
+             for p in range(P)]
+    opened = [[(req(p, i), 500_000 + p * 1_000_000 + i, int(sched[p][i])) for i in range(n_each)]
+              for p in range(P)]
+    lag, last, _, t_end = run_leg(opened, 1)
     po = srv.stats()
     srv.close()
+    span = (max(int(a[-1]) for a in sched) - t_start) / 1e9  # the schedule's length
+    sub = (last - t_start) / 1e9                              # submissions took
+    wall = (t_end - t_start) / 1e9                            # to the last result
+    achieved = total / max(sub, span)
     res["poisson_80pct"] = {"requests": total, "offered_requests_per_s": rate * P,
-                            "achieved_requests_per_s": total / wall, "p50_ms": po["p50_ms"],
-                            "p99_ms": po["p99_ms"], "mean_ms": po["mean_ms"], "max_ms": po["max_ms"],
-                            "primaries_per_s": prims / wall, "dropped_warmup_requests": total // 10}
+                            "achieved_requests_per_s": achieved,
+                            "achieved_over_offered": achieved / (rate * P),
+                            "below_95pct_of_offered": achieved < 0.95 * rate * P,
+                            "max_submission_lag_ms": lag,
+                            "latency_from": "scheduled arrival",
+                            "p50_ms": po["p50_ms"], "p99_ms": po["p99_ms"], "mean_ms": po["mean_ms"],
+                            "max_ms": po["max_ms"], "primaries_per_s": prims / wall,
+                            "dropped_warmup_requests": total // 10}
     return res
 
 
@@ -324,20 +315,28 @@ def atomics_report(leg, workload, peak):
 
 def kernel_source_digest(csrc=None):
     """SHA-256 over the sources the visit kernels are built from
-    (ems_kernels.hip and the headers) with their comments and blank space
-    removed: counter figures are valid only for the code they were measured
-    on, and a comment does not change the code."""
+    (ems_kernels.hip and the headers it includes, directly or through other
+    headers) with their comments and blank space removed: counter figures
+    are valid only for the code they were measured on, and neither a comment
+    nor a host-only file changes that code."""
     import hashlib
     import re
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2209_15445_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name == "ems_kernels.hip" or name.endswith(".hpp"):
-            text = open(os.path.join(csrc, name), encoding="utf-8").read()
-            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-            text = re.sub(r"//[^\n]*", "", text)
-            code = "\n".join(" ".join(line.split()) for line in text.splitlines() if line.strip())
-            h.update(name.encode() + b"\0" + code.encode() + b"\0")
+    used, todo = set(), ["ems_kernels.hip"]
+    while todo:
+        name = todo.pop()
+        if name in used or not os.path.exists(os.path.join(csrc, name)):
+            continue
+        used.add(name)
+        src = open(os.path.join(csrc, name), encoding="utf-8").read()
+        todo += re.findall(r'^\s*#include\s+"([^"/]+)"', src, re.M)
+    for name in sorted(used):
+        text = open(os.path.join(csrc, name), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(" ".join(line.split()) for line in text.splitlines() if line.strip())
+        h.update(name.encode() + b"\0" + code.encode() + b"\0")
     return h.hexdigest()
 
 
@@ -394,7 +393,7 @@ def layer_error(leg, n_events):
     geo, cfg, prim = leg["geo"], leg["cfg"], leg["prim"]
     k = min(n_events, len(prim))
     idx = np.arange(k)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = cpu_threads()[0]
     o = oracle.Oracle(geo, cfg)
     parts = np.array_split(idx, threads)
     res = [None] * len(parts)
@@ -420,6 +419,34 @@ def layer_error(leg, n_events):
     return {"events": int(k), "layers": int(live.sum()), "rms_rel": float(np.sqrt(np.mean(rel ** 2))),
             "max_abs_rel": float(np.abs(rel).max()), "mean_stat_rel": float(stat.mean()),
             "total_rel": float((lm.sum() - lo.sum()) / lo.sum())}
+
+
+def leg_summary(leg):
+    """Throughput and the roofline of the dominant kernel of one leg (the
+    same quantities as the headline line's, per workload and form)."""
+    r = leg["roofline"]
+    return {"value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
+            "photon_launch": leg["photon_launch"], "track_steps_per_step": leg["track_steps"],
+            "iterations": leg["iterations"],
+            "roofline": {"bound": r["bound"], "kernel": r["kernel"], "achieved": r["achieved"], "peak": r["peak"],
+                         "unit": r["unit"], "frac": r["frac"], "bytes_per_launch": r["bytes_per_launch"],
+                         "avg_launch_us": r["avg_launch_us"], "run_frac": r["run"]["frac"]},
+            "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in r["kernels"].items()}}
+
+
+def cpu_threads():
+    """Worker threads for the oracle: the CPUs this process may run on,
+    capped by the job's CPU share where the environment states one
+    (OMP_NUM_THREADS); also returns the machine's and the affinity's CPU
+    counts for the record."""
+    machine = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = machine
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(affinity, share) if share > 0 else affinity
+    return max(1, threads), machine, affinity, share or None
 
 
 def main():
@@ -451,6 +478,8 @@ def main():
     ap.add_argument("--mixed-workload", default="cal_10GeV_e-_x100k")
     ap.add_argument("--mixed-capacity", type=int, default=1 << 28)
     ap.add_argument("--extra-capacity", type=int, default=1 << 26)
+    ap.add_argument("--small-workload", default="cal_1GeV_e-_x32",
+                    help="also time this small batch in both forms ('' to skip)")
     ap.add_argument("--extra-workload",
                     default="cal_mixed_1-100GeV_bz3.8_x10k,calPbWO4_10GeV_e-_x10k,cal_10GeV_e-_x10k_msc_fluct,"
                             "towers_10GeV_e-_x10k",
@@ -544,24 +573,28 @@ def main():
         with_traffic_rate(out["mixed"]["roofline"], copy_gbs)
         if not args.no_cpu:
             out["mixed"]["per_layer_error_vs_fp64_oracle"] = layer_error(mx, args.error_events)
+    if args.small_workload:
+        # the small-batch regime (32 showers: too few tracks to fill the
+        # device for most of the run), both forms
+        out["small_batch"] = {}
+        for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
+            leg = transport_leg(E, I, args.small_workload, prec, 1 << 22, args)
+            out["small_batch"][f"{args.small_workload}/{tag}"] = leg_summary(leg)
     if args.extra_workload:
         out["other_workloads"] = {}
     for wl in filter(None, args.extra_workload.split(",")):
         for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
             leg = transport_leg(E, I, wl, prec, args.extra_capacity, args)
-            out["other_workloads"][f"{wl}/{tag}"] = {
-                "value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
-                "photon_launch": leg["photon_launch"],
-                "track_steps_per_step": leg["track_steps"],
-                "kernel_avg_launch_us": {k: v["avg_launch_us"] for k, v in leg["roofline"]["kernels"].items()}}
+            out["other_workloads"][f"{wl}/{tag}"] = leg_summary(leg)
     if not args.no_serve and not args.no_fp64_serve:
         out["serving"] = serving(E, I, args, E.FP64)
     if not args.no_serve:
         if not args.no_mixed:
             out["serving_mixed"] = serving(E, I, args, E.MIXED)
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads, machine, affinity, share = cpu_threads()
         out["cpu_baseline"] = cpu_baseline(geo, cfg, prim, min(args.cpu_events, n), threads)
+        out["cpu_baseline"].update(machine_cpus=machine, affinity_cpus=affinity, cpu_share=share)
     print(json.dumps(out), flush=True)
 
 

@@ -441,6 +441,15 @@ ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, voi
  * EMS_E_INVALID as for ems_enqueue; EMS_E_BUSY when 2^20 requests wait. */
 ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t n,
                              uint32_t event_key, uint64_t* ticket);
+/* Particles in (section 4) with their arrival time (section 5 measures the
+ * time from hand-over to hits): as ems_server_submit, but the request's
+ * latency in ems_server_info counts from arrival_ns, a time on the
+ * monotonic clock (CLOCK_MONOTONIC, in ns; Python: time.monotonic_ns()),
+ * such as the arrival a load schedule planned, so that a producer running
+ * late does not hide its delay.  0, or a time later than the call, counts
+ * from the call. */
+ems_status ems_server_submit_at(ems_server* s, const ems_primary* tracks, uint32_t n,
+                                uint32_t event_key, uint64_t arrival_ns, uint64_t* ticket);
 /* Hits out per event (section 4), thread-safe.  Waits up to timeout_us
  * (< 0: forever) for the ticket and
  * copies its deposits (edep_out[n_slabs], may be NULL) and ledger (may be
@@ -471,6 +480,31 @@ ems_status ems_server_reset_stats(ems_server* s);
 /* Stops the driver thread (pending requests are dropped) and frees the
  * server; workspace and stream remain the caller's. */
 ems_status ems_server_destroy(ems_server* s);
+
+/* Measurement of the server (section 5: the time from hand-over to hits, and
+ * throughput, under load from many host threads) with native producer
+ * threads, so that the load is not limited by the caller's runtime.
+ * Producer p (n_producers threads) takes requests [first[p], first[p+1]) of
+ * reqs in order (first: n_producers + 1 non-decreasing offsets).  A request with arrival_ns = 0 is submitted when fewer than
+ * `window` (>= 1) of the producer's requests are outstanding (closed loop;
+ * latency from the submission).  A request with arrival_ns != 0 (monotonic
+ * clock, ns) is submitted at that time, the producer sleeping until then,
+ * through ems_server_submit_at (latency from the arrival, also when the
+ * producer runs late); its completions are collected after the last
+ * submission.  Results are waited for and discarded.  *max_lag_ms (may be
+ * NULL) receives the largest delay of a submission behind its arrival,
+ * *last_submit_ns (may be NULL) the monotonic time of the last submission.
+ * Returns the first error of any producer (its remaining requests are
+ * skipped); EMS_E_INVALID for bad arguments. */
+typedef struct {
+  const ems_primary* tracks;     /* host, n_tracks records, read during the call */
+  uint32_t n_tracks;
+  uint32_t event_key;
+  uint64_t arrival_ns;           /* 0: closed loop                          */
+} ems_load_request;
+ems_status ems_server_drive(ems_server* s, const ems_load_request* reqs, const uint64_t* first,
+                            uint32_t n_producers, uint32_t window, double* max_lag_ms,
+                            uint64_t* last_submit_ns);
 
 /* Physics data (section 2.2), host only (no device needed): the tables the
  * library would upload, layout

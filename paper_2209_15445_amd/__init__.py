@@ -73,6 +73,11 @@ class RunStats(C.Structure):
                 ("graph_launches", C.c_uint64)]
 
 
+class LoadRequest(C.Structure):
+    _fields_ = [("tracks", C.c_void_p), ("n_tracks", C.c_uint32), ("event_key", C.c_uint32),
+                ("arrival_ns", C.c_uint64)]
+
+
 class ServerInfo(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("in_flight", C.c_uint64),
                 ("queued", C.c_uint64), ("admitted_bytes", C.c_uint64), ("admit_cap_bytes", C.c_uint64),
@@ -126,6 +131,7 @@ def lib():
                                          C.POINTER(u64)],
             "ems_server_create": [C.POINTER(Config), C.POINTER(Geometry), vp, u64, vp, u64, C.POINTER(vp)],
             "ems_server_submit": [vp, vp, u32, u32, C.POINTER(u64)],
+            "ems_server_submit_at": [vp, vp, u32, u32, u64, C.POINTER(u64)],
             "ems_server_wait": [vp, u64, C.c_int64, vp, vp],
             "ems_server_wait_exits": [vp, u64, C.c_int64, vp, vp, vp, u64, C.POINTER(u64)],
             "ems_server_poll": [vp, u64, C.POINTER(C.c_int)],
@@ -133,6 +139,7 @@ def lib():
             "ems_server_stats": [vp, C.POINTER(ServerInfo)],
             "ems_server_reset_stats": [vp],
             "ems_server_destroy": [vp],
+            "ems_server_drive": [vp, vp, vp, u32, u32, C.POINTER(C.c_double), C.POINTER(u64)],
             "ems_probe_atomics": [vp, u64, u64, vp, C.POINTER(C.c_double)],
         }
         for name, args in sig.items():
@@ -426,10 +433,14 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, tracks, key):
+    def submit(self, tracks, key, arrival_ns=0):
+        """Queues one request; its latency counts from arrival_ns (a
+        time.monotonic_ns() value, e.g. a scheduled arrival) if given and
+        not later than now, else from this call."""
         p = _prim(tracks)
         t = C.c_uint64()
-        _check(lib().ems_server_submit(self._h, p.ctypes.data_as(C.c_void_p), len(p), int(key), C.byref(t)))
+        _check(lib().ems_server_submit_at(self._h, p.ctypes.data_as(C.c_void_p), len(p), int(key),
+                                          int(arrival_ns), C.byref(t)))
         return t.value
 
     def wait(self, ticket, timeout_s=None, exits=False):
@@ -454,6 +465,26 @@ class Server:
                 continue
             _check(rc)
             return edep, led[0], buf[: n.value]
+
+    def drive(self, producers, window=64):
+        """Native producer threads (ems_server_drive): producers[p] is a list
+        of (tracks, event_key, arrival_ns) submitted in order by thread p
+        (arrival_ns 0: closed loop with `window` outstanding; else at that
+        time.monotonic_ns() instant, latency counted from it).  Returns
+        (largest submission lag in ms, monotonic time of the last
+        submission in ns)."""
+        keep, flat, first = [], [], [0]
+        for reqs in producers:
+            for tracks, key, arrival in reqs:
+                p = _prim(tracks)
+                keep.append(p)
+                flat.append(LoadRequest(p.ctypes.data, len(p), int(key), int(arrival)))
+            first.append(len(flat))
+        arr = (LoadRequest * len(flat))(*flat)
+        fst = (C.c_uint64 * len(first))(*first)
+        lag, last = C.c_double(), C.c_uint64()
+        _check(lib().ems_server_drive(self._h, arr, fst, len(producers), int(window), C.byref(lag), C.byref(last)))
+        return lag.value, last.value
 
     def poll(self, ticket):
         d = C.c_int()

@@ -238,6 +238,11 @@ ems_status ems_server_create(const ems_config* cfg, const ems_geometry* geo, voi
 }
 
 ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t n, uint32_t key, uint64_t* ticket) {
+  return ems_server_submit_at(s, tracks, n, key, 0, ticket);
+}
+
+ems_status ems_server_submit_at(ems_server* s, const ems_primary* tracks, uint32_t n, uint32_t key,
+                                uint64_t arrival_ns, uint64_t* ticket) {
   if (!s || !ticket || !tracks) return fail(EMS_E_INVALID, "null argument");
   if (n < 1 || n > kMaxTracks) return fail(EMS_E_INVALID, "a request holds 1..65536 tracks");
   auto r = std::make_shared<Request>();
@@ -265,7 +270,11 @@ ems_status ems_server_submit(ems_server* s, const ems_primary* tracks, uint32_t 
   // estimated peak tracks of the event in both queue buffers
   r->bytes = 2 * queue_track_bytes(&s->ctx->cfg) * (uint64_t)(n + 0.1 * etot + 1.0);
   r->key = key;
-  r->t_submit = Clock::now();
+  // latency counts from the request's arrival (a monotonic-clock time the
+  // caller gives, e.g. its scheduled arrival), or from now; never from later
+  const Clock::time_point now = Clock::now();
+  const Clock::time_point arrival{std::chrono::duration_cast<Clock::duration>(std::chrono::nanoseconds(arrival_ns))};
+  r->t_submit = arrival_ns != 0 && arrival < now ? arrival : now;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->failed) return fail(EMS_E_STATE, s->fail_msg);
   if (s->queue.size() >= kMaxQueued) return fail(EMS_E_BUSY, "request queue full");
@@ -366,6 +375,61 @@ ems_status ems_server_reset_stats(ems_server* s) {
   s->completed = s->prim_completed = s->submitted = s->chunks = 0;
   s->peak_bytes = s->admitted_bytes;
   s->t0 = Clock::now();
+  return EMS_OK;
+}
+
+ems_status ems_server_drive(ems_server* s, const ems_load_request* reqs, const uint64_t* first,
+                            uint32_t n_producers, uint32_t window, double* max_lag_ms, uint64_t* last_submit_ns) {
+  if (!s || !reqs || !first || n_producers == 0 || window == 0) return fail(EMS_E_INVALID, "null argument or zero count");
+  for (uint32_t p = 0; p < n_producers; ++p)
+    if (first[p] > first[p + 1]) return fail(EMS_E_INVALID, "request ranges must not decrease");
+  std::mutex mu;
+  ems_status first_err = EMS_OK;
+  std::string err_msg;
+  int64_t lag_ns = 0, last_ns = 0;
+  auto record = [&](ems_status st) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (first_err == EMS_OK) {
+      first_err = st;
+      err_msg = ems_last_error();
+    }
+  };
+  auto producer = [&](uint32_t p) {
+    std::deque<uint64_t> out;
+    int64_t my_lag = 0, my_last = 0;
+    for (uint64_t i = first[p]; i < first[p + 1]; ++i) {
+      const ems_load_request& r = reqs[i];
+      if (r.arrival_ns == 0) {
+        while (out.size() >= window) {
+          const ems_status st = ems_server_wait(s, out.front(), -1, nullptr, nullptr);
+          out.pop_front();
+          if (st) return record(st);
+        }
+      } else {
+        const Clock::time_point due{std::chrono::duration_cast<Clock::duration>(std::chrono::nanoseconds(r.arrival_ns))};
+        std::this_thread::sleep_until(due);
+        my_lag = std::max<int64_t>(my_lag, std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - due).count());
+      }
+      uint64_t t = 0;
+      const ems_status st = ems_server_submit_at(s, r.tracks, r.n_tracks, r.event_key, r.arrival_ns, &t);
+      if (st) return record(st);
+      my_last = std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch()).count();
+      out.push_back(t);
+    }
+    for (uint64_t t : out) {
+      const ems_status st = ems_server_wait(s, t, -1, nullptr, nullptr);
+      if (st) return record(st);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    lag_ns = std::max(lag_ns, my_lag);
+    last_ns = std::max(last_ns, my_last);
+  };
+  std::vector<std::thread> th;
+  for (uint32_t p = 0; p < n_producers; ++p) th.emplace_back(producer, p);
+  for (std::thread& t : th) t.join();
+  if (max_lag_ms) *max_lag_ms = lag_ns / 1e6;
+  if (last_submit_ns) *last_submit_ns = (uint64_t)last_ns;
+  if (first_err) return fail(first_err, err_msg);
   return EMS_OK;
 }
 

@@ -104,6 +104,52 @@ def test_flush_admission_and_errors(E):
     srv.close()
 
 
+def test_latency_counts_from_the_given_arrival(E):
+    # a request handed over with an arrival 200 ms in the past reports at
+    # least those 200 ms; an arrival in the future counts from the call
+    import time
+    print("latency from arrival", flush=True)
+    geo, cfg, srv = make_server(E, slots=8)
+    rng = np.random.Generator(np.random.Philox(21))
+    tr = I.serving_request(rng, e_median_MeV=500.0, max_tracks=10)
+    srv.reset_stats()
+    srv.wait(srv.submit(tr, 1, arrival_ns=time.monotonic_ns() - 200_000_000), timeout_s=60)
+    st = srv.stats()
+    assert st["completed"] == 1 and st["max_ms"] >= 200.0, st
+    srv.reset_stats()
+    srv.wait(srv.submit(tr, 2, arrival_ns=time.monotonic_ns() + 10_000_000_000), timeout_s=60)
+    st = srv.stats()
+    assert st["completed"] == 1 and 0.0 <= st["max_ms"] < 5000.0, st
+    srv.close()
+
+
+def test_native_producers_drive_the_server(E):
+    # ems_server_drive: closed loop (window 3) and scheduled arrivals from 6
+    # native threads; every request completes, lateness is reported and the
+    # latency of scheduled requests counts from their arrival
+    import time
+    print("native producers", flush=True)
+    geo, cfg, srv = make_server(E, slots=16)
+    rng = np.random.Generator(np.random.Philox(31))
+    reqs = [[(I.serving_request(rng, e_median_MeV=300.0, max_tracks=8), p * 100 + i, 0) for i in range(10)]
+            for p in range(6)]
+    srv.reset_stats()
+    lag, last = srv.drive(reqs, window=3)
+    st = srv.stats()
+    assert st["completed"] == 60 and st["in_flight"] == 0 and lag == 0.0 and last > 0
+    t0 = time.monotonic_ns() + 20_000_000
+    timed = [[(tr, 5000 + k, t0 + 2_000_000 * i) for i, (tr, k, _) in enumerate(r)] for r in reqs]
+    srv.reset_stats()
+    lag, last = srv.drive(timed, window=1)
+    st = srv.stats()
+    assert st["completed"] == 60 and last >= t0 + 18_000_000 and lag >= 0.0
+    # a request scheduled in the past reports at least its age
+    srv.reset_stats()
+    srv.drive([[(reqs[0][0][0], 9999, time.monotonic_ns() - 100_000_000)]], window=1)
+    assert srv.stats()["max_ms"] >= 100.0
+    srv.close()
+
+
 def test_server_returns_outgoing_tracks(E, oracle_mod):
     """A request's outgoing tracks come back with its deposits and equal the
     oracle's for the same tracks and event key."""
