@@ -85,10 +85,16 @@ enum {
                                   device time in ems_run_stats.kernel_ms;
                                   the chunk's kernels are then launched
                                   directly, not replayed from a graph      */
-  EMS_F_NO_GRAPH = 1u << 5      /* launch each chunk's kernels directly
+  EMS_F_NO_GRAPH = 1u << 5,     /* launch each chunk's kernels directly
                                   instead of replaying a captured hipGraph
                                   of steps_per_launch iterations (always
                                   direct on the null stream)               */
+  EMS_F_FULL_KERNELS = 1u << 6  /* launch the kernels built with every
+                                  optional part (field, multiple scattering,
+                                  fluctuations, compound targets, per-step
+                                  records) instead of the smallest variant
+                                  that covers the configuration; the
+                                  results are the same (tests)             */
 };
 
 /* A material: a single element (n_elements = 0: Z, A_g_mol), or a compound

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libems.so")
 ABI_VERSION = 7
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
-F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH = 1, 2, 4, 8, 16, 32
+F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH, F_FULL_KERNELS = 1, 2, 4, 8, 16, 32, 64
 
 
 class EmsError(RuntimeError):

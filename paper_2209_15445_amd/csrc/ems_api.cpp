@@ -610,6 +610,20 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
   a.env = env_for(cfg, geo, c->ts);
   a.geo = geo->n_boxes ? 1u : 0u;
   a.vol_bits = vol_bits(geo);
+  // the smallest kernel variants that cover the configuration's optional
+  // parts (the others are compiled out of them)
+  bool compound = false;
+  for (const MatRT& m : c->ts.rt) compound = compound || m.n_el > 1;
+  const bool record = (cfg->flags & (EMS_F_STEPLOG | EMS_F_FULL_LEDGER | EMS_F_EVENT_LIVE)) || cfg->exit_capacity;
+  const uint32_t need_l = (geo->n_boxes == 0 && cfg->bz_tesla != 0.0 ? kFField : 0) |
+                          (cfg->process_mask & EMS_P_MSC ? kFMsc : 0) | (cfg->process_mask & EMS_P_FLUCT ? kFFluct : 0) |
+                          (compound ? kFCompound : 0) | (record ? kFRecord : 0);
+  const uint32_t need_g = (compound ? kFCompound : 0) | (record ? kFRecord : 0);
+  a.feat_l = need_l == 0 ? 0u
+             : (geo->n_boxes == 0 && (need_l & ~(uint32_t)(kFField | kFRecord)) == 0) ? (uint32_t)(kFField | kFRecord)
+                                                                                      : (uint32_t)kFAll;
+  a.feat_g = need_g == 0 ? 0u : (uint32_t)kFAll;
+  if (cfg->flags & EMS_F_FULL_KERNELS) a.feat_g = a.feat_l = kFAll;
   if (geo->n_boxes) {
     // device view of the hierarchy (same layout as the host one)
     a.env.nav = c->nav;

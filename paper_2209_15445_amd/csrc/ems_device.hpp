@@ -147,6 +147,7 @@ struct KArgs {
   ExitRec* exits;             // outgoing tracks (exit_cap records)
   uint64_t exit_cap;
   uint32_t geo;               // geometry kind: 0 slab stack, 1 boxes
+  uint32_t feat_g, feat_l;    // optional parts (kF* bits) of the photon and e-/e+ kernels launched
   uint32_t vol_bits;          // low bits of the packed word that hold the volume
   StepEnv<double> env;  // scalars; its pointers are set per block
 };

@@ -227,7 +227,9 @@ struct DevSink {
     acc_dep = 0.0;
   }
 
-  template <class R>
+  // F: the kernel's optional parts; the per-step records (exits, full
+  // ledger, step log) exist only with kFRecord
+  template <int F, class R>
   __device__ void apply(int sp, const Trk<R>& t, const StepOut<R>& o, double e_before) {
     if (o.dep != 0.0) {
       const size_t cell = (size_t)t.ev * n_slabs + o.slab;
@@ -239,6 +241,10 @@ struct DevSink {
     }
     LedgerDev& L = ledger[t.ev];
     if (o.escaped != 0.0) atomicAdd(&L.escaped[0] + sp, o.escaped);
+    if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
+    if (o.pair) atomicAdd(&L.n_pair, (uint32_t)o.pair);
+    if (o.annih) atomicAdd(&L.n_annih, (uint32_t)o.annih);
+    if constexpr ((F & kFRecord) == 0) return;
     if (exit_cap) {
       // the track left the stack: its state at the exit point
       const bool out = o.escaped != 0.0;
@@ -256,9 +262,6 @@ struct DevSink {
         x.dir[2] = t.uz;
       }
     }
-    if (o.killed != 0.0) atomicAdd(&L.killed, o.killed);
-    if (o.pair) atomicAdd(&L.n_pair, (uint32_t)o.pair);
-    if (o.annih) atomicAdd(&L.n_annih, (uint32_t)o.annih);
     if (full) {
       atomicAdd(&L.n_steps, 1ull);
       if (o.clen != 0.0) atomicAdd(&L.charged_len, o.clen);
@@ -369,7 +372,7 @@ constexpr int visit_waves() {
   return sizeof(R) == 8 ? (PHOTONS ? EMS_WAVES_F64_PHOTON : EMS_WAVES_F64_LEPTON)
                         : (PHOTONS ? EMS_WAVES_F32_PHOTON : EMS_WAVES_F32_LEPTON);
 }
-template <bool PHOTONS, class R, int GEO>
+template <bool PHOTONS, class R, int GEO, int F>
 __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_visit(KArgs a) {
   extern __shared__ double lds_words[];
   char* lds = reinterpret_cast<char*>(lds_words);
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
                  (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0, 0.0,
                  a.exits, a.exit_cap};
     uint32_t* cursor = &ctl->cursor[PHOTONS ? 0 : 1];
-    const bool track_live = (a.flags & kFlagEventLive) != 0;
+    const bool track_live = (F & kFRecord) && (a.flags & kFlagEventLive) != 0;
 
     bool has = false;   // lane holds a track (inside a visit or waiting to commit)
     bool fin = false;   // its visit ended; outputs wait for the batch commit
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
         }
         // (2) the interactions selected by the lanes' last steps, sampled
         // together (one pass through each sampler the wave needs)
-        if (done && o.pending) interact<KIND>(env, t, o);
+        if (done && o.pending) interact<KIND, F>(env, t, o);
         // (3) the prefetched records have arrived; waiting here, before any
         // store of this batch is issued, keeps later uses of their fields
         // from waiting on those stores (vector memory completes in order)
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
             if (mine) hs = slot_of(th, hx);
           }
           if (apply_now) {
-            sink.apply(sp, t, o, before.E);
+            sink.apply<F>(sp, t, o, before.E);
             if (sp == 2) ++steps_p;
             else ++steps_e;
             made0 += d[0];
@@ -610,10 +613,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
       if (has && !fin) {
         before = t;
         const double e0 = t.E;
-        fin = visit_step<KIND, R, GEO>(env, sp, vs, t, o, max_visit);
+        fin = visit_step<KIND, R, GEO, F>(env, sp, vs, t, o, max_visit);
         held = o.pending;
         if (!held) {
-          sink.apply(sp, t, o, e0);
+          sink.apply<F>(sp, t, o, e0);
           if (sp == 2) ++steps_p;
           else ++steps_e;
         }
@@ -818,15 +821,46 @@ __global__ void k_census(KArgs a) {
   }
 }
 
+// Kernel variants: the optional parts each kernel is built with.  The
+// e-/e+ kernel of a slab stack comes without any, with the field and the
+// records (mixed-species runs in a field, the offload server) or with all;
+// the photon kernels and the box-geometry e-/e+ kernels without any or with
+// all.  A context launches the smallest variant that covers its
+// configuration (KArgs::feat_g, feat_l).
+template <bool PHOTONS, class R, int GEO>
+const void* visit_fn(uint32_t feat) {
+  if (feat == 0) return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, 0>);
+  if constexpr (!PHOTONS && GEO == 0) {
+    if (feat == (kFField | kFRecord))
+      return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFField | kFRecord>);
+  }
+  return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFAll>);
+}
+template <bool PHOTONS, class R, int GEO>
+void launch_visit_v(const KArgs& a, uint32_t blocks, hipStream_t s) {
+  const uint32_t lds = PHOTONS ? a.lds_g : a.lds_l;
+  const uint32_t feat = PHOTONS ? a.feat_g : a.feat_l;
+  if (feat == 0) {
+    hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, 0>), dim3(blocks), dim3(kBlock), lds, s, a);
+    return;
+  }
+  if constexpr (!PHOTONS && GEO == 0) {
+    if (feat == (kFField | kFRecord)) {
+      hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, kFField | kFRecord>), dim3(blocks), dim3(kBlock), lds, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, kFAll>), dim3(blocks), dim3(kBlock), lds, s, a);
+}
 // one iteration is the photon launch followed by the e-/e+ launch
 template <int GEO>
 void launch_visit_g(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
   if (photons) {
-    if (a.precision) hipLaunchKernelGGL((k_visit<true, float, GEO>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
-    else hipLaunchKernelGGL((k_visit<true, double, GEO>), dim3(blocks), dim3(kBlock), a.lds_g, s, a);
+    if (a.precision) launch_visit_v<true, float, GEO>(a, blocks, s);
+    else launch_visit_v<true, double, GEO>(a, blocks, s);
   } else {
-    if (a.precision) hipLaunchKernelGGL((k_visit<false, float, GEO>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
-    else hipLaunchKernelGGL((k_visit<false, double, GEO>), dim3(blocks), dim3(kBlock), a.lds_l, s, a);
+    if (a.precision) launch_visit_v<false, float, GEO>(a, blocks, s);
+    else launch_visit_v<false, double, GEO>(a, blocks, s);
   }
 }
 hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
@@ -871,18 +905,19 @@ hipError_t launch_census(const KArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_census, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
-// blocks of each visit kernel that fit on one CU (registers and LDS)
+// blocks of each visit kernel that fit on one CU (registers and LDS), for
+// the variants the context launches
 template <class R, int GEO>
 hipError_t visit_occupancy_r(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<true, R, GEO>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
+  const void* fg = visit_fn<true, R, GEO>(a.feat_g);
+  const void* fl = visit_fn<false, R, GEO>(a.feat_l);
+  hipError_t e = hipFuncSetAttribute(fg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visit<false, R, GEO>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
+  e = hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, k_visit<true, R, GEO>, kBlock, a.lds_g);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, fg, kBlock, a.lds_g);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, k_visit<false, R, GEO>, kBlock, a.lds_l);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, fl, kBlock, a.lds_l);
 }
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
   if (a.geo == 1)

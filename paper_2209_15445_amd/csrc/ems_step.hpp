@@ -22,6 +22,14 @@ namespace ems {
 
 constexpr double kInf = __builtin_huge_val();
 
+// Optional parts of the step, compiled into a kernel only when its
+// configuration uses them (a kernel without one is launched only for
+// configurations that leave it off; the host path has all of them): the
+// helix in a field, multiple scattering, loss fluctuations, a compound
+// target element, and the per-step records (step log, full ledger, exits,
+// per-event live counters).
+enum : int { kFField = 1, kFMsc = 2, kFFluct = 4, kFCompound = 8, kFRecord = 16, kFAll = 31 };
+
 // Tables are held in two blocks so each kernel stages only its own: the
 // photon block [mat][3][nodes] (tables 0..2) and the lepton block
 // [mat][10][nodes] (tables 3..12).
@@ -480,7 +488,7 @@ EMS_HD R gamma_loss(R mean, R var, Draws& r) {
   return x * theta;
 }
 
-template <class R, int GEO = 0>
+template <class R, int GEO = 0, int F = kFAll>
 EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
@@ -497,7 +505,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     }
     return;
   }
-  const bool field = GEO == 0 && e.bz != 0.0;  // box geometries take no field
+  const bool field = (F & kFField) && GEO == 0 && e.bz != 0.0;  // box geometries take no field
   Face fc{0, 0.0};
   double sz;
   if constexpr (GEO == 1) sz = box_dist(e, t, fc);
@@ -517,13 +525,24 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     zlim = sz <= dw;
     sg = zlim ? sz : dw;
   } else {
-    const double sw = GEO == 1 ? kInf : dist_to_walls(e, t);
+    // The distance along the track to a transverse wall is at least the
+    // perpendicular distance to the nearest wall (|u_x|, |u_y| <= 1 up to the
+    // rounding of a unit vector, covered by the 2^-20 margin), so the wall
+    // can only limit the step when that perpendicular distance does not
+    // exceed the plane distance; otherwise sz <= sw holds and the two
+    // divisions are skipped, with the same result.
+    double sw = kInf;
+    if constexpr (GEO != 1) {
+      const double ax = fabs(t.x), ay = fabs(t.y);
+      const double dperp = e.half_xy - (ax > ay ? ax : ay);
+      if (!(dperp * (1.0 - 0x1p-20) > sz)) sw = dist_to_walls(e, t);
+    }
     zlim = sz <= sw;
     sg = zlim ? sz : sw;
   }
   const uint32_t m = e.slab_mat[t.slab];
   const bool cont = (e.mask & kPCont) != 0;
-  const bool fluct = cont && (e.mask & kPFluct) != 0;
+  const bool fluct = (F & kFFluct) && cont && (e.mask & kPFluct) != 0;
   const R lnT = xlog((R)T);
   const Bin<R> b = bin_of(e, lnT);
   const R* Rt = e.T(m, positron ? tRep : tRem);
@@ -609,7 +628,7 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     return;
   }
   const bool up = t.uz > R(0);  // the plane reached, fixed before any deflection
-  if ((e.mask & kPMsc) && s > 0.0) msc_deflect(highland_width<R>(T, s, e.mat[m].x0), r, t);
+  if ((F & kFMsc) && (e.mask & kPMsc) && s > 0.0) msc_deflect(highland_width<R>(T, s, e.mat[m].x0), r, t);
   if (lim == kLimZ) {
     if constexpr (GEO == 1) box_land(e, t, o, fc);
     else land_on_plane(e, t, o, up);
@@ -645,11 +664,11 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
 // energy E in material m.  In a compound the next draw u picks the first
 // element whose running sum of interpolated partial totals exceeds u times
 // their sum; a single element takes no draw.
-template <class R>
+template <int F, class R>
 EMS_HD MatRT target_element(const StepEnv<R>& e, uint32_t m, int w, double E, Draws& r) {
   MatRT me = e.mat[m];
   const uint32_t n = me.n_el;
-  if (n <= 1) return me;
+  if (!(F & kFCompound) || n <= 1) return me;
   const R u = r.u<R>();
   const Bin<R> b = bin_of(e, xlog((R)E));
   R s[kMaxElements];
@@ -682,7 +701,7 @@ EMS_HD MatRT target_element(const StepEnv<R>& e, uint32_t m, int w, double E, Dr
 // watchdog.  Running it right after the step or later in a batch with other
 // tracks gives the same result.  KIND: 0 = photon processes only, 1 = e-/e+
 // processes only, 2 = any.
-template <int KIND, class R>
+template <int KIND, int F = kFAll, class R>
 EMS_HD void interact(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
@@ -696,14 +715,14 @@ EMS_HD void interact(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o) {
   } else if (KIND != 1 && p == kXPhot) {
     photo(E, u, oc);
   } else if (KIND != 1 && p == kXConv) {
-    pair(target_element(e, m, 0, E, r), E, u, r, oc);
+    pair(target_element<F>(e, m, 0, E, r), E, u, r, oc);
     o.pair += 1;
   } else if (KIND != 0 && p == kXMoller) {
     moller(E, e.tcut, u, r, oc);
   } else if (KIND != 0 && p == kXBhabha) {
     bhabha(E, e.tcut, u, r, oc);
   } else if (KIND != 0 && p == kXBrem) {
-    brem(target_element(e, m, 1, E, r), E, e.kcut, u, r, oc);
+    brem(target_element<F>(e, m, 1, E, r), E, e.kcut, u, r, oc);
   } else if (KIND != 0 && p == kXAnnih) {
     annihilate(E, u, r, oc);
     o.annih += 1;
@@ -864,14 +883,14 @@ EMS_HD void visit_begin(const StepEnv<R>& e, int sp, const Trk<R>& t, VisitState
 // run of visits is step for step the one-step-at-a-time loop.  The step's
 // interaction is left pending (o.pending) for the caller to run with
 // interact(), so that a wave samples its interactions together.
-template <int KIND, class R, int GEO = 0>
+template <int KIND, class R, int GEO = 0, int F = kFAll>
 EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps) {
   bool end;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
     end = photon_substep<R, GEO>(e, vs.pc, t, o);
   } else {
     clear_out(t, o);
-    lepton_step<R, GEO>(e, sp == kPositron, t, o);
+    lepton_step<R, GEO, F>(e, sp == kPositron, t, o);
     if (!o.pending) watchdog(e, t, o);
     end = t.slab < 0 || o.pending;
   }

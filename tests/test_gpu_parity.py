@@ -499,6 +499,32 @@ def test_graph_replays_match_direct_launches(E):
     t.close()
 
 
+@pytest.mark.parametrize("case", ["fp64", "mixed", "fp64_bz3.8", "mixed_bz3.8", "fp64_towers"])
+def test_smallest_kernel_variant_matches_the_full_one(E, case):
+    """The kernels are built in variants without the optional parts a
+    configuration leaves off (field, multiple scattering, fluctuations,
+    compound targets, per-step records); the variant a context launches gives
+    the results of the kernels with every part compiled in."""
+    print(f"kernel variants {case}", flush=True)
+    if case.endswith("towers"):
+        geo, cfg, prim = I.workload("towers_1GeV_e-_x32")
+        prim = prim[:8]
+    else:
+        geo, cfg, prim = I.workload("cal_1GeV_e-_x32")
+        if case.endswith("bz3.8"):
+            cfg = I.RunConfig(seed=1, bz_tesla=3.8)
+    prec = E.MIXED if case.startswith("mixed") else E.FP64
+    n = len(prim)
+    small = run_gpu(E, geo, cfg, prim, n, precision=prec)
+    full = run_gpu(E, geo, cfg, prim, n, precision=prec, flags=E.F_FULL_KERNELS)
+    assert small["stats"]["steps"] == full["stats"]["steps"]
+    assert small["stats"]["created"] == full["stats"]["created"]
+    assert np.allclose(small["edep"], full["edep"], rtol=1e-12, atol=1e-12)
+    for f in ("escaped", "killed", "n_pair", "n_annih"):
+        assert np.allclose(small["ledger"][f], full["ledger"][f], rtol=1e-12, atol=1e-12), f
+    assert ledger_residual(small["edep"], small["ledger"], prim).max() < (1e-9 if prec == E.FP64 else 1e-5)
+
+
 @pytest.mark.parametrize("bz", [0.0, 3.8])
 def test_exits_match_oracle(E, oracle_mod, bz):
     """Outgoing tracks (the hybrid contract's particles out): the same
