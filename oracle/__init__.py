@@ -151,6 +151,9 @@ def lib():
         L.or_geo_distance.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.or_geo_distance.restype = C.c_double
+        L.or_geo_helix_distance.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                            C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.or_geo_helix_distance.restype = C.c_double
         _lib = L
     return _lib
 
@@ -285,6 +288,15 @@ class Oracle:
         ax = C.c_int()
         f = C.c_double()
         d = lib().or_geo_distance(self._h, v, (C.c_double * 3)(*p), (C.c_double * 3)(*u), C.byref(ax), C.byref(f))
+        return d, ax.value, f.value
+
+    def geo_helix_distance(self, v, p, u, kappa, smax=float("inf")):
+        """(path length, axis, face coordinate) to the next boundary along the
+        helix of signed curvature kappa (1/mm) about z, searched up to smax"""
+        ax = C.c_int()
+        f = C.c_double()
+        d = lib().or_geo_helix_distance(self._h, v, (C.c_double * 3)(*p), (C.c_double * 3)(*u), float(kappa),
+                                        float(smax), C.byref(ax), C.byref(f))
         return d, ax.value, f.value
 
     # -- transport ------------------------------------------------------

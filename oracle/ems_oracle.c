@@ -1102,6 +1102,179 @@ static void move_helix(or_track* t, double kappa, double s) {
   t->dir[0] = ux * cp + uy * sp;
   t->dir[1] = -ux * sp + uy * cp;
 }
+/* ---- charged tracks in a box geometry with a field ----
+ * Reading (section 2.3 asks for propagation in the field with the boundary
+ * found along the curved path): the step follows the exact helix of
+ * move_helix, and a box face is reached where the helix meets its plane.
+ * With psi = |kappa| s the angle turned, the transverse motion is the
+ * circle x = xc + r sin(psi - beta), y = yc + sg r cos(psi - beta) (sg the
+ * sign of kappa, r = u_perp / |kappa|), so a plane x = X or y = Y is met at
+ * angles given by asin or acos; z = z0 + uz s is linear. */
+typedef struct {
+  double x0, y0, z0, uz, ak, r, xc, yc, beta;
+  int sg;
+} or_helix;
+
+static or_helix helix_of(const double p[3], const double u[3], double kappa) {
+  or_helix h;
+  h.x0 = p[0];
+  h.y0 = p[1];
+  h.z0 = p[2];
+  h.uz = u[2];
+  h.ak = fabs(kappa);
+  h.sg = kappa > 0.0 ? 1 : -1;
+  double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+  h.r = up / h.ak;
+  h.xc = p[0] + u[1] / kappa;
+  h.yc = p[1] - u[0] / kappa;
+  /* x - xc = (u_x sin phi - u_y cos phi) / kappa with phi = kappa s */
+  h.beta = h.sg * atan2(u[1], u[0]);
+  return h;
+}
+
+/* the point after path s (the same formulas as move_helix) */
+static void helix_at(const or_helix* h, const double u[3], double kappa, double s, double out[3]) {
+  double phi = kappa * s;
+  double sp = sin(phi), hh = sin(0.5 * phi), omc = 2.0 * hh * hh;
+  out[0] = h->x0 + (u[0] * sp + u[1] * omc) / kappa;
+  out[1] = h->y0 + (u[1] * sp - u[0] * omc) / kappa;
+  out[2] = h->z0 + u[2] * s;
+}
+
+/* angle psi in [0, 2 pi) from the start to the angle theta of the circle
+ * (theta = psi - beta); within 1e-9 of a full turn counts as 0 (the start
+ * itself, up to rounding) */
+static double helix_turn_to(const or_helix* h, double theta) {
+  double d = fmod(theta + h->beta, 2.0 * PI);
+  if (d < 0.0) d += 2.0 * PI;
+  if (d > 2.0 * PI - 1e-9) d = 0.0;
+  return d;
+}
+
+/* first angle psi >= 0 at which the helix crosses the plane (axis 0: x = v,
+ * axis 1: y = v) moving up (+1) or down (-1) that axis; -1 if never */
+static double helix_plane_psi(const or_helix* h, int axis, double v, int dirn) {
+  if (!(h->r > 0.0)) return -1.0;
+  double theta;
+  if (axis == 0) {
+    double w = (v - h->xc) / h->r;
+    if (w < -1.0 || w > 1.0) return -1.0;
+    double a = asin(w);             /* the branch with cos(theta) >= 0: x increasing */
+    theta = dirn > 0 ? a : PI - a;
+  } else {
+    double w = h->sg * (v - h->yc) / h->r;
+    if (w < -1.0 || w > 1.0) return -1.0;
+    double a = acos(w);             /* y increasing where sg sin(theta) < 0 */
+    theta = dirn > 0 ? -h->sg * a : h->sg * a;
+  }
+  return helix_turn_to(h, theta);
+}
+
+/* Leaving the box [lo, hi] from inside along the helix: the path length to
+ * the first face crossed outward (the first axis on ties, as ray_exit),
+ * infinity if the helix never leaves it. */
+static double helix_exit(const or_helix* h, const double* lo, const double* hi, int* ax, double* face) {
+  double s = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    double d = INFINITY, f = 0.0;
+    if (k < 2) {
+      double a = helix_plane_psi(h, k, hi[k], +1);
+      double b = helix_plane_psi(h, k, lo[k], -1);
+      if (a >= 0.0 && (b < 0.0 || a <= b)) {
+        d = a / h->ak;
+        f = hi[k];
+      } else if (b >= 0.0) {
+        d = b / h->ak;
+        f = lo[k];
+      }
+    } else if (h->uz > 0.0) {
+      d = (hi[2] - h->z0) / h->uz;
+      f = hi[2];
+    } else if (h->uz < 0.0) {
+      d = (lo[2] - h->z0) / h->uz;
+      f = lo[2];
+    }
+    if (d < 0.0) d = 0.0;
+    if (d < s) {
+      s = d;
+      *ax = k;
+      *face = f;
+    }
+  }
+  return s;
+}
+
+/* Entering the box [lo, hi] from outside: the smallest path length s in
+ * [0, smax] at which the helix crosses one of its face planes inward at a
+ * point within the other two bounds (x and y planes are met once per turn
+ * in each direction); infinity if none. */
+static double helix_entry(const or_helix* h, const double u[3], double kappa, const double* lo,
+                          const double* hi, double smax, int* ax, double* face) {
+  double best = INFINITY;
+  for (int k = 0; k < 3; ++k)
+    for (int side = 0; side < 2; ++side) {
+      double v = side ? hi[k] : lo[k];
+      int dirn = side ? -1 : +1; /* entering through lo moving up, through hi moving down */
+      double s0, period;
+      if (k < 2) {
+        double psi = helix_plane_psi(h, k, v, dirn);
+        if (psi < 0.0) continue;
+        s0 = psi / h->ak;
+        period = 2.0 * PI / h->ak;
+      } else {
+        if (h->uz == 0.0 || (h->uz > 0.0) != (dirn > 0)) continue;
+        s0 = (v - h->z0) / h->uz;
+        if (s0 < 0.0) continue;
+        period = INFINITY;
+      }
+      for (double sc = s0; sc <= smax && sc < best; sc += period) {
+        double q[3];
+        helix_at(h, u, kappa, sc, q);
+        q[k] = v;
+        int inside = 1;
+        for (int j = 0; j < 3; ++j)
+          if (j != k && !(q[j] >= lo[j] && q[j] <= hi[j])) inside = 0;
+        if (inside) {
+          best = sc;
+          *ax = k;
+          *face = v;
+          break;
+        }
+        if (!(period < INFINITY)) break;
+      }
+    }
+  return best;
+}
+
+/* path length along the helix to the next boundary from volume v, searched
+ * up to smax (infinity: none within smax): a box's own faces, or from the
+ * world the nearer of its exit and the first box entered (boxes win ties,
+ * the last such box in index order) */
+static double helix_distance(const or_ctx* c, int v, const double p[3], const double u[3], double kappa,
+                             double smax, int* ax, double* face) {
+  or_helix h = helix_of(p, u, kappa);
+  double s;
+  if ((uint32_t)v < c->nbox) {
+    s = helix_exit(&h, c->blo + 3 * v, c->bhi + 3 * v, ax, face);
+  } else {
+    s = helix_exit(&h, c->wlo, c->whi, ax, face);
+    /* a circle in a plane (u_z = 0) meets what it meets within one turn */
+    double lim = smax < s ? smax : s;
+    if (h.uz == 0.0 && 2.0 * PI / h.ak < lim) lim = 2.0 * PI / h.ak;
+    for (uint32_t b = 0; b < c->nbox; ++b) {
+      int a = 0;
+      double f = 0.0;
+      double d = helix_entry(&h, u, kappa, c->blo + 3 * b, c->bhi + 3 * b, lim, &a, &f);
+      if (d <= s) {
+        s = d;
+        *ax = a;
+        *face = f;
+      }
+    }
+  }
+  return s <= smax ? s : INFINITY;
+}
+
 /* a track leaving the stack: its state at the exit point, in the primary
  * record layout (so that it can be handed back as input) */
 static void record_exit(or_event* ev, const or_track* t) {
@@ -1378,10 +1551,31 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
   int field = (c->s.bz_tesla != 0.0);
   int ax = 0;
   double face = 0.0;
-  double sz = c->nbox ? box_distance(c, t->slab, t->pos, t->dir, &ax, &face) : dist_z(c, t);
+  uint32_t m = vol_material(c, t->slab);
+  const double* Rtab = tab_ptr(c, m, positron ? T_R_EP : T_R_EM);
+  double S = 0.0, R = INFINITY, scont = INFINITY;
+  if (cont) {
+    S = plain_lookup(c, m, positron ? T_S_EP : T_S_EM, T);
+    R = plain_lookup(c, m, positron ? T_R_EP : T_R_EM, T);
+    double rho = c->s.final_range_mm, al = c->s.dr_over_range;
+    scont = (R <= rho) ? R : al * R + rho * (1.0 - al) * (2.0 - rho / R);
+  }
   double sgeom, sw = INFINITY, dw = INFINITY;
   int zlimited;
-  if (field) {
+  if (c->nbox && field) {
+    /* along the helix, searched up to the continuous-loss limit (beyond it
+     * the boundary cannot limit the step) */
+    double kappa = (positron ? 1.0 : -1.0) * KB * c->s.bz_tesla / sqrt(T * (T + 2.0 * ME));
+    sgeom = helix_distance(c, t->slab, t->pos, t->dir, kappa, scont, &ax, &face);
+    zlimited = 1;
+    if (!(sgeom < INFINITY) && !(scont < INFINITY)) {
+      /* nothing limits the step (no continuous loss, a circle that meets no
+       * boundary): one turn, without a crossing */
+      sgeom = 2.0 * PI / fabs(kappa);
+      zlimited = 0;
+    }
+  } else if (field) {
+    double sz = dist_z(c, t);
     double ax = fabs(t->pos[0]), ay = fabs(t->pos[1]);
     dw = c->s.half_xy_mm - (ax > ay ? ax : ay);
     if (dw < OR_SAFETY_EPS) {
@@ -1392,19 +1586,10 @@ static void lepton_step(or_event* ev, or_track* t, or_step_rec* rec) {
     sgeom = sz <= dw ? sz : dw;
     zlimited = (sz <= dw);
   } else {
+    double sz = c->nbox ? box_distance(c, t->slab, t->pos, t->dir, &ax, &face) : dist_z(c, t);
     if (!c->nbox) sw = dist_wall(c, t);
     sgeom = sz <= sw ? sz : sw;
     zlimited = (sz <= sw);
-  }
-
-  uint32_t m = vol_material(c, t->slab);
-  const double* Rtab = tab_ptr(c, m, positron ? T_R_EP : T_R_EM);
-  double S = 0.0, R = INFINITY, scont = INFINITY;
-  if (cont) {
-    S = plain_lookup(c, m, positron ? T_S_EP : T_S_EM, T);
-    R = plain_lookup(c, m, positron ? T_R_EP : T_R_EM, T);
-    double rho = c->s.final_range_mm, al = c->s.dr_over_range;
-    scont = (R <= rho) ? R : al * R + rho * (1.0 - al) * (2.0 - rho / R);
   }
   double smax = scont <= sgeom ? scont : sgeom;
 
@@ -1622,7 +1807,7 @@ int or_create(const or_setup* s, or_ctx** out) {
 
 int or_create_boxes(const or_setup* s, const or_boxes* b, or_ctx** out) {
   if (!s || !b || !out || b->n_boxes == 0 || !b->lo || !b->hi || !b->material) return -1;
-  if (s->bz_tesla != 0.0 || b->world_material >= s->n_materials) return -1;
+  if (b->world_material >= s->n_materials) return -1;
   for (int k = 0; k < 3; ++k)
     if (!(b->world_lo[k] < b->world_hi[k])) return -1;
   for (uint32_t i = 0; i < b->n_boxes; ++i) {
@@ -1674,6 +1859,13 @@ double or_geo_distance(const or_ctx* c, int v, const double p[3], const double u
   *axis = -1;
   *face = NAN;
   return box_distance(c, v, p, u, axis, face);
+}
+double or_geo_helix_distance(const or_ctx* c, int v, const double p[3], const double u[3], double kappa,
+                             double smax, int* axis, double* face) {
+  if (!c || !c->nbox || v < 0 || (uint32_t)v > c->nbox || !axis || !face || kappa == 0.0) return NAN;
+  *axis = -1;
+  *face = NAN;
+  return helix_distance(c, v, p, u, kappa, smax, axis, face);
 }
 void or_destroy(or_ctx* c) {
   if (!c) return;

@@ -170,6 +170,12 @@ int or_geo_locate(const or_ctx* c, const double p[3], const double u[3]);
  * crossed face (axis, coordinate) */
 double or_geo_distance(const or_ctx* c, int v, const double p[3], const double u[3],
                        int* axis, double* face);
+/* The same along the helix of curvature kappa (1/mm, signed as in the
+ * transport: q 0.299792458 Bz / p) about z: path length to the next
+ * boundary searched up to smax (infinity when none is met within it), with
+ * the face reached. */
+double or_geo_helix_distance(const or_ctx* c, int v, const double p[3], const double u[3], double kappa,
+                             double smax, int* axis, double* face);
 void or_destroy(or_ctx* c);
 
 /*

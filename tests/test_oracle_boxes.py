@@ -160,8 +160,6 @@ def test_box_geometry_validation(oracle_mod):
     for g in bad:
         with pytest.raises(ValueError):
             oracle_mod.Oracle(g, cfg)
-    with pytest.raises(ValueError):
-        oracle_mod.Oracle(base, I.RunConfig(bz_tesla=1.0))
     o = oracle_mod.Oracle(base, cfg)
     p = I.beam(2, I.ELECTRON, 10.0)
     p["pos"][1] = (1e4, 0.0, 0.0)
