@@ -129,8 +129,12 @@ typedef struct {
  * moving with u < 0).  Navigation walks a bounding-volume hierarchy built at
  * ems_create, the acceleration structure of the paper's geometry work
  * (section 2.1), whose results equal a walk over all boxes.  Deposits are
- * scored per volume: n_boxes + 1 columns, the world last.  No magnetic
- * field (bz_tesla must be 0).  The volume index shares a 32-bit word with the
+ * scored per volume: n_boxes + 1 columns, the world last.  In a field
+ * (bz_tesla != 0) charged tracks follow the exact helix about z and reach a
+ * box face where the helix meets its plane (section 2.3: the boundary along
+ * the curved path), searched up to the continuous-loss step limit; from the
+ * world volume the hierarchy supplies the boxes the arc's bounding box
+ * overlaps.  The volume index shares a 32-bit word with the
  * track's step count: max_steps_per_track must stay below 2^(32 - b), b the
  * bits of n_boxes + 2 (at least 12). */
 typedef struct {

@@ -76,8 +76,8 @@ uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 
 // box geometry: finite boxes inside the world, known materials, no two
-// boxes sharing interior points (sweep over x), no field, step counts that
-// fit beside the volume index
+// boxes sharing interior points (sweep over x), step counts that fit beside
+// the volume index
 ems_status check_boxes(const ems_config* c, const ems_geometry* g) {
   if (g->n_slabs != 0) return fail(EMS_E_INVALID, "a box geometry has no slabs (n_slabs = 0)");
   if (g->n_boxes > kMaxBoxes || !g->box_lo || !g->box_hi || !g->box_material)
@@ -105,7 +105,6 @@ ems_status check_boxes(const ems_config* c, const ems_geometry* g) {
         return fail(EMS_E_INVALID, "boxes " + std::to_string(i) + " and " + std::to_string(j) + " overlap");
     }
   }
-  if (c->bz_tesla != 0.0) return fail(EMS_E_INVALID, "box geometries take no magnetic field");
   if ((uint64_t)c->max_steps_per_track >= (1ull << (32 - vol_bits(g))))
     return fail(EMS_E_INVALID, "max_steps_per_track too large for this many boxes");
   return EMS_OK;
@@ -615,7 +614,7 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
   bool compound = false;
   for (const MatRT& m : c->ts.rt) compound = compound || m.n_el > 1;
   const bool record = (cfg->flags & (EMS_F_STEPLOG | EMS_F_FULL_LEDGER | EMS_F_EVENT_LIVE)) || cfg->exit_capacity;
-  const uint32_t need_l = (geo->n_boxes == 0 && cfg->bz_tesla != 0.0 ? kFField : 0) |
+  const uint32_t need_l = (cfg->bz_tesla != 0.0 ? kFField : 0) |
                           (cfg->process_mask & EMS_P_MSC ? kFMsc : 0) | (cfg->process_mask & EMS_P_FLUCT ? kFFluct : 0) |
                           (compound ? kFCompound : 0) | (record ? kFRecord : 0);
   const uint32_t need_g = (compound ? kFCompound : 0) | (record ? kFRecord : 0);

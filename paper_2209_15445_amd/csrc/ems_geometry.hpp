@@ -218,20 +218,17 @@ EMS_HD double box_distance(const BoxNav& g, int v, const double p[3], const doub
   fc.box = -1;
   const double iu[3] = {1.0 / u[0], 1.0 / u[1], 1.0 / u[2]};
   // front to back: the nearer child first, nodes entered beyond the best
-  // distance so far skipped (entry distances kept beside the stack)
+  // distance so far skipped (entry distances kept beside the stack).  The
+  // walk descends into the nearer child with the bounds it has just read
+  // and stacks only the farther one, so a descent costs one dependent read
+  // per level; the order of the visits is that of pushing both children
+  // and popping the nearer one.
   uint32_t stack[kBvhStack];
   float tstack[kBvhStack];
   int sp = 0;
-  const double t0 = node_entry(g.node[0], p, iu, u, best);
-  if (t0 <= best) {
-    stack[0] = 0;
-    tstack[0] = (float)t0;
-    sp = 1;
-  }
-  while (sp > 0) {
-    --sp;
-    if ((double)tstack[sp] > best * (1.0 + 1e-6)) continue;  // float copy: compare with margin
-    const BvhNode nd = g.node[stack[sp]];
+  BvhNode nd = g.node[0];
+  if (!(node_entry(nd, p, iu, u, best) <= best)) return best;
+  for (;;) {
     if (nd.count) {
       for (uint32_t i = 0; i < nd.count; ++i) {
         const uint32_t id = g.leaf[nd.a + i];
@@ -246,24 +243,230 @@ EMS_HD double box_distance(const BoxNav& g, int v, const double p[3], const doub
         }
       }
     } else if (sp + 2 <= kBvhStack) {
-      const double tl = node_entry(g.node[nd.a], p, iu, u, best);
-      const double tr = node_entry(g.node[nd.a + 1], p, iu, u, best);
+      const BvhNode cl = g.node[nd.a], cr = g.node[nd.a + 1];
+      const double tl = node_entry(cl, p, iu, u, best);
+      const double tr = node_entry(cr, p, iu, u, best);
       const bool lfirst = tl <= tr;
       const double tn = lfirst ? tl : tr, tf = lfirst ? tr : tl;
-      const uint32_t cn = lfirst ? nd.a : nd.a + 1, cf = lfirst ? nd.a + 1 : nd.a;
+      const uint32_t cf = lfirst ? nd.a + 1 : nd.a;
       if (tf <= best) {
         stack[sp] = cf;
         tstack[sp] = (float)tf;
         ++sp;
       }
       if (tn <= best) {
-        stack[sp] = cn;
-        tstack[sp] = (float)tn;
-        ++sp;
+        nd = lfirst ? cl : cr;
+        continue;
+      }
+    }
+    // the next stacked node still entered within the best distance
+    // (float copy: compared with a margin)
+    bool more = false;
+    while (sp > 0) {
+      --sp;
+      if ((double)tstack[sp] > best * (1.0 + 1e-6)) continue;
+      nd = g.node[stack[sp]];
+      more = true;
+      break;
+    }
+    if (!more) break;
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------- helix
+// A charged track in the field Bz turns about z: with psi = |kappa| s the
+// angle turned after path s, its transverse position runs on the circle
+// x = cx + rad sin(psi - phase), y = cy + sgn rad cos(psi - phase)
+// (sgn the sign of kappa, rad = u_perp / |kappa|) and z = z0 + uz s.  A
+// plane x = X or y = Y is met at angles from asin / acos, a z plane
+// linearly; the boundary of a box is reached at the first such crossing
+// (leaving a box: outward through any face; entering one: inward at a point
+// within the face).
+struct HelixPath {
+  double p0[3], uz, ak, rad, cx, cy, phase;
+  int sgn;
+};
+
+EMS_HD HelixPath helix_path(const double p[3], const double u[3], double kappa) {
+  HelixPath h;
+  for (int k = 0; k < 3; ++k) h.p0[k] = p[k];
+  h.uz = u[2];
+  h.ak = fabs(kappa);
+  h.sgn = kappa > 0.0 ? 1 : -1;
+  h.rad = sqrt(u[0] * u[0] + u[1] * u[1]) / h.ak;
+  h.cx = p[0] + u[1] / kappa;
+  h.cy = p[1] - u[0] / kappa;
+  h.phase = h.sgn * atan2(u[1], u[0]);
+  return h;
+}
+
+// angle from the start (psi = 0) forward to the circle angle th, in
+// [0, 2 pi); within 1e-9 of a whole turn it is the start itself
+EMS_HD double helix_advance(const HelixPath& h, double th) {
+  constexpr double kTurn = 6.28318530717958647692;
+  double d = fmod(th + h.phase, kTurn);
+  if (d < 0.0) d += kTurn;
+  return d > kTurn - 1e-9 ? 0.0 : d;
+}
+
+// first psi >= 0 at which the plane coordinate[axis] = v (axis 0 or 1) is
+// crossed moving up (up = true) or down that axis; negative if never
+EMS_HD double helix_plane(const HelixPath& h, int axis, double v, bool up) {
+  if (!(h.rad > 0.0)) return -1.0;
+  constexpr double kPiD = 3.14159265358979323846;
+  if (axis == 0) {
+    const double w = (v - h.cx) / h.rad;
+    if (!(w >= -1.0 && w <= 1.0)) return -1.0;
+    const double a = asin(w);  // x grows where cos(theta) > 0
+    return helix_advance(h, up ? a : kPiD - a);
+  }
+  const double w = h.sgn * (v - h.cy) / h.rad;
+  if (!(w >= -1.0 && w <= 1.0)) return -1.0;
+  const double a = acos(w);    // y grows where sgn sin(theta) < 0
+  return helix_advance(h, up ? -h.sgn * a : h.sgn * a);
+}
+
+// position after path s (the propagation's formulas)
+EMS_HD void helix_point(const HelixPath& h, const double u[3], double kappa, double s, double q[3]) {
+  const double ph = kappa * s;
+  double sh, ch;
+  sincos(0.5 * ph, &sh, &ch);
+  const double sp = 2.0 * sh * ch, omc = 2.0 * sh * sh;
+  q[0] = h.p0[0] + (u[0] * sp + u[1] * omc) / kappa;
+  q[1] = h.p0[1] + (u[1] * sp - u[0] * omc) / kappa;
+  q[2] = h.p0[2] + u[2] * s;
+}
+
+// leaving the box [lo, hi] from inside: path length to the first outward
+// crossing (the first axis on ties), infinity if it never leaves
+EMS_HD double helix_leave(const HelixPath& h, const double* lo, const double* hi, Face& fc) {
+  double best = __builtin_huge_val();
+  for (int k = 0; k < 3; ++k) {
+    double d = __builtin_huge_val(), f = 0.0;
+    int side = 0;
+    if (k < 2) {
+      const double a = helix_plane(h, k, hi[k], true), b = helix_plane(h, k, lo[k], false);
+      if (a >= 0.0 && (b < 0.0 || a <= b)) {
+        d = a / h.ak;
+        f = hi[k];
+        side = 1;
+      } else if (b >= 0.0) {
+        d = b / h.ak;
+        f = lo[k];
+      }
+    } else if (h.uz != 0.0) {
+      side = h.uz > 0.0 ? 1 : 0;
+      f = side ? hi[2] : lo[2];
+      d = (f - h.p0[2]) / h.uz;
+      d = d < 0.0 ? 0.0 : d;
+    }
+    if (d < best) {
+      best = d;
+      fc.ax = k;
+      fc.f = f;
+      fc.side = side;
+    }
+  }
+  return best;
+}
+
+// entering the box [lo, hi] from outside within path smax: the smallest
+// path length at which the helix crosses a face plane inward at a point
+// within the face (x and y planes once per turn each way), or infinity
+EMS_HD double helix_enter(const HelixPath& h, const double u[3], double kappa, const double* lo, const double* hi,
+                          double smax, Face& fc) {
+  double best = __builtin_huge_val();
+  for (int k = 0; k < 3; ++k) {
+    for (int side = 0; side < 2; ++side) {
+      const double v = side ? hi[k] : lo[k];
+      double s0, turn = __builtin_huge_val();
+      if (k < 2) {
+        const double a = helix_plane(h, k, v, side == 0);
+        if (a < 0.0) continue;
+        s0 = a / h.ak;
+        turn = 6.28318530717958647692 / h.ak;
+      } else {
+        if (h.uz == 0.0 || (h.uz > 0.0) != (side == 0)) continue;
+        s0 = (v - h.p0[2]) / h.uz;
+        if (s0 < 0.0) continue;
+      }
+      for (double sc = s0; sc <= smax && sc < best; sc += turn) {
+        double q[3];
+        helix_point(h, u, kappa, sc, q);
+        q[k] = v;
+        const int j1 = k == 0 ? 1 : 0, j2 = k == 2 ? 1 : 2;
+        if (q[j1] >= lo[j1] && q[j1] <= hi[j1] && q[j2] >= lo[j2] && q[j2] <= hi[j2]) {
+          best = sc;
+          fc.ax = k;
+          fc.f = v;
+          fc.side = side;
+          break;
+        }
+        if (!(turn < __builtin_huge_val())) break;
       }
     }
   }
   return best;
+}
+
+// path length along the helix of curvature kappa to the next boundary from
+// volume v, searched up to smax (infinity: none within smax), with the face
+// reached: a box's own faces; from the world the nearer of its exit and the
+// first box entered (boxes win ties), the boxes found through the hierarchy
+// by the bounding box of the arc
+EMS_HD double helix_distance(const BoxNav& g, int v, const double p[3], const double u[3], double kappa,
+                             double smax, Face& fc) {
+  const HelixPath h = helix_path(p, u, kappa);
+  double best;
+  if ((uint32_t)v < g.n_boxes) {
+    const BoxRec& b = g.rec[v];
+    best = helix_leave(h, b.lo, b.hi, fc);
+    fc.box = v;
+  } else {
+    best = helix_leave(h, g.wlo, g.whi, fc);
+    fc.box = -1;
+    double lim = smax < best ? smax : best;
+    const double turn = 6.28318530717958647692 / h.ak;
+    if (h.uz == 0.0 && turn < lim) lim = turn;  // a circle in a plane: one turn
+    if (lim < __builtin_huge_val()) {
+      // the arc over [0, lim] lies within the circle's box, within lim of
+      // the start, and between the z of its ends
+      double alo[3], ahi[3];
+      alo[0] = fmax(h.cx - h.rad, p[0] - lim);
+      ahi[0] = fmin(h.cx + h.rad, p[0] + lim);
+      alo[1] = fmax(h.cy - h.rad, p[1] - lim);
+      ahi[1] = fmin(h.cy + h.rad, p[1] + lim);
+      alo[2] = fmin(p[2], p[2] + u[2] * lim);
+      ahi[2] = fmax(p[2], p[2] + u[2] * lim);
+      uint32_t stack[kBvhStack];
+      int sp = 0;
+      stack[sp++] = 0;
+      while (sp > 0) {
+        const BvhNode nd = g.node[stack[--sp]];
+        if (ahi[0] < nd.lo[0] || alo[0] > nd.hi[0] || ahi[1] < nd.lo[1] || alo[1] > nd.hi[1] || ahi[2] < nd.lo[2] ||
+            alo[2] > nd.hi[2])
+          continue;
+        if (nd.count) {
+          for (uint32_t i = 0; i < nd.count; ++i) {
+            const uint32_t id = g.leaf[nd.a + i];
+            const double* b = g.box + (size_t)id * 6;
+            Face f2{0, 0.0, 0, (int)id};
+            const double d = helix_enter(h, u, kappa, b, b + 3, lim < best ? lim : best, f2);
+            if (d <= best) {
+              best = d;
+              fc = f2;
+              fc.box = (int)id;
+            }
+          }
+        } else if (sp + 2 <= kBvhStack) {
+          stack[sp++] = nd.a + 1;
+          stack[sp++] = nd.a;
+        }
+      }
+    }
+  }
+  return best <= smax ? best : __builtin_huge_val();
 }
 
 // volume entered after reaching face fc at p (the coordinate is set to the

@@ -30,6 +30,12 @@ namespace ems {
 namespace {
 
 constexpr int kBlock = 256;
+// lanes waiting in the world volume that make a wave compute their boundary
+// distances together (box geometries)
+#ifndef EMS_WORLD_BATCH
+#define EMS_WORLD_BATCH 16
+#endif
+constexpr uint32_t kWorldBatch = EMS_WORLD_BATCH;
 // s_waitcnt immediate for "all vector memory operations done" (vmcnt 0,
 // expcnt and lgkmcnt at their maxima: not waited on)
 constexpr int kWaitVmem = 0x0F70;
@@ -348,18 +354,20 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 #ifndef EMS_WAVES_F32_LEPTON
 #define EMS_WAVES_F32_LEPTON 3  // 168 registers, a few spills: 8% faster than 2 waves of 205
 #endif
-// Box geometries: photon steps wait on dependent loads of box records, so
-// more resident waves pay for the spills they cost (FP64 at 3: photon
-// launches 7% shorter; FP32 at 4: 25% shorter than at 2).  The e-/e+
-// kernels keep the slab settings (more waves made them slower).
+// Box geometries: photon steps wait on dependent loads of box records; with
+// the world volume's boundary distances computed for many lanes at once,
+// the photon kernels gain more from running without register spills (FP64
+// at 2 waves: 168 VGPRs and 132 spilled at 3; towers photon launch 2.85 ms
+// instead of 3.44 ms; FP32 at 3: 2.58 ms instead of 2.90 ms at 4).  The
+// e-/e+ kernels keep the slab settings (more waves made them slower).
 #ifndef EMS_WAVES_BOX_F64_PHOTON
-#define EMS_WAVES_BOX_F64_PHOTON 3
+#define EMS_WAVES_BOX_F64_PHOTON 2
 #endif
 #ifndef EMS_WAVES_BOX_F64_LEPTON
 #define EMS_WAVES_BOX_F64_LEPTON EMS_WAVES_F64_LEPTON
 #endif
 #ifndef EMS_WAVES_BOX_F32_PHOTON
-#define EMS_WAVES_BOX_F32_PHOTON 4
+#define EMS_WAVES_BOX_F32_PHOTON 3
 #endif
 #ifndef EMS_WAVES_BOX_F32_LEPTON
 #define EMS_WAVES_BOX_F32_LEPTON EMS_WAVES_F32_LEPTON
@@ -414,8 +422,35 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     uint32_t visits_e = 0, visits_p = 0, steps_e = 0, steps_p = 0, carried_n = 0;
     uint32_t made0 = 0, made1 = 0, made2 = 0;
     uint32_t kept_a = 0, kept_b = 0;  // home records written (own species; e+)
+    // Box geometries: a step that starts in the world volume needs the
+    // nearest box along the track, a walk of the hierarchy that costs the
+    // whole wave as much as many ordinary steps however few lanes take it.
+    // Such lanes wait (world_wait), also across batches, until kWorldBatch
+    // of them do or no other lane steps; then the wave computes their
+    // distances together (world_ready, world_pre) and they take their steps
+    // with them.
+    bool world_ready = false;
+    GeoPre world_pre{0.0, Face{0, 0.0, 0, -1}};
+    // (charged tracks in a field search their boundary along the helix
+    // within their own step limit: they take no straight-line distance)
+    const bool world_batch = PHOTONS || !((F & kFField) && env.bz != 0.0);
     for (;;) {
-      const uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin));
+      bool world_wait = false;
+      if constexpr (GEO == 1)
+        world_wait = world_batch && has && !fin && !world_ready && (uint32_t)t.slab == env.nav.n_boxes;
+      uint32_t stepping = (uint32_t)__popcll(__ballot(has && !fin && !world_wait));
+      if constexpr (GEO == 1) {
+        const uint32_t nw = (uint32_t)__popcll(__ballot(world_wait));
+        if (nw && (nw >= kWorldBatch || stepping == 0)) {
+          if (world_wait) {
+            const double p[3] = {t.x, t.y, t.z}, u[3] = {(double)t.ux, (double)t.uy, (double)t.uz};
+            world_pre.s = box_distance(env.nav, t.slab, p, u, world_pre.fc);
+            world_ready = true;
+            world_wait = false;
+          }
+          stepping += nw;
+        }
+      }
       // batch point: few lanes still stepping (or none, once the queue is drained)
       if (stepping <= (drained ? 0u : refill_below)) {
         // (0) e-/e+: while the queue still has tracks, interactions are
@@ -600,6 +635,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
           sp = nsp;
           has = true;
           visit_begin<KIND>(env, sp, t, vs);
+          world_ready = false;
           if (sp == 2) ++visits_p;
           else ++visits_e;
         }
@@ -607,13 +643,17 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
           if (drained) break;
           continue;
         }
+        // tracks just taken that start in the world wait for a world pass
+        if constexpr (GEO == 1)
+          world_wait = world_batch && has && !fin && !world_ready && (uint32_t)t.slab == env.nav.n_boxes;
       }
 
       // one step of every lane inside a visit
-      if (has && !fin) {
+      if (has && !fin && !world_wait) {
         before = t;
         const double e0 = t.E;
-        fin = visit_step<KIND, R, GEO, F>(env, sp, vs, t, o, max_visit);
+        fin = visit_step<KIND, R, GEO, F>(env, sp, vs, t, o, max_visit, world_ready ? &world_pre : nullptr);
+        world_ready = false;
         held = o.pending;
         if (!held) {
           sink.apply<F>(sp, t, o, e0);

@@ -203,6 +203,13 @@ EMS_HD void land_on_plane(const StepEnv<R>& e, Trk<R>& t, StepOut<R>& o, bool up
 }
 
 // Geometry kinds: 0 = the slab stack, 1 = boxes (see ems_geometry.hpp).
+// A boundary distance computed before the step (box geometries: the
+// kernels compute the world volume's distances for several lanes at once),
+// exactly the value the step would compute itself.
+struct GeoPre {
+  double s;
+  Face fc;
+};
 // Box geometry: distance to the next boundary and the face reached.
 template <class R>
 EMS_HD double box_dist(const StepEnv<R>& e, const Trk<R>& t, Face& fc, const double* iu = nullptr) {
@@ -489,7 +496,7 @@ EMS_HD R gamma_loss(R mean, R var, Draws& r) {
 }
 
 template <class R, int GEO = 0, int F = kFAll>
-EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o) {
+EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R>& o, const GeoPre* pre = nullptr) {
   Draws r;
   r.init(e.seed, t.key, t.id, t.n);
   const double T = t.E;
@@ -505,41 +512,6 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     }
     return;
   }
-  const bool field = (F & kFField) && GEO == 0 && e.bz != 0.0;  // box geometries take no field
-  Face fc{0, 0.0};
-  double sz;
-  if constexpr (GEO == 1) sz = box_dist(e, t, fc);
-  else sz = dist_to_planes(e, t);
-  double sg;
-  bool zlim;
-  if (field) {
-    const double ax = fabs(t.x), ay = fabs(t.y);
-    const double dw = e.half_xy - (ax > ay ? ax : ay);
-    if (dw < kSafetyMin) {
-      o.limiter = kLimEscapeSafety;
-      o.escaped += T;
-      t.E = 0.0;
-      t.slab = -1;
-      return;
-    }
-    zlim = sz <= dw;
-    sg = zlim ? sz : dw;
-  } else {
-    // The distance along the track to a transverse wall is at least the
-    // perpendicular distance to the nearest wall (|u_x|, |u_y| <= 1 up to the
-    // rounding of a unit vector, covered by the 2^-20 margin), so the wall
-    // can only limit the step when that perpendicular distance does not
-    // exceed the plane distance; otherwise sz <= sw holds and the two
-    // divisions are skipped, with the same result.
-    double sw = kInf;
-    if constexpr (GEO != 1) {
-      const double ax = fabs(t.x), ay = fabs(t.y);
-      const double dperp = e.half_xy - (ax > ay ? ax : ay);
-      if (!(dperp * (1.0 - 0x1p-20) > sz)) sw = dist_to_walls(e, t);
-    }
-    zlim = sz <= sw;
-    sg = zlim ? sz : sw;
-  }
   const uint32_t m = e.slab_mat[t.slab];
   const bool cont = (e.mask & kPCont) != 0;
   const bool fluct = (F & kFFluct) && cont && (e.mask & kPFluct) != 0;
@@ -552,6 +524,60 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
     Rv = lerp(Rt, b);
     const R al = (R)e.alpha, rh = (R)e.rho;
     scont = Rv <= rh ? Rv : al * Rv + rh * (R(1) - al) * (R(2) - rh / Rv);
+  }
+  const bool field = (F & kFField) && e.bz != 0.0;
+  Face fc{0, 0.0, 0, -1};
+  double sg;
+  bool zlim;
+  if constexpr (GEO == 1) {
+    if (field) {
+      // the boundary along the helix, searched up to the continuous-loss
+      // limit (beyond it the boundary cannot limit the step)
+      const double kap = (positron ? kKB : -kKB) * e.bz / sqrt(T * (T + 2.0 * kMe));
+      const double p[3] = {t.x, t.y, t.z}, u[3] = {(double)t.ux, (double)t.uy, (double)t.uz};
+      sg = helix_distance(e.nav, t.slab, p, u, kap, (double)scont, fc);
+      zlim = true;
+      if (!(sg < kInf) && !((double)scont < kInf)) {
+        sg = kTwoPi / fabs(kap);  // nothing limits the step: one turn, no crossing
+        zlim = false;
+      }
+    } else {
+      if (pre) {
+        sg = pre->s;
+        fc = pre->fc;
+      } else {
+        sg = box_dist(e, t, fc);
+      }
+      zlim = true;
+    }
+  } else {
+    const double sz = dist_to_planes(e, t);
+    if (field) {
+      const double ax = fabs(t.x), ay = fabs(t.y);
+      const double dw = e.half_xy - (ax > ay ? ax : ay);
+      if (dw < kSafetyMin) {
+        o.limiter = kLimEscapeSafety;
+        o.escaped += T;
+        t.E = 0.0;
+        t.slab = -1;
+        return;
+      }
+      zlim = sz <= dw;
+      sg = zlim ? sz : dw;
+    } else {
+      // The distance along the track to a transverse wall is at least the
+      // perpendicular distance to the nearest wall (|u_x|, |u_y| <= 1 up to
+      // the rounding of a unit vector, covered by the 2^-20 margin), so the
+      // wall can only limit the step when that perpendicular distance does
+      // not exceed the plane distance; otherwise sz <= sw holds and the two
+      // divisions are skipped, with the same result.
+      double sw = kInf;
+      const double ax = fabs(t.x), ay = fabs(t.y);
+      const double dperp = e.half_xy - (ax > ay ? ax : ay);
+      if (!(dperp * (1.0 - 0x1p-20) > sz)) sw = dist_to_walls(e, t);
+      zlim = sz <= sw;
+      sg = zlim ? sz : sw;
+    }
   }
   const double smax = (double)scont <= sg ? (double)scont : sg;
   double elo = T, loss_max = 0.0;
@@ -800,7 +826,8 @@ EMS_HD void photon_begin(const StepEnv<R>& e, const Trk<R>& t, PhotonCache<R>& p
 // step count and watchdog of take_step.  Returns true when the visit must
 // end after it (the photon interacted or is gone).
 template <class R, int GEO = 0>
-EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>& t, StepOut<R>& o) {
+EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>& t, StepOut<R>& o,
+                           const GeoPre* pre = nullptr) {
   clear_out(t, o);
   const double E = t.E;
   if (E < e.ecut) {
@@ -818,8 +845,13 @@ EMS_HD bool photon_substep(const StepEnv<R>& e, const PhotonCache<R>& pc, Trk<R>
     Face fc{0, 0.0};
     double sz, sw;
     if constexpr (GEO == 1) {
-      const double iu[3] = {pc.iux, pc.iuy, pc.iuz};
-      sz = box_dist(e, t, fc, iu);
+      if (pre) {
+        sz = pre->s;
+        fc = pre->fc;
+      } else {
+        const double iu[3] = {pc.iux, pc.iuy, pc.iuz};
+        sz = box_dist(e, t, fc, iu);
+      }
       sw = kInf;
     } else {
       const double h = e.half_xy;
@@ -884,13 +916,14 @@ EMS_HD void visit_begin(const StepEnv<R>& e, int sp, const Trk<R>& t, VisitState
 // interaction is left pending (o.pending) for the caller to run with
 // interact(), so that a wave samples its interactions together.
 template <int KIND, class R, int GEO = 0, int F = kFAll>
-EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps) {
+EMS_HD bool visit_step(const StepEnv<R>& e, int sp, VisitState<R>& vs, Trk<R>& t, StepOut<R>& o, int max_steps,
+                       const GeoPre* pre = nullptr) {
   bool end;
   if (KIND == 0 || (KIND == 2 && sp == kGamma)) {
-    end = photon_substep<R, GEO>(e, vs.pc, t, o);
+    end = photon_substep<R, GEO>(e, vs.pc, t, o, pre);
   } else {
     clear_out(t, o);
-    lepton_step<R, GEO, F>(e, sp == kPositron, t, o);
+    lepton_step<R, GEO, F>(e, sp == kPositron, t, o, pre);
     if (!o.pending) watchdog(e, t, o);
     end = t.slab < 0 || o.pending;
   }

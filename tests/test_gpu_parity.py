@@ -159,13 +159,15 @@ def test_msc_fluct_1gev_32_events(E, oracle_mod):
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
 
 
+@pytest.mark.parametrize("bz", [0.0, 3.8])
 @pytest.mark.parametrize("mask", [I.P_ALL, I.P_ALL | I.P_MSC | I.P_FLUCT])
-def test_box_geometry_history_parity(E, oracle_mod, mask):
+def test_box_geometry_history_parity(E, oracle_mod, mask, bz):
     """towers of boxes with cracks of world material: the kernels walking the
-    hierarchy against the oracle walking all boxes, step by step"""
-    print(f"box history parity mask={mask}", flush=True)
+    hierarchy against the oracle walking all boxes, step by step; in the
+    field charged tracks cross boxes and cracks along the helix"""
+    print(f"box history parity mask={mask} bz={bz}", flush=True)
     geo = I.towers(cells=5, n_layers=10)
-    cfg = I.RunConfig(seed=23, process_mask=mask)
+    cfg = I.RunConfig(seed=23, process_mask=mask, bz_tesla=bz)
     prim = tiny_mixed_primaries()
     prim["ekin"] *= 20.0
     rng = np.random.default_rng(2)
@@ -183,6 +185,30 @@ def test_box_geometry_history_parity(E, oracle_mod, mask):
     assert np.allclose(g["edep"], r["edep"], rtol=tol, atol=tol)
     assert g["edep"][:, -1].sum() > 0.0
     assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box_towers_in_a_field_1gev(E, oracle_mod, precision):
+    """1 GeV showers into the 9 x 9 towers at 3.8 T: FP64 equal to the oracle
+    per volume; mixed within its tolerance of energy conservation, with the
+    same per-layer deposits as FP64 within the statistics of 16 showers"""
+    print(f"towers in a field 1 GeV {precision}", flush=True)
+    geo = I.towers()
+    cfg = I.RunConfig(seed=31, bz_tesla=3.8)
+    prim = I.beam(16, I.ELECTRON, 1000.0, smear_rad=1e-3, seed=31)
+    prim["pos"][:, 0] = np.linspace(-25.0, 25.0, 16)
+    prec = E.MIXED if precision == "mixed" else E.FP64
+    g = run_gpu(E, geo, cfg, prim, 16, flags=E.F_FULL_LEDGER, precision=prec, capacity=1 << 22)
+    if prec == E.FP64:
+        r = oracle_mod.Oracle(geo, cfg).run(prim, n_events=16)
+        assert np.array_equal(g["ledger"]["n_steps"], r["ledger"]["n_steps"])
+        assert np.allclose(g["edep"], r["edep"], rtol=1e-9, atol=1e-9)
+        assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-9
+    else:
+        assert ledger_residual(g["edep"], g["ledger"], prim).max() < 1e-5
+        f = run_gpu(E, geo, cfg, prim, 16, flags=E.F_FULL_LEDGER, capacity=1 << 22)
+        assert abs(g["edep"].sum() / f["edep"].sum() - 1.0) < 0.02
+    assert g["edep"][:, -1].sum() > 0.0
 
 
 def test_box_towers_1gev_32_events(E, oracle_mod):

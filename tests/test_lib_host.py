@@ -298,6 +298,42 @@ def test_host_box_9x9_towers_showers(E, oracle_mod):
     _box_parity(E, oracle_mod, geo, cfg, prim, 4)
 
 
+@pytest.mark.parametrize("mask", [I.P_ALL, I.P_ALL | I.P_MSC | I.P_FLUCT])
+def test_host_box_navigation_in_a_field_matches_the_oracle(E, oracle_mod, mask):
+    """charged tracks on the helix through towers and cracks (the step code's
+    crossings found through the hierarchy) against the oracle's crossings
+    over all boxes, step by step, at 3.8 T"""
+    geo = I.towers(cells=5, n_layers=10)
+    cfg = I.RunConfig(seed=33, bz_tesla=3.8, process_mask=mask)
+    prim = tiny_mixed_primaries()
+    prim["ekin"] *= 20.0
+    rng = np.random.default_rng(12)
+    prim["pos"][:, 0] = rng.uniform(-70, 70, len(prim))
+    prim["pos"][:, 1] = rng.uniform(-70, 70, len(prim))
+    d = rng.normal(size=(len(prim), 3))
+    d[:, 2] = np.abs(d[:, 2]) + 0.3
+    prim["dir"] = d / np.linalg.norm(d, axis=1)[:, None]
+    h, r = _box_parity(E, oracle_mod, geo, cfg, prim, 48, e_rtol=1e-9)
+    log = r["log"][: r["n_log"]]
+    assert np.any((log["species"] != 0) & (log["slab_after"] == geo.n_boxes))  # charged steps in the cracks
+
+
+def test_host_box_random_tracks_in_a_field(E, oracle_mod):
+    geo = I.towers(cells=5, n_layers=10)
+    cfg = I.RunConfig(seed=34, bz_tesla=3.8)
+    rng = np.random.default_rng(6)
+    n = 300
+    prim = I.primaries(n)
+    prim["event"] = rng.integers(0, 20, n)
+    prim["species"] = rng.integers(0, 3, n)
+    prim["ekin"] = np.exp(rng.uniform(np.log(1e-2), np.log(50.0), n))
+    prim["pos"] = rng.uniform(np.array(geo.world_lo) * 0.999, np.array(geo.world_hi) * 0.999, (n, 3))
+    prim["pos"][:, 2] = rng.uniform(0.0, geo.world_hi[2], n)
+    d = rng.normal(size=(n, 3))
+    prim["dir"] = d / np.linalg.norm(d, axis=1)[:, None]
+    _box_parity(E, oracle_mod, geo, cfg, prim, 20, e_rtol=1e-9)
+
+
 def test_box_validation(E):
     good = E.make_config(I.RunConfig(), 4)
     geo = I.towers(cells=3, n_layers=2)
@@ -310,7 +346,7 @@ def test_box_validation(E):
     g.material = g.material.copy()
     g.material[1] = 5
     assert _bad(E, good, g) == E.E_INVALID
-    assert _bad(E, E.make_config(I.RunConfig(bz_tesla=1.0), 4), geo) == E.E_INVALID
+    assert _bad(E, E.make_config(I.RunConfig(bz_tesla=1.0), 4), geo) == E.OK  # a field is taken
     big = I.towers(cells=9, n_layers=50)
     assert _bad(E, E.make_config(I.RunConfig(max_steps_per_track=(1 << 19) - 1), 4), big) == E.OK
     assert _bad(E, E.make_config(I.RunConfig(max_steps_per_track=1 << 19), 4), big) == E.E_INVALID
