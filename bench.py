@@ -192,12 +192,17 @@ def transport_leg(E, I, workload, precision, capacity, args):
                       interact_min=args.interact_min, photon_steps_per_visit=pvisit,
                       photon_refill_below=prefill, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
+    # the job's inputs resident in HBM before the timed region; the tallies
+    # stay there (the rate with host memory on both sides follows below)
+    prim_dev = torch.from_numpy(np.ascontiguousarray(prim).view(np.uint8)).to("cuda")
+    out_dev = torch.empty((c.max_events, eng.n_slabs), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
 
     def one_step():
         eng.reset()
-        eng.enqueue(prim)
+        eng.enqueue_device(prim_dev)
         eng.run()
-        return eng.edep()
+        eng.edep_device(out_dev)
 
     for _ in range(args.warmup):
         one_step()
@@ -209,7 +214,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
     visits = [0, 0, 0]
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        edep = one_step()
+        one_step()
         s = eng.stats()
         kms = [a + b for a, b in zip(kms, s["kernel_ms"])]
         launches += s["launches"]
@@ -218,6 +223,24 @@ def transport_leg(E, I, workload, precision, capacity, args):
         visits = [a + b for a, b in zip(visits, s["visits"])]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    edep = out_dev.cpu().numpy()
+    # the same steps with the primaries taken from host memory and the
+    # tallies copied to host memory (both over PCIe): a few steps after one
+    # untimed one
+    host_steps = max(1, min(args.steps, 5))
+    eng.reset()
+    eng.enqueue(prim)
+    eng.run()
+    eng.edep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(host_steps):
+        eng.reset()
+        eng.enqueue(prim)
+        eng.run()
+        eng.edep()
+    torch.cuda.synchronize()
+    value_host_io = n * host_steps / (time.perf_counter() - t1)
     eng.close()
     tb = TRACK_BYTES if precision == E.FP64 else TRACK_BYTES_MIXED
     # algorithmic bytes of the method: every track-step reads the track's
@@ -268,7 +291,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
         eng.close()
     return dict(geo=geo, cfg=cfg, prim=prim, key=key, photon_launch=[pvisit, prefill],
                 value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
-                value_graph=value_graph,
+                value_graph=value_graph, value_host_io=value_host_io,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
                 deferred=s["deferred"], peak_live=s["peak_live"], iterations=s["iterations"])
 
@@ -427,11 +450,21 @@ def layer_error(leg, n_events):
             "total_rel": float((lm.sum() - lo.sum()) / lo.sum())}
 
 
+def geometry_label(geo):
+    """what a workload's geometry is, with its sizes"""
+    if hasattr(geo, "world_lo"):
+        w = np.subtract(geo.world_hi, geo.world_lo)
+        return f"{geo.n_boxes} boxes in a {w[0]:g} x {w[1]:g} x {w[2]:g} mm world (BVH)"
+    z = np.asarray(geo.z_mm)
+    return f"{len(z) - 1} slabs over {z[-1] - z[0]:g} mm, {2 * geo.half_xy_mm:g} mm square"
+
+
 def leg_summary(leg):
     """Throughput and the roofline of the dominant kernel of one leg (the
     same quantities as the headline line's, per workload and form)."""
     r = leg["roofline"]
     return {"value": leg["value"], "unit": "primaries/s", "ms_per_step": leg["ms_per_step"],
+            "value_host_io": leg["value_host_io"], "geometry": geometry_label(leg["geo"]),
             "photon_launch": leg["photon_launch"], "track_steps_per_step": leg["track_steps"],
             "iterations": leg["iterations"],
             "roofline": {"bound": r["bound"], "kernel": r["kernel"], "achieved": r["achieved"], "peak": r["peak"],
@@ -553,7 +586,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "events": n, "primary": "e-", "energy_MeV": float(prim["ekin"][0]),
-                   "geometry": "50 x (2.3 mm Pb + 5.7 mm lAr), 40x40 cm", "bz_tesla": cfg.bz_tesla,
+                   "geometry": geometry_label(geo), "bz_tesla": cfg.bz_tesla,
                    "precision": "fp64", "track_steps_per_step": fp["track_steps"],
                    "visits_per_step": fp["visits"], "iterations": fp["iterations"],
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
@@ -562,6 +595,9 @@ def main():
                    "photon_refill_below": fp["photon_launch"][1]},
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
+        "inputs": "primaries resident in device memory, deposits left there (ems_enqueue_device, "
+                  "ems_read_edep_device); value_host_io: primaries from and deposits to host memory",
+        "value_host_io": fp["value_host_io"],
     }
     out["atomics"] = atomics_report(fp, fp["key"], atomic_probe(E, n * geo.n_cols))
     copy_gbs = copy_bandwidth()
@@ -570,7 +606,7 @@ def main():
         mx = transport_leg(E, I, args.mixed_workload, E.MIXED, args.mixed_capacity, args)
         out["mixed"] = {"workload": args.mixed_workload, "events": len(mx["prim"]), "value": mx["value"],
                         "unit": "primaries/s", "ms_per_step": mx["ms_per_step"], "dtype": "f32 physics / f64 state",
-                        "value_graph_replay": mx["value_graph"],
+                        "value_graph_replay": mx["value_graph"], "value_host_io": mx["value_host_io"],
                         "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
                         "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
                         "capacity": args.mixed_capacity, "steps_per_visit": args.steps_per_visit_mixed,

@@ -338,6 +338,20 @@ ems_status ems_set_event_keys(ems_ctx* ctx, uint32_t first_row, uint32_t n,
  * outside the stack, bad species, event >= max_events) or EMS_E_CAPACITY
  * leaves the context unchanged.  Asynchronous on the bound stream. */
 ems_status ems_enqueue(ems_ctx* ctx, const ems_primary* host, uint64_t n);
+/* Particles in (section 4), already resident in device memory: as
+ * ems_enqueue for n primaries held by the caller in one device allocation
+ * (64-byte records, read by work queued on the bound stream: keep them
+ * unchanged until that stream has passed this call).  The checks,
+ * normalisation, volume location and per-row track ids (the running index
+ * of each primary within its row, in input order) are computed on the
+ * device and give the tracks ems_enqueue would give for the same records.
+ * All or nothing: EMS_E_INVALID for an invalid primary (as ems_enqueue) or
+ * a pointer that is not n records inside one device allocation;
+ * EMS_E_CAPACITY as ems_enqueue.  The primaries of a batch (between two
+ * ems_reset_tallies) come either from host or from device memory:
+ * EMS_E_STATE for a mix.  Returns after the check pass has drained the
+ * bound stream; staging and injection stay queued there. */
+ems_status ems_enqueue_device(ems_ctx* ctx, const ems_primary* d_primaries, uint64_t n);
 
 /* The stepping loop (section 3): every live track takes its steps, the
  * secondaries are appended to the next arrays, the arrays are swapped,
@@ -350,6 +364,13 @@ ems_status ems_run(ems_ctx* ctx);
  * the FP64 deposits of rows [first, first+n) to host_out[n][n_slabs]
  * (row-major, caller-owned); EMS_E_INVALID for rows out of range. */
 ems_status ems_read_edep(ems_ctx* ctx, uint32_t first, uint32_t n, double* host_out);
+/* Hits out (section 4), kept in device memory: copies the FP64 deposits
+ * of rows [first, first+n) to d_out[n][n_slabs] (row-major, caller-owned
+ * device memory, one allocation), asynchronously on the bound stream: the
+ * caller orders its own reads of d_out after that stream.  EMS_E_INVALID
+ * for rows out of range or an output that is not n rows inside one device
+ * allocation. */
+ems_status ems_read_edep_device(ems_ctx* ctx, uint32_t first, uint32_t n, double* d_out);
 /* Hits out (section 4), with the energy accounting of killed tracks that
  * section 2.3 requires: copies the ledgers of rows [first, first+n) to
  * host_out[n]; EMS_E_INVALID for rows out of range. */

@@ -116,6 +116,8 @@ def lib():
             "ems_create_static": [C.POINTER(Config), C.POINTER(Geometry), vp, C.POINTER(vp)],
             "ems_set_event_keys": [vp, u32, u32, vp],
             "ems_enqueue": [vp, vp, u64],
+            "ems_enqueue_device": [vp, vp, u64],
+            "ems_read_edep_device": [vp, u32, u32, vp],
             "ems_run": [vp],
             "ems_read_edep": [vp, u32, u32, vp],
             "ems_read_ledger": [vp, u32, u32, vp],
@@ -319,6 +321,18 @@ class Transport:
         p = _prim(prim)
         _check(lib().ems_enqueue(self._h, p.ctypes.data_as(C.c_void_p), len(p)))
 
+    def enqueue_device(self, prim):
+        """Primaries already in device memory: a contiguous CUDA tensor holding
+        whole 64-byte primary records (e.g. a uint8 copy of a PRIMARY_DTYPE
+        array)."""
+        nbytes = prim.numel() * prim.element_size()
+        if not prim.is_cuda or not prim.is_contiguous() or nbytes % PRIMARY_DTYPE.itemsize:
+            raise ValueError("primaries must be a contiguous device tensor of whole 64-byte records")
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(prim.device))  # the records are written
+        prim.record_stream(self.stream)  # and stay allocated until the library's stream has read them
+        _check(lib().ems_enqueue_device(self._h, C.c_void_p(prim.data_ptr()), nbytes // PRIMARY_DTYPE.itemsize))
+
     def run(self):
         _check(lib().ems_run(self._h))
 
@@ -326,6 +340,20 @@ class Transport:
         n = self.config.max_events - first if n is None else n
         out = np.empty((n, self.n_slabs))
         _check(lib().ems_read_edep(self._h, first, n, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def edep_device(self, out, first=0):
+        """Deposits of rows [first, first + out.shape[0]) into `out`, a
+        contiguous float64 CUDA tensor of shape (rows, n_slabs), copied on the
+        context's stream; the caller's current stream waits for the copy."""
+        import torch
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.dim() == 2
+                and out.shape[1] == self.n_slabs):
+            raise ValueError("out must be a contiguous float64 device tensor of shape (rows, n_slabs)")
+        self.stream.wait_stream(torch.cuda.current_stream(out.device))  # earlier uses of out are done
+        _check(lib().ems_read_edep_device(self._h, first, out.shape[0], C.c_void_p(out.data_ptr())))
+        out.record_stream(self.stream)
+        torch.cuda.current_stream(out.device).wait_stream(self.stream)  # later reads see the copy
         return out
 
     def ledger(self, first=0, n=None):

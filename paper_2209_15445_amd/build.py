@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libems.so")
-SOURCES = ["ems_kernels.hip", "ems_static.hip", "ems_api.cpp", "ems_tables.cpp", "ems_server.cpp", "ems_geometry.cpp"]
+SOURCES = ["ems_kernels.hip", "ems_primaries.hip", "ems_static.hip", "ems_api.cpp", "ems_tables.cpp", "ems_server.cpp", "ems_geometry.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

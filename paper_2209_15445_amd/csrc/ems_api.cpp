@@ -220,6 +220,9 @@ Layout plan(const ems_config* c, const ems_geometry* g, uint32_t inj_chunk = kIn
   L.profile = take((c->flags & EMS_F_PROFILE) ? (uint64_t)c->profile_capacity * 3 * 4 : 0);
   L.log = take((c->flags & EMS_F_STEPLOG) ? c->steplog_capacity * sizeof(StepRec) : 0);
   L.inj = take((uint64_t)inj_chunk * sizeof(InjRec));
+  L.dkey = take((uint64_t)c->max_events * 4);
+  L.drow = take((uint64_t)c->max_events * 8);
+  L.dchk = take(4 * 8);
   L.queues = take(6 * L.cap * queue_track_bytes(c));
   L.total = o;
   return L;
@@ -266,6 +269,24 @@ StepEnv<double> env_for(const ems_config* c, const ems_geometry* g, const TableS
   e.seed = c->seed;
   e.max_steps = c->max_steps_per_track;
   return e;
+}
+
+// true if [p, p + bytes) lies inside one device allocation
+bool device_range(const void* p, uint64_t bytes) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (at.type != hipMemoryTypeDevice) return false;
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+  return q >= b && bytes <= size - (q - b);
 }
 
 // slab of a point; a point on a plane belongs to the slab it moves into
@@ -700,6 +721,7 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
             hipMemcpyAsync(c->ws + L.elem, elem.data(), elem.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
             launch_fill_zero(c->ws + L.edep, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
             launch_fill_zero(c->ws + L.queues, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
+            launch_fill_zero(c->ws + L.drow, (uint64_t)cfg->max_events * 8, s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
     if (!no_alloc) {
@@ -745,6 +767,7 @@ ems_status ems_set_event_keys(ems_ctx* c, uint32_t first, uint32_t n, const uint
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   if (!keys || (uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
   std::copy(keys, keys + n, c->keys.begin() + first);  // applied to tracks enqueued from now on
+  c->keys_dirty = true;
   return EMS_OK;
 }
 
@@ -752,6 +775,12 @@ ems_status ems_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   if (!c) return fail(EMS_E_INVALID, "null context");
   if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
   return rt_enqueue(c, p, n);
+}
+
+ems_status ems_enqueue_device(ems_ctx* c, const ems_primary* p, uint64_t n) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  return rt_enqueue_device(c, p, n);
 }
 
 ems_status ems_run(ems_ctx* c) {
@@ -772,6 +801,17 @@ ems_status ems_run(ems_ctx* c) {
   }
   c->stats.run_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < 3; ++i) c->pending[i] = 0;
+  return EMS_OK;
+}
+
+ems_status ems_read_edep_device(ems_ctx* c, uint32_t first, uint32_t n, double* out) {
+  if (!c) return fail(EMS_E_INVALID, "null context");
+  if (c->failed) return fail(EMS_E_STATE, "context failed earlier");
+  if ((uint64_t)first + n > c->cfg.max_events) return fail(EMS_E_INVALID, "rows out of range");
+  if (n == 0) return EMS_OK;
+  const uint64_t row = (uint64_t)c->ncols * 8;
+  if (!out || !device_range(out, n * row)) return fail(EMS_E_INVALID, "output is not n rows in one device allocation");
+  HIPCHK(c, hipMemcpyAsync(out, c->ws + c->L.edep + first * row, n * row, hipMemcpyDeviceToDevice, c->stream));
   return EMS_OK;
 }
 
@@ -825,6 +865,11 @@ ems_status ems_reset_tallies(ems_ctx* c) {
   *c->pin_ctl = fresh;
   HIPCHK(c, hipMemcpyAsync(c->ws + L.ctl, c->pin_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->source == 2) {
+    HIPCHK(c, launch_fill_zero(c->ws + L.drow, (uint64_t)c->cfg.max_events * 8, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  c->source = 0;
   std::fill(c->row_count.begin(), c->row_count.end(), 0);
   c->stats = ems_run_stats{};
   return EMS_OK;
@@ -1034,6 +1079,9 @@ namespace ems {
 ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   if (n == 0) return EMS_OK;
   if (!p) return fail(EMS_E_INVALID, "null primaries");
+  if (c->source == 2)
+    return fail(EMS_E_STATE, "primaries of this batch came from device memory: reset the tallies before enqueueing from "
+                             "host memory");
   uint64_t add[3] = {0, 0, 0};
   for (uint64_t i = 0; i < n; ++i)
     if (p[i].species <= EMS_POSITRON) add[p[i].species] += 1;
@@ -1053,6 +1101,45 @@ ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n) {
   }
   c->row_count.swap(rows);
   for (int s = 0; s < 3; ++s) c->pending[s] += add[s];
+  c->source = 1;
+  return EMS_OK;
+}
+
+ems_status rt_enqueue_device(ems_ctx* c, const ems_primary* p, uint64_t n) {
+  static_assert(sizeof(ems_primary) == sizeof(PrimRec) && offsetof(ems_primary, ekin_MeV) == offsetof(PrimRec, E) &&
+                    offsetof(ems_primary, dir) == offsetof(PrimRec, dir),
+                "primary layout");
+  if (n == 0) return EMS_OK;
+  if (!p) return fail(EMS_E_INVALID, "null primaries");
+  if (c->source == 1)
+    return fail(EMS_E_STATE, "primaries of this batch came from host memory: reset the tallies before enqueueing from "
+                             "device memory");
+  if (n > (1ull << 40) || !device_range(p, n * sizeof(ems_primary)))
+    return fail(EMS_E_INVALID, "primaries are not n records in one device allocation");
+  const Layout& L = c->L;
+  uint32_t* keys = reinterpret_cast<uint32_t*>(c->ws + L.dkey);
+  if (c->keys_dirty) {
+    HIPCHK(c, hipMemcpyAsync(keys, c->keys.data(), c->keys.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->keys_dirty = false;
+  }
+  unsigned long long* chk = reinterpret_cast<unsigned long long*>(c->ws + L.dchk);
+  HIPCHK(c, launch_fill_zero(chk, sizeof(c->chk_host), c->stream));
+  HIPCHK(c, launch_check_primaries(c->args, p, n, chk, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->chk_host, chk, sizeof(c->chk_host), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->chk_host[0]) return fail(EMS_E_INVALID, "invalid primary #" + std::to_string(n - c->chk_host[0]));
+  for (int s = 0; s < 3; ++s)
+    if (c->pending[s] + c->chk_host[1 + s] > c->L.cap) return fail(EMS_E_CAPACITY, "queue capacity exceeded by primaries");
+  InjRec* d = reinterpret_cast<InjRec*>(c->ws + L.inj);
+  unsigned long long* rows = reinterpret_cast<unsigned long long*>(c->ws + L.drow);
+  for (uint64_t done = 0; done < n; done += L.inj_chunk) {
+    const uint32_t k = (uint32_t)std::min<uint64_t>(L.inj_chunk, n - done);
+    HIPCHK(c, launch_stage_primaries(c->args, p + done, k, keys, rows, d, c->stream));
+    HIPCHK(c, launch_inject(c->args, d, k, c->stream));
+  }
+  for (int s = 0; s < 3; ++s) c->pending[s] += c->chk_host[1 + s];
+  c->source = 2;
   return EMS_OK;
 }
 

@@ -19,12 +19,24 @@ hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, 
 hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s);
 hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s);
 hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
+// primaries in device memory: check pass (chk: first invalid, species
+// counts) and stage pass (injection records with ids) of k of them
+hipError_t launch_check_primaries(const KArgs& a, const void* p, uint64_t n, unsigned long long* chk, hipStream_t s);
+hipError_t launch_stage_primaries(const KArgs& a, const void* p, uint32_t k, const uint32_t* keys,
+                                  unsigned long long* row_next, InjRec* out, hipStream_t s);
 // zero bytes at p (8-byte aligned) with a kernel on stream s
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t s);
+
+// a primary as the public header lays it out (64 bytes)
+struct PrimRec {
+  uint32_t event, species;
+  double E, pos[3], dir[3];
+};
 
 // workspace regions (byte offsets) and the queue capacity
 struct Layout {
   uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, brec, nbr_off, nbr, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
+  uint64_t dkey, drow, dchk;  // device enqueue: event keys, ids per row, check words
   uint64_t cap;
   uint32_t inj_chunk;  // primaries staged per injection launch
 };
@@ -69,6 +81,12 @@ struct ems_ctx {
   uint32_t blocks_g = 0, blocks_l = 0;
   std::vector<uint64_t> row_count;
   std::vector<uint32_t> keys;  // RNG event key per row (host; travels with each injected track)
+  // where the batch's primaries came from since the last reset (0: none,
+  // 1: host memory, 2: device memory): the two paths count ids per row in
+  // different places (row_count here, the workspace's row counters there)
+  uint32_t source = 0;
+  bool keys_dirty = true;  // keys changed since their last upload (device enqueues read them there)
+  unsigned long long chk_host[4] = {0, 0, 0, 0};
   uint64_t pending[3] = {0, 0, 0};
   InjRec* pin_inj = nullptr;
   Ctl* pin_ctl = nullptr;
@@ -118,6 +136,7 @@ hipError_t static_workspace(int dev, void** p);
 // validate, prepare and append n primaries to the current queues (all or
 // nothing); rows listed in fresh_rows restart their track ids at 0
 ems_status rt_enqueue(ems_ctx* c, const ems_primary* p, uint64_t n);
+ems_status rt_enqueue_device(ems_ctx* c, const ems_primary* d_primaries, uint64_t n);
 // K iterations (after a census of the injected tracks); the status block is
 // left in c->pin_ctl; queue errors are returned as status codes
 ems_status rt_chunk(ems_ctx* c, uint32_t K);
