@@ -88,7 +88,7 @@ def serving(E, I, args, precision):
         pools.append([I.serving_request(rng) for _ in range(args.serve_pool)])
     c = E.make_config(cfg, args.serve_slots, track_capacity=args.serve_capacity,
                       steps_per_launch=args.serve_steps_per_launch, steps_per_visit=args.serve_steps_per_visit,
-                      refill_below=args.refill_below, interact_min=args.interact_min, precision=precision,
+                      refill_below=args.refill_below, interact_min=args.interact_min, short_electron_MeV=args.short_mev, precision=precision,
                       photon_steps_per_visit=args.serve_photon_steps_per_visit,
                       photon_refill_below=args.serve_photon_refill_below)
     srv = E.Server(c, geo, admit_cap_bytes=args.serve_admit_gib << 30)
@@ -171,6 +171,10 @@ def serving(E, I, args, precision):
 # (measured best): slab stacks favour long visits and an early refill, box
 # geometries, whose photon steps wait on box records, the opposite
 PHOTON_LAUNCH = {"slab": (32, 24), "boxes": (16, 40)}
+# short-electron threshold (MeV) per workload and form where the launch of
+# its own pays off (measured: the 10^5-event beam in the mixed form gains 3%;
+# 10^4-event workloads and the FP64 form lose 1-7%, small batches 13%)
+SHORT_MEV = {("cal_10GeV_e-_x100k", 1): 0.5}
 
 
 def photon_launch(args, geo):
@@ -187,9 +191,10 @@ def transport_leg(E, I, workload, precision, capacity, args):
     n = len(prim)
     visit = args.steps_per_visit if precision == E.FP64 else args.steps_per_visit_mixed
     pvisit, prefill = photon_launch(args, geo)
+    short_mev = SHORT_MEV.get((workload, precision), 0.0) if args.short_mev is None else args.short_mev
     c = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                       launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                      interact_min=args.interact_min, photon_steps_per_visit=pvisit,
+                      interact_min=args.interact_min, short_electron_MeV=short_mev, photon_steps_per_visit=pvisit,
                       photon_refill_below=prefill, precision=precision, flags=E.F_KERNEL_TIMING)
     eng = E.Transport(c, geo)
     # the job's inputs resident in HBM before the timed region; the tallies
@@ -207,8 +212,9 @@ def transport_leg(E, I, workload, precision, capacity, args):
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    kms = [0.0, 0.0]
+    kms = [0.0, 0.0, 0.0]
     launches = 0
+    short_steps = 0
     steps = [0, 0, 0]
     made_by = [0, 0]
     visits = [0, 0, 0]
@@ -218,6 +224,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
         s = eng.stats()
         kms = [a + b for a, b in zip(kms, s["kernel_ms"])]
         launches += s["launches"]
+        short_steps += s["short_steps"]
         steps = [a + b for a, b in zip(steps, s["steps"])]
         made_by = [a + b for a, b in zip(made_by, s["made_by"])]
         visits = [a + b for a, b in zip(visits, s["visits"])]
@@ -247,11 +254,15 @@ def transport_leg(E, I, workload, precision, capacity, args):
     # record and writes the survivor (2 records), every secondary adds one
     # record.  Multi-step visits move fewer: one read and at most one write
     # per visit ("record_bytes_per_launch").
-    names = ["k_visit<photons>", "k_visit<e-/e+>"]
-    alg = [tb * (2 * steps[0] + made_by[0]), tb * (2 * (steps[1] + steps[2]) + made_by[1])]
-    rec = [tb * (2 * visits[0] + made_by[0]), tb * (2 * (visits[1] + visits[2]) + made_by[1])]
+    # The short-electron launch takes one step of each short e- (its share
+    # of the e- steps is counted apart: short_steps).
+    names = ["k_visit<photons>", "k_visit<e-/e+>", "k_short<e->"]
+    alg = [tb * (2 * steps[0] + made_by[0]), tb * (2 * (steps[1] + steps[2] - short_steps) + made_by[1]),
+           tb * 2 * short_steps]
+    rec = [tb * (2 * visits[0] + made_by[0]), tb * (2 * (visits[1] + visits[2] - short_steps) + made_by[1]),
+           tb * 2 * short_steps]
     kern = {}
-    for i in range(2):
+    for i in range(3 if kms[2] > 0 else 2):
         per_launch = alg[i] / max(launches, 1)
         avg_s = kms[i] / 1e3 / max(launches, 1)
         ach = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
@@ -262,13 +273,13 @@ def transport_leg(E, I, workload, precision, capacity, args):
     dom = names[1] if kms[1] >= kms[0] else names[0]
     d = kern[dom]
     key = counter_key(workload, precision == E.FP64, visit, args.refill_below, args.interact_min,
-                      pvisit, prefill)
+                      pvisit, prefill, c.short_electron_MeV)
     roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["frac"], "traffic": traffic_for(dom, key),
             "kernel": dom, "bytes_per_launch": d["bytes_per_launch"], "avg_launch_us": d["avg_launch_us"],
             "launches": launches, "kernels": kern}
     # the whole step against the same peak: the method's bytes of both
-    # kernels over the wall time of a step (enqueue to tallies on the host)
+    # kernels over the wall time of a step (enqueue to tallies in device memory)
     run_b = sum(alg) / args.steps
     roof["run"] = {"bytes_per_step": run_b, "GB_per_s": run_b / (dt / args.steps) / 1e9,
                    "frac": run_b / (dt / args.steps) / 1e9 / HBM_PEAK_GBS}
@@ -277,7 +288,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
     if args.graph_check:
         cg = E.make_config(cfg, n, track_capacity=capacity, steps_per_launch=args.steps_per_launch,
                            launch_blocks=args.blocks, steps_per_visit=visit, refill_below=args.refill_below,
-                           interact_min=args.interact_min, photon_steps_per_visit=pvisit,
+                           interact_min=args.interact_min, short_electron_MeV=short_mev, photon_steps_per_visit=pvisit,
                            photon_refill_below=prefill, precision=precision)
         eng = E.Transport(cg, geo)
         one_step()
@@ -289,7 +300,7 @@ def transport_leg(E, I, workload, precision, capacity, args):
         value_graph = n * args.steps / (time.perf_counter() - t0)
         assert eng.stats()["graph_launches"] > 0
         eng.close()
-    return dict(geo=geo, cfg=cfg, prim=prim, key=key, photon_launch=[pvisit, prefill],
+    return dict(geo=geo, cfg=cfg, prim=prim, key=key, photon_launch=[pvisit, prefill], short_mev=c.short_electron_MeV,
                 value=n * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
                 value_graph=value_graph, value_host_io=value_host_io,
                 track_steps=sum(steps) // args.steps, visits=sum(visits) // args.steps, roofline=roof, edep=edep,
@@ -369,11 +380,12 @@ def kernel_source_digest(csrc=None):
     return h.hexdigest()
 
 
-def counter_key(workload, fp64, visit, refill, interact_min, photon_visit, photon_refill):
+def counter_key(workload, fp64, visit, refill, interact_min, photon_visit, photon_refill, short_mev=0.0):
     """Rows of the counter tables are keyed by workload, form and the launch
-    parameters that shape a launch's batches."""
+    parameters that shape a launch's batches (and the short-electron
+    threshold, when there is one)."""
     return (f"{workload}/{'fp64' if fp64 else 'mixed'}/v{visit}r{refill}i{interact_min}"
-            f"pv{photon_visit}pr{photon_refill}")
+            f"pv{photon_visit}pr{photon_refill}" + (f"s{short_mev:g}" if short_mev > 0 else ""))
 
 
 def counted_for(kernel, workload, name="traffic.txt"):
@@ -500,6 +512,9 @@ def main():
     ap.add_argument("--steps-per-visit", type=int, default=16, help="FP64 legs")
     ap.add_argument("--steps-per-visit-mixed", type=int, default=32, help="mixed legs")
     ap.add_argument("--refill-below", type=int, default=32)
+    ap.add_argument("--short-mev", type=float, default=None,
+                    help="e- secondaries below this energy take their first step in the short-electron launch "
+                         "(0: off; default: SHORT_MEV per workload and form)")
     ap.add_argument("--interact-min", type=int, default=24,
                     help="e-/e+ batches sample interactions once this many lanes wait for one")
     ap.add_argument("--photon-steps-per-visit", type=int, default=None,
@@ -592,7 +607,7 @@ def main():
                    "peak_live": fp["peak_live"], "deferred_steps": fp["deferred"], "capacity": args.capacity,
                    "steps_per_visit": args.steps_per_visit, "refill_below": args.refill_below,
                    "interact_min": args.interact_min, "photon_steps_per_visit": fp["photon_launch"][0],
-                   "photon_refill_below": fp["photon_launch"][1]},
+                   "photon_refill_below": fp["photon_launch"][1], "short_electron_MeV": fp["short_mev"]},
         "roofline": fp["roofline"],
         "value_graph_replay": fp["value_graph"],
         "inputs": "primaries resident in device memory, deposits left there (ems_enqueue_device, "
@@ -610,6 +625,7 @@ def main():
                         "track_steps_per_step": mx["track_steps"], "iterations": mx["iterations"],
                         "peak_live": mx["peak_live"], "deferred_steps": mx["deferred"],
                         "capacity": args.mixed_capacity, "steps_per_visit": args.steps_per_visit_mixed,
+                        "short_electron_MeV": mx["short_mev"],
                         "roofline": mx["roofline"],
                         "atomics": atomics_report(mx, mx["key"], atomic_probe(E, len(mx["prim"]) * mx["geo"].n_cols))}
         with_traffic_rate(out["mixed"]["roofline"], copy_gbs)

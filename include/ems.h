@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define EMS_ABI_VERSION 7u
+#define EMS_ABI_VERSION 8u
 
 typedef int32_t ems_status;
 enum {
@@ -197,6 +197,13 @@ typedef struct {
   uint32_t photon_refill_below;
   uint64_t exit_capacity;        /* outgoing-track records kept per run
                                     (0 = none; see ems_read_exits)          */
+  double short_electron_MeV;     /* e- secondaries below this kinetic energy
+                                    take their first step in a launch of
+                                    their own at the start of the next
+                                    iteration (most range out there); 0 =
+                                    off.  Adds two buffers of half the
+                                    track capacity and one of 5/8 of it.
+                                    Results do not depend on it             */
 } ems_config;
 
 /* One primary track (64 bytes). event is the tally row (< max_events); the
@@ -252,10 +259,13 @@ typedef struct {
                                     per visit of a thread to a track)       */
   uint64_t made_by[2];           /* secondary records written by the photon
                                     launches and by the e-/e+ launches      */
-  double kernel_ms[2];           /* with EMS_F_KERNEL_TIMING: device time of
-                                    the photon and of the e-/e+ launches,
-                                    event to event on the bound stream      */
+  double kernel_ms[3];           /* with EMS_F_KERNEL_TIMING: device time of
+                                    the photon, the e-/e+ and the short-
+                                    electron launches, event to event on
+                                    the bound stream                        */
   uint64_t graph_launches;       /* chunks replayed from a captured hipGraph */
+  uint64_t short_steps;          /* e- steps (within steps[1]) taken by the
+                                    short-electron launches                 */
 } ems_run_stats;
 
 typedef struct ems_ctx ems_ctx;

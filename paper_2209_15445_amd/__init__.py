@@ -15,9 +15,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libems.so")
 
-ABI_VERSION = 7
+ABI_VERSION = 8
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_TIMEOUT, E_VERSION = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
+# e- secondaries below this energy take their first step in the short-electron
+# launch (ems_config.short_electron_MeV; 0 turns it off), by form.  Off by
+# default: it pays off only for large e- populations in the mixed form
+SHORT_ELECTRON_MEV = {0: 0.0, 1: 0.0}
 F_STEPLOG, F_FULL_LEDGER, F_PROFILE, F_EVENT_LIVE, F_KERNEL_TIMING, F_NO_GRAPH, F_FULL_KERNELS = 1, 2, 4, 8, 16, 32, 64
 
 
@@ -62,15 +66,15 @@ class Config(C.Structure):
                 ("launch_blocks", C.c_uint32), ("steplog_capacity", C.c_uint64), ("profile_capacity", C.c_uint32),
                 ("steps_per_visit", C.c_uint32), ("refill_below", C.c_uint32), ("interact_min", C.c_uint32),
                 ("photon_steps_per_visit", C.c_uint32), ("photon_refill_below", C.c_uint32),
-                ("exit_capacity", C.c_uint64)]
+                ("exit_capacity", C.c_uint64), ("short_electron_MeV", C.c_double)]
 
 
 class RunStats(C.Structure):
     _fields_ = [("iterations", C.c_uint64), ("steps", C.c_uint64 * 3), ("created", C.c_uint64 * 3),
                 ("deferred", C.c_uint64), ("launches", C.c_uint64), ("peak_live", C.c_uint32 * 3),
                 ("steplog_overflow", C.c_uint32), ("run_ms", C.c_double), ("step_kernel_ms", C.c_double),
-                ("visits", C.c_uint64 * 3), ("made_by", C.c_uint64 * 2), ("kernel_ms", C.c_double * 2),
-                ("graph_launches", C.c_uint64)]
+                ("visits", C.c_uint64 * 3), ("made_by", C.c_uint64 * 2), ("kernel_ms", C.c_double * 3),
+                ("graph_launches", C.c_uint64), ("short_steps", C.c_uint64)]
 
 
 class LoadRequest(C.Structure):
@@ -196,12 +200,14 @@ class _GeoHolder:
 
 def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0, steps_per_launch=16,
                 launch_blocks=0, steplog_capacity=0, profile_capacity=0, steps_per_visit=16, refill_below=32,
-                interact_min=24, exit_capacity=0, photon_steps_per_visit=None, photon_refill_below=None):
+                interact_min=24, exit_capacity=0, photon_steps_per_visit=None, photon_refill_below=None,
+                short_electron_MeV=None):
     """Config struct from a run description (any object with the physics
     fields: bz_tesla, cuts, grid, step function, mask, watchdog, seed).  The
-    launch parameters (steps_per_visit, refill_below, interact_min and the
-    photon kernel's photon_steps_per_visit and photon_refill_below) shape
-    the kernels' batches and change no result."""
+    launch parameters (steps_per_visit, refill_below, interact_min, the
+    photon kernel's photon_steps_per_visit and photon_refill_below, and the
+    short-electron threshold short_electron_MeV) shape the kernels' work and
+    change no result."""
     c = Config()
     c.abi_version = ABI_VERSION
     c.precision = precision
@@ -223,6 +229,7 @@ def make_config(run, max_events, track_capacity=1 << 20, precision=FP64, flags=0
     c.photon_steps_per_visit = steps_per_visit if photon_steps_per_visit is None else photon_steps_per_visit
     c.photon_refill_below = refill_below if photon_refill_below is None else photon_refill_below
     c.exit_capacity = exit_capacity
+    c.short_electron_MeV = SHORT_ELECTRON_MEV[precision] if short_electron_MeV is None else short_electron_MeV
     return c
 
 
@@ -407,7 +414,8 @@ class Transport:
         return dict(iterations=s.iterations, steps=list(s.steps), created=list(s.created), deferred=s.deferred,
                     launches=s.launches, peak_live=list(s.peak_live), steplog_overflow=s.steplog_overflow,
                     run_ms=s.run_ms, step_kernel_ms=s.step_kernel_ms, visits=list(s.visits),
-                    made_by=list(s.made_by), kernel_ms=list(s.kernel_ms), graph_launches=s.graph_launches)
+                    made_by=list(s.made_by), kernel_ms=list(s.kernel_ms), graph_launches=s.graph_launches,
+                    short_steps=s.short_steps)
 
 
 def probe_atomics(cells, n_ops, stream=None):

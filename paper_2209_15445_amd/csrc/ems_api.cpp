@@ -159,6 +159,8 @@ ems_status check_inputs(const ems_config* c, const ems_geometry* g) {
     return fail(EMS_E_INVALID, "photon_steps_per_visit in [1, 1024]");
   if (c->photon_refill_below > 63) return fail(EMS_E_INVALID, "photon_refill_below in [0, 63]");
   if (c->exit_capacity > (1ull << 32)) return fail(EMS_E_INVALID, "exit_capacity above 2^32");
+  if (!(c->short_electron_MeV >= 0.0) || !isfinite(c->short_electron_MeV))
+    return fail(EMS_E_INVALID, "short_electron_MeV must be finite and >= 0");
   if (c->track_capacity < 64 || c->track_capacity > (1ull << 28))
     return fail(EMS_E_INVALID, "track_capacity must be in [64, 2^28]");
   return EMS_OK;
@@ -224,6 +226,11 @@ Layout plan(const ems_config* c, const ems_geometry* g, uint32_t inj_chunk = kIn
   L.drow = take((uint64_t)c->max_events * 8);
   L.dchk = take(4 * 8);
   L.queues = take(6 * L.cap * queue_track_bytes(c));
+  // short electrons: two buffers of half the queue capacity and a spill
+  // buffer a quarter larger (room for the unused ends of append chunks)
+  L.cap_s = c->short_electron_MeV > 0.0 ? (L.cap / 2 + 63) / 64 * 64 : 0;
+  L.cap_p = L.cap_s + L.cap_s / 4;
+  L.squeues = take((2 * L.cap_s + L.cap_p) * queue_track_bytes(c));
   L.total = o;
   return L;
 }
@@ -598,6 +605,10 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
 
   KArgs& a = c->args;
   a.qbase = c->ws + L.queues;
+  a.sbase = c->ws + L.squeues;
+  a.cap_s = L.cap_s;
+  a.cap_p = L.cap_p;
+  a.short_E = cfg->short_electron_MeV;
   a.ctl = reinterpret_cast<Ctl*>(c->ws + L.ctl);
   a.edep = reinterpret_cast<double*>(c->ws + L.edep);
   a.ledger = reinterpret_cast<LedgerDev*>(c->ws + L.ledger);
@@ -639,10 +650,16 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
                           (cfg->process_mask & EMS_P_MSC ? kFMsc : 0) | (cfg->process_mask & EMS_P_FLUCT ? kFFluct : 0) |
                           (compound ? kFCompound : 0) | (record ? kFRecord : 0);
   const uint32_t need_g = (compound ? kFCompound : 0) | (record ? kFRecord : 0);
+  constexpr uint32_t kAllParts = kFAll & ~kFShort;
   a.feat_l = need_l == 0 ? 0u
              : (geo->n_boxes == 0 && (need_l & ~(uint32_t)(kFField | kFRecord)) == 0) ? (uint32_t)(kFField | kFRecord)
-                                                                                      : (uint32_t)kFAll;
-  a.feat_g = need_g == 0 ? 0u : (uint32_t)kFAll;
+                                                                                      : kAllParts;
+  a.feat_g = need_g == 0 ? 0u : kAllParts;
+  // the short-electron routing is compiled into variants of its own
+  if (L.cap_s) {
+    a.feat_g |= kFShort;
+    a.feat_l |= kFShort;
+  }
   if (cfg->flags & EMS_F_FULL_KERNELS) a.feat_g = a.feat_l = kFAll;
   if (geo->n_boxes) {
     // device view of the hierarchy (same layout as the host one)
@@ -654,15 +671,17 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
     a.env.nav.nbr_off = reinterpret_cast<const uint32_t*>(c->ws + L.nbr_off);
     a.env.nav.nbr = reinterpret_cast<const uint32_t*>(c->ws + L.nbr);
   }
-  int per_g = 0, per_l = 0;
-  if (visit_occupancy(a, &per_g, &per_l) != hipSuccess || per_g < 1 || per_l < 1)
+  int per_g = 0, per_l = 0, per_s = 0;
+  if (visit_occupancy(a, &per_g, &per_l, &per_s) != hipSuccess || per_g < 1 || per_l < 1 || per_s < 1)
     return bad(fail(EMS_E_DEVICE, "cannot configure the visit kernels"));
   // one resident wave of blocks per launch; blocks grid-stride over the queue
   const uint32_t cus = (uint32_t)prop.multiProcessorCount;
   c->blocks_g = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_g;
   c->blocks_l = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_l;
+  c->blocks_s = cfg->launch_blocks ? cfg->launch_blocks : cus * (uint32_t)per_s;
   a.waves_g = c->blocks_g * 4;  // 256-thread blocks of 64-lane waves
   a.waves_l = c->blocks_l * 4;
+  a.waves_s = c->blocks_s * 4;
 
   if (no_alloc) {
     // ordinary host memory for the staging and the status block; no events,
@@ -721,6 +740,7 @@ ems_status rt_create(const ems_config* cfg, const ems_geometry* geo, void* d_ws,
             hipMemcpyAsync(c->ws + L.elem, elem.data(), elem.size(), hipMemcpyHostToDevice, s) == hipSuccess &&
             launch_fill_zero(c->ws + L.edep, (L.live - L.edep) + (uint64_t)cfg->max_events * 4, s) == hipSuccess &&
             launch_fill_zero(c->ws + L.queues, 6 * L.cap * queue_track_bytes(cfg), s) == hipSuccess &&
+            launch_fill_zero(c->ws + L.squeues, (2 * L.cap_s + L.cap_p) * queue_track_bytes(cfg), s) == hipSuccess &&
             launch_fill_zero(c->ws + L.drow, (uint64_t)cfg->max_events * 8, s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -862,6 +882,8 @@ ems_status ems_reset_tallies(ems_ctx* c) {
     fresh.n_sec[s] = c->pin_ctl->n_sec[s];
     fresh.n_real[s] = c->pin_ctl->n_real[s];
   }
+  fresh.n_short = c->pin_ctl->n_short;
+  fresh.n_short_real = c->pin_ctl->n_short_real;
   *c->pin_ctl = fresh;
   HIPCHK(c, hipMemcpyAsync(c->ws + L.ctl, c->pin_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1151,10 +1173,12 @@ static hipError_t enqueue_chunk(ems_ctx* c, uint32_t K, bool timing) {
   hipError_t e = launch_census(c->args, c->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(c->evk[0], c->stream);
   for (uint32_t k = 0; k < K && e == hipSuccess; ++k) {
-    e = launch_visit(c->args, true, c->blocks_g, c->stream);
-    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[2 * k + 1], c->stream);
+    if (c->args.cap_s) e = launch_short(c->args, c->blocks_s, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[3 * k + 1], c->stream);
+    if (e == hipSuccess) e = launch_visit(c->args, true, c->blocks_g, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[3 * k + 2], c->stream);
     if (e == hipSuccess) e = launch_visit(c->args, false, c->blocks_l, c->stream);
-    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[2 * k + 2], c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->evk[3 * k + 3], c->stream);
   }
   return e;
 }
@@ -1178,7 +1202,7 @@ static hipError_t capture_chunk(ems_ctx* c, uint32_t K) {
 
 ems_status rt_chunk(ems_ctx* c, uint32_t K) {
   const bool timing = (c->cfg.flags & EMS_F_KERNEL_TIMING) != 0;
-  while (timing && c->evk.size() < 2 * (size_t)K + 1) {
+  while (timing && c->evk.size() < 3 * (size_t)K + 1) {
     hipEvent_t e = nullptr;
     HIPCHK(c, hipEventCreate(&e));
     c->evk.push_back(e);
@@ -1211,11 +1235,13 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
   ems_run_stats& st = c->stats;
   st.step_kernel_ms += ms;
   for (uint32_t k = 0; timing && k < K; ++k) {
-    float a = 0.0f, b = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&a, c->evk[2 * k], c->evk[2 * k + 1]));
-    HIPCHK(c, hipEventElapsedTime(&b, c->evk[2 * k + 1], c->evk[2 * k + 2]));
+    float a = 0.0f, b = 0.0f, d = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&d, c->evk[3 * k], c->evk[3 * k + 1]));
+    HIPCHK(c, hipEventElapsedTime(&a, c->evk[3 * k + 1], c->evk[3 * k + 2]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->evk[3 * k + 2], c->evk[3 * k + 3]));
     st.kernel_ms[0] += a;
     st.kernel_ms[1] += b;
+    st.kernel_ms[2] += d;
   }
   st.made_by[0] = s.made_by[0];
   st.made_by[1] = s.made_by[1];
@@ -1228,6 +1254,7 @@ ems_status rt_chunk(ems_ctx* c, uint32_t K) {
     st.peak_live[i] = s.peak[i];
   }
   st.deferred = s.deferred;
+  st.short_steps = s.steps_s;
   st.steplog_overflow = (c->args.log_cap && s.log_n > c->args.log_cap) ? 1u : 0u;
   if (s.error & kErrOverflow) {
     c->failed = true;

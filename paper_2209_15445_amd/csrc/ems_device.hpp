@@ -79,6 +79,12 @@ struct Ctl {
   uint32_t n_real[3];
   uint32_t next_real[3];
   unsigned long long exit_n;  // outgoing tracks recorded (may exceed the capacity)
+  // Short electrons (KArgs::short_E): extent and live records of the
+  // current short buffer, append counters of the next one, the spill
+  // buffer's extent (tracks the short launch hands to this iteration's
+  // e-/e+ launch) and the short launch's cursor.
+  uint32_t n_short, n_short_real, next_short, next_short_real, n_spill, cursor_s;
+  unsigned long long steps_s;  // e- steps taken by the short launches
 };
 enum : uint32_t { kErrOverflow = 1u, kErrStall = 2u, kErrCorrupt = 4u };
 
@@ -150,6 +156,22 @@ struct KArgs {
   uint32_t feat_g, feat_l;    // optional parts (kF* bits) of the photon and e-/e+ kernels launched
   uint32_t vol_bits;          // low bits of the packed word that hold the volume
   StepEnv<double> env;  // scalars; its pointers are set per block
+  // Short electrons: e- secondaries below short_E (0: none) are appended to
+  // a buffer of their own (two of cap_s records, current and next) and take
+  // their first step in a launch of their own at the start of the next
+  // iteration; a track whose first step selects an interaction goes to the
+  // spill buffer (cap_p records) for the e-/e+ launch of that iteration.
+  char* sbase;                // the two short buffers, then the spill buffer
+  uint64_t cap_s, cap_p;
+  double short_E;
+  uint32_t waves_s;           // waves of the short launch
 };
+
+// short buffer b (0/1) and the spill buffer (b = 2), laid out as queues
+template <class R>
+EMS_HD Queue<R> short_view(const KArgs& a, uint32_t b) {
+  char* base = a.sbase + (size_t)b * a.cap_s * track_bytes<R>();
+  return queue_view<R>(base, b == 2 ? a.cap_p : a.cap_s, 0, 0);
+}
 
 }  // namespace ems

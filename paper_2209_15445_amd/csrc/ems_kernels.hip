@@ -139,20 +139,60 @@ __device__ inline uint32_t slot_of(const Take& tk, uint32_t x) {
 #endif
 struct Plan {
   uint32_t lim[3], chunk[3];
+  uint32_t lim_s, chunk_s;  // appends to the next short buffer
 };
-__device__ inline Plan append_plan(const KArgs& a, uint32_t n0, uint32_t n1, uint32_t n2) {
+// The current short electrons (ns) may all survive their first step into
+// the next e- queue, so they count with the current e- tracks; the short
+// launch's waves also append to that queue's home region.  New short
+// electrons are e- of the next iteration as well: the e- secondary limit is
+// shared, half of it (at most the short buffer's capacity) for the short
+// buffer, so that the next iteration's e- and short electrons together
+// again leave room for all their survivors.  The short buffer takes the e-
+// chunk, bounded so that all waves together leave unused at most a quarter
+// of its capacity.
+// SHORT: the kernel variant routes short electrons (the plan is the same
+// as without when the context has no short buffers).
+template <bool SHORT>
+__device__ inline Plan append_plan(const KArgs& a, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t ns) {
   Plan p;
+  if constexpr (!SHORT) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint64_t n = q == 0 ? n0 : (q == 1 ? n1 : n2);
+      const uint64_t room = a.cap - n;
+      const uint64_t waves = (uint64_t)a.waves_g + a.waves_l;
+      const uint64_t budget = (n < room ? n : room) / 4;
+      uint32_t chunk = EMS_APPEND_CHUNK;
+      while (chunk > 1 && waves * chunk > budget) chunk >>= 1;
+      const uint64_t home_waves = q == 0 ? a.waves_g : a.waves_l;
+      p.chunk[q] = chunk;
+      p.lim[q] = (uint32_t)(room - (chunk > 1 ? home_waves * chunk : 0));  // slack <= room / 4
+    }
+    p.lim_s = 0;
+    p.chunk_s = 1;
+    return p;
+  }
+  const uint64_t waves = (uint64_t)a.waves_g + a.waves_l + (a.cap_s ? a.waves_s : 0u);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const uint64_t n = q == 0 ? n0 : (q == 1 ? n1 : n2);
-    const uint64_t room = a.cap - n;
-    const uint64_t waves = (uint64_t)a.waves_g + a.waves_l;
+    const uint64_t n = q == 0 ? n0 : (q == 1 ? (uint64_t)n1 + ns : n2);
+    const uint64_t room = n < a.cap ? a.cap - n : 0;
     const uint64_t budget = (n < room ? n : room) / 4;
     uint32_t chunk = EMS_APPEND_CHUNK;
     while (chunk > 1 && waves * chunk > budget) chunk >>= 1;
-    const uint64_t home_waves = q == 0 ? a.waves_g : a.waves_l;
+    const uint64_t home_waves = q == 0 ? a.waves_g : (q == 1 && a.cap_s ? a.waves_l + a.waves_s : a.waves_l);
+    const uint64_t slack = chunk > 1 ? home_waves * chunk : 0;
     p.chunk[q] = chunk;
-    p.lim[q] = (uint32_t)(room - (chunk > 1 ? home_waves * chunk : 0));
+    p.lim[q] = (uint32_t)(room > slack ? room - slack : 0);
+  }
+  uint32_t cs = p.chunk[1];
+  while (cs > 1 && waves * cs > a.cap_s / 4) cs >>= 1;
+  p.chunk_s = cs;
+  p.lim_s = 0;
+  if (a.cap_s) {
+    const uint32_t half = p.lim[1] / 2;
+    p.lim_s = (uint64_t)half < a.cap_s ? half : (uint32_t)a.cap_s;
+    p.lim[1] -= p.lim_s;
   }
   return p;
 }
@@ -388,7 +428,12 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
   const uint32_t cur = ctl->cur;
   const uint32_t h0 = ctl->n_home[0], h1 = ctl->n_home[1], h2 = ctl->n_home[2];
   const uint32_t n0 = h0 + ctl->n_sec[0], n1 = h1 + ctl->n_sec[1], n2 = h2 + ctl->n_sec[2];
-  const uint32_t nmine = PHOTONS ? n0 : n1 + n2;
+  constexpr bool kShort = (F & kFShort) != 0;
+  const uint32_t ns = kShort ? ctl->n_short : 0u;
+  // the e-/e+ launch also takes the tracks the short launch spilled
+  const uint32_t np_raw = (PHOTONS || !(F & kFShort)) ? 0u : ctl->n_spill;
+  const uint32_t np = (uint64_t)np_raw < a.cap_p ? np_raw : (uint32_t)a.cap_p;
+  const uint32_t nmine = PHOTONS ? n0 : n1 + n2 + np;
   const uint32_t need = (nmine + kBlock - 1) / kBlock;
   const bool work = blockIdx.x < need && ctl->error == 0;
   constexpr int KIND = PHOTONS ? 0 : 1;
@@ -399,10 +444,14 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     const int max_visit = (int)(PHOTONS ? a.photon_steps_per_visit : a.steps_per_visit);
     const uint32_t refill_below = PHOTONS ? a.photon_refill_below : a.refill_below;
     // secondary slots per species that leave room for all survivors
-    const Plan plan = append_plan(a, n0, n1, n2);
+    const Plan plan = append_plan<kShort>(a, n0, n1, n2, ns);
     const uint32_t lim0 = plan.lim[0], lim1 = plan.lim[1], lim2 = plan.lim[2];
-    // wave-private append ranges (uniform): secondaries and home, per species
+    // wave-private append ranges (uniform): secondaries and home, per
+    // species, and the next short buffer
     uint32_t slo[3] = {0, 0, 0}, shi[3] = {0, 0, 0}, hlo[3] = {0, 0, 0}, hhi[3] = {0, 0, 0};
+    uint32_t sslo = 0, sshi = 0;
+    // short-electron routing: compiled into the kFShort variants only
+    const bool shorts = kShort && a.cap_s != 0;
     DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
                  (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0, 0.0,
                  a.exits, a.exit_cap};
@@ -420,7 +469,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     StepOut<R> o;
     o.nsec = 0;
     uint32_t visits_e = 0, visits_p = 0, steps_e = 0, steps_p = 0, carried_n = 0;
-    uint32_t made0 = 0, made1 = 0, made2 = 0;
+    uint32_t made0 = 0, made1 = 0, made2 = 0, made_s = 0;
     uint32_t kept_a = 0, kept_b = 0;  // home records written (own species; e+)
     // Box geometries: a step that starts in the world volume needs the
     // nearest box along the track, a walk of the hierarchy that costs the
@@ -483,8 +532,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
               idx = i - n1;
               home = h2;
             }
-            const uint32_t pos = queue_pos(idx, home, a.cap);
-            const Queue<R> src = queue_view<R>(a.qbase, a.cap, cur, (uint32_t)nsp);
+            const bool spilled = !PHOTONS && (F & kFShort) && i >= n1 + n2;  // an e- from the spill buffer
+            if (spilled) nsp = 1;
+            const uint32_t pos = spilled ? i - n1 - n2 : queue_pos(idx, home, a.cap);
+            const Queue<R> src = spilled ? short_view<R>(a, 2u) : queue_view<R>(a.qbase, a.cap, cur, (uint32_t)nsp);
             nw = src.ns[pos];
             nt.ev = src.ev[pos];
             nt.key = src.key[pos];
@@ -518,10 +569,15 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
         if (__ballot(done) != 0) {
           // secondaries into the top regions (a step commits only if all of
           // its secondaries fit), then survivors or carried tracks
+          // e- secondaries below short_E go to the next short buffer
+          const bool s0 = shorts && done && o.nsec > 0 && o.sec[0].sp == kElectron && o.sec[0].E < a.short_E;
+          const bool s1 = shorts && done && o.nsec > 1 && o.sec[1].sp == kElectron && o.sec[1].E < a.short_E;
           uint32_t d[3];
 #pragma unroll
           for (int q = 0; q < 3; ++q)
-            d[q] = (done && o.nsec > 0 && o.sec[0].sp == q ? 1u : 0u) + (done && o.nsec > 1 && o.sec[1].sp == q ? 1u : 0u);
+            d[q] = (done && o.nsec > 0 && o.sec[0].sp == q && !s0 ? 1u : 0u) +
+                   (done && o.nsec > 1 && o.sec[1].sp == q && !s1 ? 1u : 0u);
+          const uint32_t ds = (s0 ? 1u : 0u) + (s1 ? 1u : 0u);
           uint32_t slot[3];
           Take tk[3];
           bool fits = true;
@@ -531,6 +587,13 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
             const uint32_t lim = q == 0 ? lim0 : (q == 1 ? lim1 : lim2);
             if (d[q] && slot_of(tk[q], slot[q] + d[q] - 1) >= lim) fits = false;
             if (d[q] > 1 && slot_of(tk[q], slot[q]) >= lim) fits = false;
+          }
+          uint32_t slot_s = 0;
+          Take tks{0, 0, 0};
+          if (shorts) {
+            slot_s = take_slots(&ctl->next_short, ds, plan.chunk_s, sslo, sshi, tks);
+            if (ds && slot_of(tks, slot_s + ds - 1) >= plan.lim_s) fits = false;
+            if (ds > 1 && slot_of(tks, slot_s) >= plan.lim_s) fits = false;
           }
           const bool pending = done && o.nsec > 0;
           const bool commit = pending && fits;
@@ -555,12 +618,13 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
             made0 += d[0];
             made1 += d[1];
             made2 += d[2];
+            made_s += ds;
           }
           if (carry) ++carried_n;
           if (done && track_live) {
             // net change of the event's live tracks: the visited track ends
             // or stays, committed secondaries join
-            const int delta = (alive ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2]) : 0) - 1;
+            const int delta = (alive ? 1 : 0) + (commit ? (int)(d[0] + d[1] + d[2] + ds) : 0) - 1;
             if (delta != 0) atomicAdd(&a.live_ev[t.ev], delta);
           }
 #pragma unroll
@@ -592,6 +656,36 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
                   store_track(dq, ps, c, a.vol_bits);
                 } else {
                   dq.ns[ps] = kDeadRecord;  // refused: the next iteration skips this slot
+                }
+              }
+              ++x;
+            }
+          }
+          if (ds) {
+            const Queue<R> sq = short_view<R>(a, nxt);
+            uint32_t x = slot_s;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              if (!(k == 0 ? s0 : s1)) continue;
+              const uint32_t sl = slot_of(tks, x);
+              if (sl < plan.lim_s) {
+                if (commit) {
+                  Trk<R> c;
+                  c.x = t.x;
+                  c.y = t.y;
+                  c.z = t.z;
+                  c.ux = o.sec[k].ux;
+                  c.uy = o.sec[k].uy;
+                  c.uz = o.sec[k].uz;
+                  c.E = o.sec[k].E;
+                  c.id = o.sec[k].id;
+                  c.ev = t.ev;
+                  c.key = t.key;
+                  c.n = 0;
+                  c.slab = o.slab;
+                  store_track(sq, sl, c, a.vol_bits);
+                } else {
+                  sq.ns[sl] = kDeadRecord;
                 }
               }
               ++x;
@@ -675,6 +769,11 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
         if (x < a.cap) dq.ns[x] = kDeadRecord;
       }
     }
+    if (shorts) {
+      const Queue<R> sq = short_view<R>(a, nxt);
+      const uint32_t send = sshi < plan.lim_s ? sshi : plan.lim_s;
+      for (uint32_t x = sslo + __lane_id(); x < send; x += 64) sq.ns[x] = kDeadRecord;
+    }
     // statistics and per-launch progress
     if (PHOTONS) {
       wave_count(&ctl->steps[0], steps_e);
@@ -687,9 +786,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     }
     wave_count(&ctl->deferred, carried_n);
     wave_count(&ctl->created[0], made0);
-    wave_count(&ctl->created[1], made1);
+    wave_count(&ctl->created[1], made1 + made_s);
     wave_count(&ctl->created[2], made2);
-    wave_count(&ctl->made_by[PHOTONS ? 0 : 1], made0 + made1 + made2);
+    wave_count(&ctl->made_by[PHOTONS ? 0 : 1], made0 + made1 + made2 + made_s);
+    if (shorts) wave_count(&ctl->next_short_real, made_s);
     wave_count(&ctl->next_real[0], made0 + (PHOTONS ? kept_a : 0u));
     wave_count(&ctl->next_real[1], made1 + (PHOTONS ? 0u : kept_a));
     wave_count(&ctl->next_real[2], made2 + kept_b);
@@ -713,7 +813,7 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
   __syncthreads();
   if (last && threadIdx.x == 0) {
     __threadfence();
-    const uint32_t r0 = ctl->n_real[0], r1 = ctl->n_real[1], r2 = ctl->n_real[2];
+    const uint32_t r0 = ctl->n_real[0], r1 = ctl->n_real[1] + (kShort ? ctl->n_short_real : 0u), r2 = ctl->n_real[2];
     if (a.flags & kFlagProfile) {
       if (ctl->iteration < a.profile_cap) {
         a.profile[(size_t)ctl->iteration * 3 + 0] = r0;
@@ -724,9 +824,10 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     if (r0 + r1 + r2 > 0) ctl->iteration += 1;
     const uint32_t commits = atomicAdd(&ctl->commits, 0u), carried = atomicAdd(&ctl->carried, 0u);
     if (carried > 0 && commits == 0) ctl->error |= kErrStall;  // nothing can move: queues too small
-    uint32_t live = 0;
+    const uint32_t srv = kShort ? atomicAdd(&ctl->next_short_real, 0u) : 0u;
+    uint32_t live = srv;
     for (int q = 0; q < 3; ++q) live += atomicAdd(&ctl->next_real[q], 0u);
-    const Plan plan = append_plan(a, n0, n1, n2);
+    const Plan plan = append_plan<kShort>(a, n0, n1, n2, ns);
     for (int q = 0; q < 3; ++q) {
       const uint32_t lim = plan.lim[q];
       const uint32_t hv = atomicAdd(&ctl->next_home[q], 0u);
@@ -742,6 +843,17 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
       ctl->next_real[q] = 0;
       ctl->peak[q] = rv > ctl->peak[q] ? rv : ctl->peak[q];
     }
+    if constexpr (kShort) {
+      // the next short buffer becomes the current one
+      const uint32_t sv = atomicAdd(&ctl->next_short, 0u);
+      ctl->n_short = live ? (sv < plan.lim_s ? sv : plan.lim_s) : 0u;
+      ctl->n_short_real = srv;
+      ctl->next_short = 0;
+      ctl->next_short_real = 0;
+      ctl->n_spill = 0;
+      ctl->cursor_s = 0;
+      ctl->peak[1] = ctl->n_real[1] + srv > ctl->peak[1] ? ctl->n_real[1] + srv : ctl->peak[1];
+    }
     ctl->live = live;
     ctl->commits = 0;
     ctl->carried = 0;
@@ -751,6 +863,143 @@ __global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_vi
     ctl->blocks_done = 0;
     __threadfence();
   }
+}
+
+// Short electrons.  Most e- secondaries of a shower are slow (Compton and
+// photo-electrons, delta rays) and end in their first step, ranged out.
+// In the e-/e+ launch each of them costs a lane a record load, one step and
+// a commit in a wave whose other lanes follow long tracks; here a launch of
+// its own, at the start of the iteration, gives every lane one such track:
+// one step, its tallies, and the survivor (if any) appended to the next e-
+// queue as any e-/e+ survivor.  A track whose first step selects a discrete
+// interaction is handed unchanged to this iteration's e-/e+ launch (spill
+// buffer), which takes the same step again and samples the interaction
+// there: every step still draws from its own (id, step) stream, so results
+// and the iteration of every step are those of the e-/e+ launch.
+// (without optional parts the step and a prefetched record fit 3 resident
+// waves per SIMD in FP64, 5 in FP32; with them 3 and 4; in box geometries
+// 2 and 3)
+#ifndef EMS_WAVES_F64_SHORT
+#define EMS_WAVES_F64_SHORT 3
+#endif
+#ifndef EMS_WAVES_F32_SHORT
+#define EMS_WAVES_F32_SHORT 5
+#endif
+template <class R, int GEO, int F>
+constexpr int short_waves() {
+  if (GEO == 1) return sizeof(R) == 8 ? 2 : 3;  // box navigation needs more registers
+  return sizeof(R) == 8 ? (F == 0 ? EMS_WAVES_F64_SHORT : 3) : (F == 0 ? EMS_WAVES_F32_SHORT : 4);
+}
+template <class R, int GEO, int F>
+__global__ __launch_bounds__(kBlock, (short_waves<R, GEO, F>())) void k_short(KArgs a) {
+  extern __shared__ double lds_words[];
+  char* lds = reinterpret_cast<char*>(lds_words);
+  Ctl* ctl = a.ctl;
+  const uint32_t cur = ctl->cur;
+  const uint32_t ns = ctl->n_short;
+  if (blockIdx.x >= (ns + kBlock - 1) / kBlock || ctl->error != 0) return;
+  const uint32_t n0 = ctl->n_home[0] + ctl->n_sec[0], n1 = ctl->n_home[1] + ctl->n_sec[1];
+  const uint32_t n2 = ctl->n_home[2] + ctl->n_sec[2];
+  const StepEnv<R> env = stage<R, GEO>(a, lds, false);
+  const Plan plan = append_plan<true>(a, n0, n1, n2, ns);
+  DevSink sink{a.edep, a.ledger, ctl, a.log, a.log_cap, a.env.n_slabs,
+               (a.flags & kFlagFullLedger) != 0, (a.flags & kFlagSteplog) != 0, 0, 0.0,
+               a.exits, a.exit_cap};
+  const bool track_live = (F & kFRecord) && (a.flags & kFlagEventLive) != 0;
+  const Queue<R> src = short_view<R>(a, cur);
+  const Queue<R> spill = short_view<R>(a, 2u);
+  const Queue<R> dst = queue_view<R>(a.qbase, a.cap, cur ^ 1u, (uint32_t)kElectron);
+  // wave-private append ranges (uniform): next e- home, spill buffer
+  uint32_t hlo = 0, hhi = 0, plo = 0, phi = 0;
+  // spill appends: all waves' unused chunk ends fit in the spill buffer's
+  // room beyond cap_s (at most ns <= cap_s tracks spill)
+  uint32_t chunk_p = plan.chunk[1] < 64u ? plan.chunk[1] : 64u;
+  while (chunk_p > 1 && (uint64_t)a.waves_s * chunk_p > a.cap_p - a.cap_s) chunk_p >>= 1;
+  uint32_t steps = 0, loads = 0, kept = 0;
+  // the record of the lane's next track is loaded while the current one
+  // steps (the step reads only LDS, so nothing waits for those loads early)
+  auto load = [&](uint32_t i, Trk<R>& t, uint32_t& w) {
+    w = kDeadRecord;
+    if (i < ns) {
+      w = src.ns[i];
+      t.x = src.x[i];
+      t.y = src.y[i];
+      t.z = src.z[i];
+      t.ux = src.ux[i];
+      t.uy = src.uy[i];
+      t.uz = src.uz[i];
+      t.E = src.E[i];
+      t.id = src.id[i];
+      t.ev = src.ev[i];
+      t.key = src.key[i];
+    }
+  };
+  const uint32_t stride = gridDim.x * kBlock;
+  Trk<R> t;
+  uint32_t w;
+  load(blockIdx.x * kBlock + threadIdx.x, t, w);
+  for (uint32_t base = blockIdx.x * kBlock; base < ns; base += stride) {
+    Trk<R> tn;
+    uint32_t wn;
+    load(base + stride + threadIdx.x, tn, wn);
+    bool has = w != kDeadRecord;
+    t.slab = (int32_t)(w & ((1u << a.vol_bits) - 1u));
+    t.n = w >> a.vol_bits;
+    if (has && (t.slab >= (int32_t)a.env.n_slabs || t.ev >= a.max_events)) {
+      atomicOr(&ctl->error, kErrCorrupt);
+      has = false;
+    }
+    const Trk<R> first = t;
+    StepOut<R> o;
+    o.nsec = 0;
+    bool to_spill = false, alive = false;
+    if (has) {
+      ++loads;
+      clear_out(t, o);
+      lepton_step<R, GEO, F>(env, false, t, o);
+      if (o.pending) {
+        to_spill = true;
+      } else {
+        watchdog(env, t, o);
+        sink.apply<F>(kElectron, t, o, first.E);
+        ++steps;
+        alive = t.slab >= 0;
+        if (track_live && !alive) atomicAdd(&a.live_ev[t.ev], -1);
+      }
+    }
+    Take th, tp;
+    const uint32_t hx = take_slots(&ctl->next_home[1], alive ? 1u : 0u, plan.chunk[1], hlo, hhi, th);
+    const uint32_t px = take_slots(&ctl->n_spill, to_spill ? 1u : 0u, chunk_p, plo, phi, tp);
+    if (alive) {
+      const uint32_t hs = slot_of(th, hx);
+      if (hs >= a.cap) {
+        atomicOr(&ctl->error, kErrOverflow);
+      } else {
+        store_track(dst, hs, t, a.vol_bits);
+        ++kept;
+      }
+    }
+    if (to_spill) {
+      const uint32_t ps = slot_of(tp, px);
+      if (ps >= a.cap_p) atomicOr(&ctl->error, kErrOverflow);
+      else store_track(spill, ps, first, a.vol_bits);
+    }
+    t = tn;
+    w = wn;
+  }
+  sink.flush();
+  for (uint32_t x = hlo + __lane_id(); x < hhi; x += 64) {
+    if (x < a.cap) dst.ns[x] = kDeadRecord;
+  }
+  for (uint32_t x = plo + __lane_id(); x < phi; x += 64) {
+    if (x < a.cap_p) spill.ns[x] = kDeadRecord;
+  }
+  wave_count(&ctl->steps[1], steps);
+  wave_count(&ctl->steps_s, steps);
+  wave_count(&ctl->visits[1], loads);
+  wave_count(&ctl->next_real[1], kept);
+  const uint32_t c = wave_sum(steps);
+  if (__lane_id() == 0 && c) atomicAdd(&ctl->commits, c);
 }
 
 // Zero `words` 8-byte words at p and then `ntail` single bytes at tail, with
@@ -851,11 +1100,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows(KArgs a, const uint32_t*
 __global__ void k_census(KArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Ctl* c = a.ctl;
-    uint32_t live = 0;
+    uint32_t live = c->n_short_real;
     for (int q = 0; q < 3; ++q) {
-      const uint32_t n = c->n_real[q];
+      const uint32_t n = c->n_real[q] + (q == 1 ? c->n_short_real : 0u);
       c->peak[q] = n > c->peak[q] ? n : c->peak[q];
-      live += n;
+      live += c->n_real[q];
     }
     c->live = live;
   }
@@ -870,43 +1119,47 @@ __global__ void k_census(KArgs a) {
 template <bool PHOTONS, class R, int GEO>
 const void* visit_fn(uint32_t feat) {
   if (feat == 0) return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, 0>);
+  if (feat == kFShort) return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFShort>);
   if constexpr (!PHOTONS && GEO == 0) {
     if (feat == (kFField | kFRecord))
       return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFField | kFRecord>);
+    if (feat == (kFField | kFRecord | kFShort))
+      return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFField | kFRecord | kFShort>);
   }
+  if (feat == (kFAll & ~kFShort)) return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFAll & ~kFShort>);
   return reinterpret_cast<const void*>(&k_visit<PHOTONS, R, GEO, kFAll>);
 }
-template <bool PHOTONS, class R, int GEO>
-void launch_visit_v(const KArgs& a, uint32_t blocks, hipStream_t s) {
-  const uint32_t lds = PHOTONS ? a.lds_g : a.lds_l;
-  const uint32_t feat = PHOTONS ? a.feat_g : a.feat_l;
-  if (feat == 0) {
-    hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, 0>), dim3(blocks), dim3(kBlock), lds, s, a);
-    return;
+// the short launch takes the e-/e+ launch's optional parts (its own work is
+// the short path, so the routing bit does not apply to it)
+template <class R, int GEO>
+const void* short_fn(uint32_t feat) {
+  feat &= ~(uint32_t)kFShort;
+  if (feat == 0) return reinterpret_cast<const void*>(&k_short<R, GEO, 0>);
+  if constexpr (GEO == 0) {
+    if (feat == (kFField | kFRecord)) return reinterpret_cast<const void*>(&k_short<R, GEO, kFField | kFRecord>);
   }
-  if constexpr (!PHOTONS && GEO == 0) {
-    if (feat == (kFField | kFRecord)) {
-      hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, kFField | kFRecord>), dim3(blocks), dim3(kBlock), lds, s, a);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_visit<PHOTONS, R, GEO, kFAll>), dim3(blocks), dim3(kBlock), lds, s, a);
+  return reinterpret_cast<const void*>(&k_short<R, GEO, kFAll>);
 }
-// one iteration is the photon launch followed by the e-/e+ launch
-template <int GEO>
-void launch_visit_g(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
-  if (photons) {
-    if (a.precision) launch_visit_v<true, float, GEO>(a, blocks, s);
-    else launch_visit_v<true, double, GEO>(a, blocks, s);
-  } else {
-    if (a.precision) launch_visit_v<false, float, GEO>(a, blocks, s);
-    else launch_visit_v<false, double, GEO>(a, blocks, s);
-  }
+template <class R, int GEO>
+const void* kernel_of(const KArgs& a, int which) {
+  return which == 0 ? visit_fn<true, R, GEO>(a.feat_g)
+                    : (which == 1 ? visit_fn<false, R, GEO>(a.feat_l) : short_fn<R, GEO>(a.feat_l));
 }
+// which: 0 photon, 1 e-/e+, 2 short-electron launch
+const void* kernel_for(const KArgs& a, int which) {
+  if (a.geo == 1) return a.precision ? kernel_of<float, 1>(a, which) : kernel_of<double, 1>(a, which);
+  return a.precision ? kernel_of<float, 0>(a, which) : kernel_of<double, 0>(a, which);
+}
+hipError_t launch_kernel(const KArgs& a, int which, uint32_t blocks, hipStream_t s) {
+  KArgs arg = a;
+  void* args[] = {&arg};
+  return hipLaunchKernel(kernel_for(a, which), dim3(blocks), dim3(kBlock), args, which == 0 ? a.lds_g : a.lds_l, s);
+}
+hipError_t launch_short(const KArgs& a, uint32_t blocks, hipStream_t s) { return launch_kernel(a, 2, blocks, s); }
+// one iteration is the short-electron launch, the photon launch and the
+// e-/e+ launch
 hipError_t launch_visit(const KArgs& a, bool photons, uint32_t blocks, hipStream_t s) {
-  if (a.geo == 1) launch_visit_g<1>(a, photons, blocks, s);
-  else launch_visit_g<0>(a, photons, blocks, s);
-  return hipGetLastError();
+  return launch_kernel(a, photons ? 0 : 1, blocks, s);
 }
 hipError_t launch_inject(const KArgs& a, const InjRec* rec, uint32_t n, hipStream_t s) {
   const uint32_t want = (n + kBlock - 1) / kBlock;
@@ -947,24 +1200,17 @@ hipError_t launch_census(const KArgs& a, hipStream_t s) {
 }
 // blocks of each visit kernel that fit on one CU (registers and LDS), for
 // the variants the context launches
-template <class R, int GEO>
-hipError_t visit_occupancy_r(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  const void* fg = visit_fn<true, R, GEO>(a.feat_g);
-  const void* fl = visit_fn<false, R, GEO>(a.feat_l);
-  hipError_t e = hipFuncSetAttribute(fg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_g);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_l);
-  if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_g, fg, kBlock, a.lds_g);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_l, fl, kBlock, a.lds_l);
-}
-hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l) {
-  if (a.geo == 1)
-    return a.precision ? visit_occupancy_r<float, 1>(a, per_cu_g, per_cu_l)
-                       : visit_occupancy_r<double, 1>(a, per_cu_g, per_cu_l);
-  return a.precision ? visit_occupancy_r<float, 0>(a, per_cu_g, per_cu_l)
-                     : visit_occupancy_r<double, 0>(a, per_cu_g, per_cu_l);
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l, int* per_cu_s) {
+  int* out[3] = {per_cu_g, per_cu_l, per_cu_s};
+  for (int w = 0; w < 3; ++w) {
+    const void* f = kernel_for(a, w);
+    const uint32_t lds = w == 0 ? a.lds_g : a.lds_l;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(out[w], f, kBlock, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ems

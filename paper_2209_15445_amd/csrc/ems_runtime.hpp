@@ -18,7 +18,8 @@ hipError_t launch_census(const KArgs& a, hipStream_t s);
 hipError_t launch_atomic_probe(double* cells, uint64_t n_cells, uint64_t n_ops, hipStream_t s);
 hipError_t launch_reset_rows(const KArgs& a, const uint32_t* rows, uint32_t n, hipStream_t s);
 hipError_t launch_gather_rows(const KArgs& a, const uint32_t* rows, uint32_t n, char* out, hipStream_t s);
-hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l);
+hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l, int* per_cu_s);
+hipError_t launch_short(const KArgs& a, uint32_t blocks, hipStream_t s);
 // primaries in device memory: check pass (chk: first invalid, species
 // counts) and stage pass (injection records with ids) of k of them
 hipError_t launch_check_primaries(const KArgs& a, const void* p, uint64_t n, unsigned long long* chk, hipStream_t s);
@@ -37,6 +38,8 @@ struct PrimRec {
 struct Layout {
   uint64_t ctl, tab, zp, smat, bvh, bleaf, bbox, brec, nbr_off, nbr, mat, elem, edep, ledger, live, rows, gather, exits, profile, log, inj, queues, total;
   uint64_t dkey, drow, dchk;  // device enqueue: event keys, ids per row, check words
+  uint64_t squeues;           // short-electron buffers (two of cap_s, spill of cap_p)
+  uint64_t cap_s, cap_p;
   uint64_t cap;
   uint32_t inj_chunk;  // primaries staged per injection launch
 };
@@ -78,7 +81,7 @@ struct ems_ctx {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   KArgs args{};
-  uint32_t blocks_g = 0, blocks_l = 0;
+  uint32_t blocks_g = 0, blocks_l = 0, blocks_s = 0;
   std::vector<uint64_t> row_count;
   std::vector<uint32_t> keys;  // RNG event key per row (host; travels with each injected track)
   // where the batch's primaries came from since the last reset (0: none,

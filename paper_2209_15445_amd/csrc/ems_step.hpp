@@ -28,7 +28,7 @@ constexpr double kInf = __builtin_huge_val();
 // helix in a field, multiple scattering, loss fluctuations, a compound
 // target element, and the per-step records (step log, full ledger, exits,
 // per-event live counters).
-enum : int { kFField = 1, kFMsc = 2, kFFluct = 4, kFCompound = 8, kFRecord = 16, kFAll = 31 };
+enum : int { kFField = 1, kFMsc = 2, kFFluct = 4, kFCompound = 8, kFRecord = 16, kFShort = 32, kFAll = 63 };
 
 // Tables are held in two blocks so each kernel stages only its own: the
 // photon block [mat][3][nodes] (tables 0..2) and the lepton block

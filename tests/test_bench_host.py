@@ -26,8 +26,11 @@ def default_keys():
     assert bench.PHOTON_LAUNCH["slab"] == (32, 24)
     assert '"--workload", default="cal_10GeV_e-_x10k"' in src
     assert '"--mixed-workload", default="cal_10GeV_e-_x100k"' in src
-    return [bench.counter_key("cal_10GeV_e-_x10k", True, 16, 32, 24, 32, 24),
-            bench.counter_key("cal_10GeV_e-_x100k", False, 32, 32, 24, 32, 24)]
+    import paper_2209_15445_amd as E
+    return [bench.counter_key("cal_10GeV_e-_x10k", True, 16, 32, 24, 32, 24,
+                              bench.SHORT_MEV.get(("cal_10GeV_e-_x10k", E.FP64), 0.0)),
+            bench.counter_key("cal_10GeV_e-_x100k", False, 32, 32, 24, 32, 24,
+                              bench.SHORT_MEV.get(("cal_10GeV_e-_x100k", E.MIXED), 0.0))]
 
 
 @pytest.mark.parametrize("table", ["traffic.txt", "atomics.txt"])
@@ -41,6 +44,7 @@ def test_counter_tables_match_the_kernel_sources(table):
 def test_counter_key_names_form_and_launch():
     assert bench.counter_key("w", True, 16, 32, 24, 32, 24) == "w/fp64/v16r32i24pv32pr24"
     assert bench.counter_key("w", False, 32, 8, 0, 1, 0) == "w/mixed/v32r8i0pv1pr0"
+    assert bench.counter_key("w", False, 32, 8, 0, 1, 0, 0.5) == "w/mixed/v32r8i0pv1pr0s0.5"
 
 
 def test_more_than_one_gpu_is_refused():

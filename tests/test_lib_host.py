@@ -63,7 +63,8 @@ def test_config_and_geometry_validation(E):
     for field, val in (("n_bins", 1), ("emin_MeV", -1.0), ("max_events", 0), ("track_capacity", 3),
                        ("max_steps_per_track", 0), ("lin_loss_limit", 1.5), ("precision", 7),
                        ("refill_below", 64), ("interact_min", 65), ("photon_steps_per_visit", 0),
-                       ("photon_refill_below", 64)):
+                       ("photon_refill_below", 64), ("short_electron_MeV", -1.0),
+                       ("short_electron_MeV", float("nan"))):
         c = E.make_config(I.RunConfig(), 4)
         setattr(c, field, val)
         assert _bad(E, c, geo) == E.E_INVALID, field
@@ -79,11 +80,16 @@ def test_config_and_geometry_validation(E):
 
 def test_workspace_grows_with_capacity_and_events(E):
     geo = I.calorimeter()
-    a = E.workspace_bytes(E.make_config(I.RunConfig(), 10, track_capacity=1024), geo)
-    b = E.workspace_bytes(E.make_config(I.RunConfig(), 10, track_capacity=2048), geo)
-    c = E.workspace_bytes(E.make_config(I.RunConfig(), 1000, track_capacity=1024), geo)
+
+    def ws(n, cap, short):
+        return E.workspace_bytes(E.make_config(I.RunConfig(), n, track_capacity=cap, short_electron_MeV=short), geo)
+    a, b, c = ws(10, 1024, 0.0), ws(10, 2048, 0.0), ws(1000, 1024, 0.0)
     assert b - a == 6 * 1024 * 76
     assert c > a and a % 256 == 0
+    # short electrons: two buffers of half the capacity and a spill buffer of
+    # 5/8 of it
+    assert ws(10, 1024, 1.0) - a == (2 * 512 + 640) * 76
+    assert ws(10, 2048, 1.0) - ws(10, 1024, 1.0) == (6 * 1024 + 2 * 512 + 640) * 76
 
 
 def test_invalid_primaries_rejected_by_host_path(E):
