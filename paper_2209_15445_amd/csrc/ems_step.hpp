@@ -148,11 +148,28 @@ EMS_HD R lerp(const R* f, Bin<R> b) {
 
 // largest node j <= jhi with R_j <= r (0 if none; clamped to the last bin),
 // then the exact inverse of the range interpolant.  The loss over one step
-// spans few bins, so the scan starts at the track's own bin and walks down.
+// spans few bins, so the scan starts at the track's own bin and walks down,
+// kWalk nodes a round: the round's loads do not wait on each other (a step
+// towards the end of the range walks down a dozen bins or more).
+constexpr int kWalk = 8;
 template <class R>
 EMS_HD R inverse_range(const StepEnv<R>& e, const R* Rt, R r, int jhi) {
   int lo = jhi > (int)e.nodes - 1 ? (int)e.nodes - 1 : jhi;
-  while (lo > 0 && Rt[lo] > r) --lo;
+  while (lo > 0) {
+    R v[kWalk];
+#pragma unroll
+    for (int k = 0; k < kWalk; ++k) v[k] = Rt[lo > k ? lo - k : 0];
+    // the first of lo, lo-1, ... that is node 0 or holds R_j <= r
+    int d = kWalk;
+#pragma unroll
+    for (int k = kWalk - 1; k >= 0; --k)
+      if (lo <= k || !(v[k] > r)) d = k;
+    if (d < kWalk) {
+      lo -= d;
+      break;
+    }
+    lo -= kWalk;
+  }
   if (lo > (int)e.nodes - 2) lo = (int)e.nodes - 2;
   return xexp(e.lnemin + (R)lo * e.dlog + e.dlog * (r - Rt[lo]) / (Rt[lo + 1] - Rt[lo]));
 }
@@ -404,6 +421,21 @@ EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, b
       const R xa = (lna - e.lnemin) * e.inv_dlog;
       int j = (int)xfloor(xa) + 1;
       j = j < 0 ? 0 : j;
+      // kWalk nodes a round (independent loads), then the rest one by one
+      for (; j + kWalk - 1 <= jb; j += kWalk) {
+        R sv[kWalk];
+#pragma unroll
+        for (int k = 0; k < kWalk; ++k) sv[k] = R(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (i >= p.n) continue;
+          const R* tt = e.T(m, p.tab[i]);
+#pragma unroll
+          for (int k = 0; k < kWalk; ++k) sv[k] += tt[j + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kWalk; ++k) best = sv[k] > best ? sv[k] : best;
+      }
       for (; j <= jb; ++j) {
         R s = R(0);
 #pragma unroll
