@@ -373,12 +373,28 @@ void pack_tables(const TableSet& ts, uint32_t n_mat, std::vector<char>& out) {
   for (uint32_t m = 0; m < n_mat; ++m)
     for (int t = 0; t < kGammaTables; ++t)
       for (uint32_t j = 0; j < ts.nodes; ++j) g.push_back((R)ts.at(m, t, j));
-  for (uint32_t m = 0; m < n_mat; ++m)
+  for (uint32_t m = 0; m < n_mat; ++m) {
     for (int t = kGammaTables; t < kNumTables; ++t)
       for (uint32_t j = 0; j < ts.nodes; ++j) {
         const bool bound = t == tPMem || t == tPMep;
         l.push_back((R)(mixed && bound ? ts.at(m, t, j) * kBoundInflation : ts.at(m, t, j)));
       }
+    // node totals of the discrete processes, as the step code would sum
+    // the packed values (e-: Moller, brems; e+: Bhabha, brems, annihilation)
+    for (uint32_t j = 0; j < ts.nodes; ++j) {
+      R s = R(0);
+      s += (R)ts.at(m, tMoller, j);
+      s += (R)ts.at(m, tBrem, j);
+      l.push_back(s);
+    }
+    for (uint32_t j = 0; j < ts.nodes; ++j) {
+      R s = R(0);
+      s += (R)ts.at(m, tBhabha, j);
+      s += (R)ts.at(m, tBrem, j);
+      s += (R)ts.at(m, tAnnih, j);
+      l.push_back(s);
+    }
+  }
   const size_t gb = (g.size() * sizeof(R) + 7) / 8 * 8;
   out.assign(gb + l.size() * sizeof(R), 0);
   memcpy(out.data(), g.data(), g.size() * sizeof(R));
@@ -454,7 +470,7 @@ ems_status ems_export_tables(ems_ctx* c, double* out, uint64_t n) {
   const uint64_t need = nm * kNumExport * nodes;
   if (!out || n < need) return fail(EMS_E_INVALID, "output buffer too small");
   // the device copy as uploaded: photon block [mat][3][nodes] (padded to 8
-  // bytes), then the lepton block [mat][10][nodes], in the form's type
+  // bytes), then the lepton block [mat][12][nodes], in the form's type
   const uint64_t rb = real_bytes(&c->cfg);
   const uint64_t gbytes = (nm * kGammaTables * nodes * rb + 7) / 8 * 8;
   const uint64_t lbytes = nm * kLeptonTables * nodes * rb;

@@ -32,8 +32,8 @@ enum : int { kFField = 1, kFMsc = 2, kFFluct = 4, kFCompound = 8, kFRecord = 16,
 
 // Tables are held in two blocks so each kernel stages only its own: the
 // photon block [mat][3][nodes] (tables 0..2) and the lepton block
-// [mat][10][nodes] (tables 3..12).
-constexpr int kGammaTables = 3, kLeptonTables = kNumTables - kGammaTables;
+// [mat][12][nodes] (tables 3..14).
+constexpr int kGammaTables = 3, kLeptonTables = kNumDevTables - kGammaTables;
 
 template <class R>
 struct StepEnv {
@@ -421,28 +421,14 @@ EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, b
       const R xa = (lna - e.lnemin) * e.inv_dlog;
       int j = (int)xfloor(xa) + 1;
       j = j < 0 ? 0 : j;
-      // kWalk nodes a round (independent loads), then the rest one by one
+      // the nodes' totals (summed over the processes when the tables were
+      // packed), kWalk nodes a round with independent loads
+      const R* tot = e.T(m, positron ? tSumEp : tSumEm);
       for (; j + kWalk - 1 <= jb; j += kWalk) {
-        R sv[kWalk];
 #pragma unroll
-        for (int k = 0; k < kWalk; ++k) sv[k] = R(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          if (i >= p.n) continue;
-          const R* tt = e.T(m, p.tab[i]);
-#pragma unroll
-          for (int k = 0; k < kWalk; ++k) sv[k] += tt[j + k];
-        }
-#pragma unroll
-        for (int k = 0; k < kWalk; ++k) best = sv[k] > best ? sv[k] : best;
+        for (int k = 0; k < kWalk; ++k) best = tot[j + k] > best ? tot[j + k] : best;
       }
-      for (; j <= jb; ++j) {
-        R s = R(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          if (i < p.n) s += e.T(m, p.tab[i])[j];
-        best = s > best ? s : best;
-      }
+      for (; j <= jb; ++j) best = tot[j] > best ? tot[j] : best;
     }
   }
   const MatRT& mr = e.mat[m];

@@ -19,7 +19,11 @@ enum : int {
   tSep = 7, tRep = 8, tBhabha = 9, tAnnih = 10,
   tPMem = 11,  // running max over nodes <= E_j of the e- discrete total
   tPMep = 12,  // same for e+
-  kNumTables = 13, kNumExport = 11
+  kNumTables = 13, kNumExport = 11,
+  // device layout only (derived when the tables are packed): the e- and e+
+  // discrete totals at the nodes, summed over the processes in the order
+  // and arithmetic type of the step code
+  tSumEm = 13, tSumEp = 14, kNumDevTables = 15
 };
 
 struct MaterialIn {
