@@ -49,6 +49,29 @@ def test_compton_sampler(cal_oracle, oracle_mod, E):
         assert Eg == pytest.approx(E / (1 + E / ME * (1 - cost)), rel=1e-9)
 
 
+@pytest.mark.parametrize("E", [0.1, 2.0, 50.0])
+def test_compton_angles_follow_klein_nishina(cal_oracle, E):
+    """The scattering angle against the Klein-Nishina cross section per unit
+    cos(theta), written here in its angular form (independent of the
+    energy-fraction form the sampler uses): with P = E'/E = 1 / (1 +
+    kappa (1 - cos)), dsigma/dcos is proportional to P^2 (P + 1/P - sin^2)."""
+    s = _samples(cal_oracle, "compton", 0, E)
+    u = _unit(np.array([0.3, -0.2, 0.9]))
+    cost = np.clip(s[:, 3:6] @ u, -1.0, 1.0)
+    kap = E / ME
+
+    def kn(c):
+        P = 1.0 / (1.0 + kap * (1.0 - c))
+        return P * P * (P + 1.0 / P - (1.0 - c * c))
+    assert _chi2(cost, kn, np.linspace(-1.0, 1.0, 41)) > 1e-3
+    # the azimuth about the incoming direction is uniform
+    ref = _unit(np.cross(u, [0.0, 0.0, 1.0]))
+    ref2 = np.cross(u, ref)
+    phi = np.arctan2(s[:, 3:6] @ ref2, s[:, 3:6] @ ref)
+    counts, _ = np.histogram(phi, np.linspace(-math.pi, math.pi, 17))
+    assert stats.chisquare(counts).pvalue > 1e-3
+
+
 @pytest.mark.parametrize("E", [3.0, 40.0, 5000.0])
 def test_pair_sampler(cal_oracle, oracle_mod, E):
     s = _samples(cal_oracle, "pair", 0, E)
