@@ -109,6 +109,65 @@ def test_pair_total_equals_integral_of_differential(oracle_mod, mat, E):
         assert got == pytest.approx(ref, rel=1e-10)
 
 
+def tsai_screening(gamma):
+    """Tsai's fits to the Thomas-Fermi screening functions (Rev. Mod. Phys.
+    46 (1974) 815), in his variable gamma = 100 m_e k / (E E' Z^(1/3)); the
+    oracle's delta = 136 m_e k / (E E' Z^(1/3)) is 1.36 gamma"""
+    p1 = 20.863 - 2 * math.log(1 + (0.55846 * gamma) ** 2) - 4 * (
+        1 - 0.6 * math.exp(-0.9 * gamma) - 0.4 * math.exp(-1.5 * gamma))
+    return p1, p1 - (2 / 3) / (1 + 6.5 * gamma + 6 * gamma * gamma)
+
+
+def coulomb_fc(Z):
+    a2 = (ALPHA * Z) ** 2
+    return a2 * (1 / (1 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 ** 2 - 0.002 * a2 ** 3)
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+def test_pair_screening_at_intermediate_delta_follows_thomas_fermi(oracle_mod, mat):
+    """Between complete screening (delta -> 0) and none, the brace of the
+    pair differential agrees with the same brace written with Tsai's
+    Thomas-Fermi screening functions, in Tsai's arrangement
+    (1 - 4/3 x(1-x)) G1 - 2/3 x(1-x) (phi1 - phi2)/4, to within the 0.6% the
+    two parametrisations of the same model differ by."""
+    Z = mat[0]
+    g_sub = math.log(Z) / 3 + coulomb_fc(Z)
+    seen = []
+    for E in (20.0, 100.0, 1e3, 1e4):
+        for x in (0.5, 0.3, 0.1, 0.03):
+            gamma = 100 * ME * Z ** (-1 / 3) / (E * x * (1 - x))
+            if gamma * 1.36 > 15 or gamma * 1.36 < 0.01:
+                continue
+            p1, p2 = tsai_screening(gamma)
+            g1 = p1 / 4 - g_sub
+            ref = (1 - 4 / 3 * x * (1 - x)) * g1 - 2 / 3 * x * (1 - x) * (p1 - p2) / 4
+            assert oracle_mod.formula("PAIR_F", mat, 0, E, x) == pytest.approx(ref, rel=8e-3), (E, x, gamma)
+            seen.append(gamma * 1.36)
+    assert min(seen) < 0.1 and max(seen) > 5 and any(0.5 < d < 2 for d in seen)
+
+
+@pytest.mark.parametrize("mat", [PB, LAR])
+def test_brems_screening_at_intermediate_delta_follows_thomas_fermi(oracle_mod, mat):
+    """The bremsstrahlung brace against Tsai's nuclear brace with his
+    Thomas-Fermi screening functions, (4/3 - 4/3 y + y^2) G1 +
+    2/3 (1-y) (phi1 - phi2)/4 with y = k / E, over the same range of delta"""
+    Z = mat[0]
+    g_sub = math.log(Z) / 3 + coulomb_fc(Z)
+    seen = []
+    for T in (20.0, 100.0, 1e3, 1e4):
+        et = T + ME
+        for y in (0.9, 0.5, 0.1, 0.01, 1e-3):
+            gamma = 100 * ME * Z ** (-1 / 3) * y / (et * (1 - y))
+            if gamma * 1.36 > 15 or gamma * 1.36 < 0.01:
+                continue
+            p1, p2 = tsai_screening(gamma)
+            g1 = p1 / 4 - g_sub
+            ref = (4 / 3 - 4 / 3 * y + y * y) * g1 + 2 / 3 * (1 - y) * (p1 - p2) / 4
+            assert oracle_mod.formula("BREM_F", mat, 0, T, y * et) == pytest.approx(ref, rel=8e-3), (T, y, gamma)
+            seen.append(gamma * 1.36)
+    assert min(seen) < 0.1 and max(seen) > 5 and any(0.5 < d < 2 for d in seen)
+
+
 # ---------------------------------------------------------------- bremsstrahlung
 @pytest.mark.parametrize("mat,x0_pdg_mm", [(PB, 5.612), (LAR, 140.0)])
 def test_brems_radiation_length(oracle_mod, mat, x0_pdg_mm):
