@@ -148,42 +148,109 @@ EMS_HD R lerp(const R* f, Bin<R> b) {
 
 // largest node j <= jhi with R_j <= r (0 if none; clamped to the last bin),
 // then the exact inverse of the range interpolant.  The loss over one step
-// spans few bins, so the scan starts at the track's own bin and walks down,
-// kWalk nodes a round: the round's loads do not wait on each other (a step
-// towards the end of the range walks down a dozen bins or more).
+// spans few bins, so the scan starts at the track's own bin and reads kWalk
+// nodes below it at once (loads that do not wait on each other).  A step
+// towards the end of the range goes down a dozen bins or more, and a wave
+// waits for its longest scan: past the first kWalk nodes the scan reads
+// every kWalk-th node to find the group of kWalk that holds the answer,
+// then that group, so any scan of up to kWalk * (kWalk + 1) nodes takes
+// three rounds of loads.
 constexpr int kWalk = 8;
+// first k of top, top - 1, ..., top - kWalk + 1 that is node 0 or holds
+// R_j <= r (kWalk if none)
 template <class R>
-EMS_HD R inverse_range(const StepEnv<R>& e, const R* Rt, R r, int jhi) {
+EMS_HD int walk_round(const R* Rt, R r, int top) {
+  R v[kWalk];
+#pragma unroll
+  for (int k = 0; k < kWalk; ++k) v[k] = Rt[top > k ? top - k : 0];
+  int d = kWalk;
+#pragma unroll
+  for (int k = kWalk - 1; k >= 0; --k)
+    if (top <= k || !(v[k] > r)) d = k;
+  return d;
+}
+// (the logarithm of the energy; inverse_range below is its exponential)
+template <class R>
+EMS_HD R inverse_range_ln(const StepEnv<R>& e, const R* Rt, R r, int jhi) {
   int lo = jhi > (int)e.nodes - 1 ? (int)e.nodes - 1 : jhi;
-  while (lo > 0) {
-    R v[kWalk];
-#pragma unroll
-    for (int k = 0; k < kWalk; ++k) v[k] = Rt[lo > k ? lo - k : 0];
-    // the first of lo, lo-1, ... that is node 0 or holds R_j <= r
-    int d = kWalk;
-#pragma unroll
-    for (int k = kWalk - 1; k >= 0; --k)
-      if (lo <= k || !(v[k] > r)) d = k;
+  if (lo > 0) {
+    int d = walk_round(Rt, r, lo);
     if (d < kWalk) {
       lo -= d;
-      break;
+    } else {
+      // nodes lo .. lo - kWalk + 1 all exceed r: look at every kWalk-th
+      // node below (R grows with the node index, so the first one at or
+      // below r bounds the group above it)
+      lo -= kWalk;
+      R v[kWalk];
+#pragma unroll
+      for (int c = 0; c < kWalk; ++c) v[c] = Rt[lo > kWalk * c ? lo - kWalk * c : 0];
+      int g = kWalk;
+#pragma unroll
+      for (int c = kWalk - 1; c >= 0; --c)
+        if (lo <= kWalk * c || !(v[c] > r)) g = c;
+      if (g == 0) {
+        // node lo is node 0 or at or below r
+      } else if (g < kWalk) {
+        // node lo - kWalk g is node 0 or at or below r, node lo - kWalk (g - 1)
+        // and every node above it exceed r: the answer lies in the kWalk
+        // nodes from lo - kWalk (g - 1) - 1 down
+        const int top = lo - kWalk * (g - 1) - 1;
+        lo = top - walk_round(Rt, r, top);
+      } else {
+        // node lo - kWalk (kWalk - 1) > 0 exceeds r: go on below it
+        lo -= kWalk * (kWalk - 1) + 1;
+        while (lo > 0) {
+          d = walk_round(Rt, r, lo);
+          if (d < kWalk) {
+            lo -= d;
+            break;
+          }
+          lo -= kWalk;
+        }
+      }
     }
-    lo -= kWalk;
   }
   if (lo > (int)e.nodes - 2) lo = (int)e.nodes - 2;
-  return xexp(e.lnemin + (R)lo * e.dlog + e.dlog * (r - Rt[lo]) / (Rt[lo + 1] - Rt[lo]));
+  return e.lnemin + (R)lo * e.dlog + e.dlog * (r - Rt[lo]) / (Rt[lo + 1] - Rt[lo]);
+}
+template <class R>
+EMS_HD R inverse_range(const StepEnv<R>& e, const R* Rt, R r, int jhi) {
+  return xexp(inverse_range_ln(e, Rt, r, jhi));
 }
 
 // energy lost over path s by a charged track of kinetic energy T (stopping
-// power S and range Rv at T); FP64 result
+// power S and range Rv at T); FP64 result.  When the remaining energy comes
+// from the range table, *ln_left receives its logarithm (as interpolated,
+// before the subtraction from T) and *have_ln is set.
 template <class R>
-EMS_HD double cont_loss(const StepEnv<R>& e, const R* Rt, int jT, double T, R S, R Rv, double s) {
+EMS_HD double cont_loss(const StepEnv<R>& e, const R* Rt, int jT, double T, R S, R Rv, double s,
+                        R* ln_left = nullptr, bool* have_ln = nullptr) {
   double L;
-  if (s >= (double)Rv) L = T;
-  else if (s < (double)(R(e.lin) * Rv)) L = (double)((R)s * S);
-  else L = T - (double)inverse_range(e, Rt, Rv - (R)s, jT + 1);
-  L = L < 0.0 ? 0.0 : L;
-  return (T - L < e.ecut) ? T : L;
+  bool from_table = false;
+  R x = R(0);
+  if (s >= (double)Rv) {
+    L = T;
+  } else if (s < (double)(R(e.lin) * Rv)) {
+    L = (double)((R)s * S);
+  } else {
+    x = inverse_range_ln(e, Rt, Rv - (R)s, jT + 1);
+    L = T - (double)xexp(x);
+    from_table = true;
+  }
+  if (L < 0.0) {
+    L = 0.0;
+    from_table = false;
+  }
+  if (T - L < e.ecut) {
+    L = T;
+    from_table = false;
+  }
+  if (ln_left) {
+    *ln_left = x;
+    *have_ln = from_table;
+  }
+  return L;
 }
 
 // Distance to the next discrete interaction, -ln(U0)/sigma, or kInf when it
@@ -403,7 +470,7 @@ EMS_HD R total_upper(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, doub
 // the running-maximum table; the values at the thresholds are precomputed
 template <class R>
 EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, bool positron, double a, double b,
-                        Bin<R> bb, R lnb, bool from_cut) {
+                        Bin<R> bb, R lnb, bool from_cut, const R* ln_a = nullptr) {
   R best = total_upper(e, m, p, b, bb);
   const R xb = (lnb - e.lnemin) * e.inv_dlog;
   int jb = (int)xceil(xb) - 1;
@@ -414,7 +481,9 @@ EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, b
     const R v = e.T(m, positron ? tPMep : tPMem)[jb];
     best = v > best ? v : best;
   } else {
-    const R lna = xlog((R)a);
+    // ln a: the range table's inverse already interpolated it when a is
+    // the energy left after s_max (equal up to the rounding of T - (T - a))
+    const R lna = ln_a ? *ln_a : xlog((R)a);
     const R va = total_upper(e, m, p, a, bin_of(e, lna));
     best = va > best ? va : best;
     if (jb >= 0) {
@@ -422,13 +491,16 @@ EMS_HD R thinning_bound(const StepEnv<R>& e, uint32_t m, const LeptonProcs& p, b
       int j = (int)xfloor(xa) + 1;
       j = j < 0 ? 0 : j;
       // the nodes' totals (summed over the processes when the tables were
-      // packed), kWalk nodes a round with independent loads
+      // packed), kWalk nodes a round with independent loads; a round past
+      // jb reads node jb again, which leaves the maximum unchanged
       const R* tot = e.T(m, positron ? tSumEp : tSumEm);
-      for (; j + kWalk - 1 <= jb; j += kWalk) {
+      for (; j <= jb; j += kWalk) {
+        R v[kWalk];
 #pragma unroll
-        for (int k = 0; k < kWalk; ++k) best = tot[j + k] > best ? tot[j + k] : best;
+        for (int k = 0; k < kWalk; ++k) v[k] = tot[j + k <= jb ? j + k : jb];
+#pragma unroll
+        for (int k = 0; k < kWalk; ++k) best = v[k] > best ? v[k] : best;
       }
-      for (; j <= jb; ++j) best = tot[j] > best ? tot[j] : best;
     }
   }
   const MatRT& mr = e.mat[m];
@@ -599,19 +671,27 @@ EMS_HD void lepton_step(const StepEnv<R>& e, bool positron, Trk<R>& t, StepOut<R
   }
   const double smax = (double)scont <= sg ? (double)scont : sg;
   double elo = T, loss_max = 0.0;
+  R ln_lo = R(0);
+  bool have_ln = false;
   if (cont) {
-    loss_max = cont_loss(e, Rt, b.j, T, S, Rv, smax);
+    // (FP64 form only: in the mixed form the longer live range of the
+    // logarithm costs the register-limited kernel more than the log saves)
+    loss_max = sizeof(R) == 8 ? cont_loss(e, Rt, b.j, T, S, Rv, smax, &ln_lo, &have_ln)
+                              : cont_loss(e, Rt, b.j, T, S, Rv, smax);
     elo = T - loss_max;
     const R lin = (R)e.lin * Rv;
     if (smax >= (double)lin) {
       const double e2 = T - (double)(lin * S);
-      elo = e2 < elo ? e2 : elo;
+      if (e2 < elo) {
+        elo = e2;
+        have_ln = false;
+      }
     }
   }
   const bool from_cut = fluct || !(elo > e.ecut);  // with fluctuations: anything down to the cut
   const double a = from_cut ? e.ecut : elo;
   const LeptonProcs pl = lepton_procs(e, positron);
-  const R bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut);
+  const R bound = thinning_bound(e, m, pl, positron, a, T, b, lnT, from_cut, have_ln ? &ln_lo : nullptr);
   const double sphys = phys_distance(r, bound, smax);
   double s;
   uint32_t lim;
