@@ -415,3 +415,25 @@ def test_static_workspace_refuses_a_configuration_beyond_its_size(E):
     bad = E.make_config(cfg, 32, track_capacity=1 << 14)
     bad.abi_version = 1
     assert E.lib().ems_create_static(C.byref(bad), C.byref(gh.g), None, C.byref(h)) == E.E_VERSION
+
+
+def test_range_table_inverse_finds_the_node_of_a_one_by_one_walk(tmp_path):
+    """The strided walk of the range-table inverse (the step code's
+    inverse_range, compiled for the host) against a plain walk down the
+    table, node by node, for walks of every length up to the whole table."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "step_scans_check"
+    subprocess.run([hipcc, "-O1", "-std=c++17", "-I", os.path.join(root, "paper_2209_15445_amd", "csrc"),
+                    os.path.join(root, "tests", "step_scans_check.cpp"), "-o", str(exe)],
+                   check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    lines = r.stdout.strip().split("\n")
+    assert r.returncode == 0, r.stdout
+    assert lines[-2].startswith("double:") and lines[-1].startswith("float:")
+    for line in lines[-2:]:
+        assert line.endswith(" 0 mismatches") and int(line.split()[1]) > 4_000_000
