@@ -5,8 +5,8 @@ records give the same step records bit for bit (and tallies equal up to
 the order of their atomic sums); deposits copied to device memory equal
 those copied to the host.  Also: several groups of 1024
 records with rows spread over them, two enqueues in a row, invalid records
-(all or nothing), a batch mixing host and device primaries, pointers that
-are not device memory."""
+(all or nothing), an empty batch, a batch mixing host and device primaries,
+pointers that are not device memory."""
 import ctypes as C
 
 import numpy as np
@@ -177,11 +177,14 @@ def test_invalid_device_primaries_are_all_or_nothing(E):
     assert E.lib().ems_enqueue_device(t._h, C.c_void_p(d.data_ptr()), 1 << 39) == E.E_INVALID
     out = np.zeros((32, t.n_slabs))
     assert E.lib().ems_read_edep_device(t._h, 0, 32, out.ctypes.data_as(C.c_void_p)) == E.E_INVALID
+    # an empty batch is accepted and adds nothing
+    t.enqueue_device(on_device(prim[:0]))
     # nothing of the refused calls reached the queues
     t.enqueue_device(d)
     t.run()
     got = torch.zeros((32, t.n_slabs), dtype=torch.float64, device="cuda")
     t.edep_device(got)
+    t.edep_device(torch.zeros((0, t.n_slabs), dtype=torch.float64, device="cuda"), first=32)
     got = got.cpu().numpy()
     t.close()
     c2 = E.make_config(cfg, 32, track_capacity=1 << 16)
