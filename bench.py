@@ -355,15 +355,18 @@ def atomics_report(leg, workload, peak):
 
 def kernel_source_digest(csrc=None):
     """SHA-256 over the sources the visit kernels are built from
-    (ems_kernels.hip and the headers it includes, directly or through other
-    headers) with their comments and blank space removed: counter figures
-    are valid only for the code they were measured on, and neither a comment
-    nor a host-only file changes that code."""
+    (ems_kernels.hip, ems_kernels_slab_f32.hip and the headers they include,
+    directly or through other headers) with their comments and blank space
+    removed, and over the compiler flags of the FP32 slab-stack kernels:
+    counter figures are valid only for the code they were measured on, and
+    neither a comment nor a host-only file changes that code."""
     import hashlib
     import re
+    from paper_2209_15445_amd import build as ems_build
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_2209_15445_amd", "csrc")
-    used, todo = set(), ["ems_kernels.hip"]
+    h.update(" ".join(ems_build.SLAB_F32_FLAGS).encode() + b"\0")
+    used, todo = set(), ["ems_kernels.hip", ems_build.SLAB_F32_SOURCE]
     while todo:
         name = todo.pop()
         if name in used or not os.path.exists(os.path.join(csrc, name)):

@@ -1002,6 +1002,7 @@ __global__ __launch_bounds__(kBlock, (short_waves<R, GEO, F>())) void k_short(KA
   if (__lane_id() == 0 && c) atomicAdd(&ctl->commits, c);
 }
 
+#ifndef EMS_SLAB_F32_TU
 // Zero `words` 8-byte words at p and then `ntail` single bytes at tail, with
 // plain vector stores (grid-stride).  The library clears its device memory
 // with this kernel instead of memset nodes, which a caller capturing the
@@ -1110,6 +1111,8 @@ __global__ void k_census(KArgs a) {
   }
 }
 
+#endif  // EMS_SLAB_F32_TU
+
 // Kernel variants: the optional parts each kernel is built with.  The
 // e-/e+ kernel of a slab stack comes without any, with the field and the
 // records (mixed-species runs in a field, the offload server) or with all;
@@ -1145,10 +1148,17 @@ const void* kernel_of(const KArgs& a, int which) {
   return which == 0 ? visit_fn<true, R, GEO>(a.feat_g)
                     : (which == 1 ? visit_fn<false, R, GEO>(a.feat_l) : short_fn<R, GEO>(a.feat_l));
 }
+#ifdef EMS_SLAB_F32_TU
+const void* kernel_of_slab_f32(const KArgs& a, int which) { return kernel_of<float, 0>(a, which); }
+#else
+// The mixed-form kernels of the slab stack come from a translation unit of
+// their own (ems_kernels_slab_f32.hip), built with another instruction
+// scheduler (see build.py).
+const void* kernel_of_slab_f32(const KArgs& a, int which);
 // which: 0 photon, 1 e-/e+, 2 short-electron launch
 const void* kernel_for(const KArgs& a, int which) {
   if (a.geo == 1) return a.precision ? kernel_of<float, 1>(a, which) : kernel_of<double, 1>(a, which);
-  return a.precision ? kernel_of<float, 0>(a, which) : kernel_of<double, 0>(a, which);
+  return a.precision ? kernel_of_slab_f32(a, which) : kernel_of<double, 0>(a, which);
 }
 hipError_t launch_kernel(const KArgs& a, int which, uint32_t blocks, hipStream_t s) {
   KArgs arg = a;
@@ -1212,5 +1222,6 @@ hipError_t visit_occupancy(const KArgs& a, int* per_cu_g, int* per_cu_l, int* pe
   }
   return hipSuccess;
 }
+#endif  // EMS_SLAB_F32_TU
 
 }  // namespace ems
