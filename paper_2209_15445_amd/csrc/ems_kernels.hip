@@ -412,8 +412,17 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 #ifndef EMS_WAVES_BOX_F32_LEPTON
 #define EMS_WAVES_BOX_F32_LEPTON EMS_WAVES_F32_LEPTON
 #endif
-template <bool PHOTONS, class R, int GEO>
+// The FP32 e-/e+ slab kernels with optional parts (every such variant has
+// the field part) need more registers: at 3 waves they spill 100-176 bytes
+// per lane, at 2 they spill none.  With 2: the mixed species in a field
+// +4.3%, PbWO4 +3.5%, scattering and fluctuations +4.2%, the offload server
+// +6.6% (mixed form); the beam's kernel (no optional parts) keeps 3.
+#ifndef EMS_WAVES_F32_LEPTON_FIELD
+#define EMS_WAVES_F32_LEPTON_FIELD 2
+#endif
+template <bool PHOTONS, class R, int GEO, int F = 0>
 constexpr int visit_waves() {
+  if (!PHOTONS && GEO == 0 && sizeof(R) == 4 && (F & kFField) != 0) return EMS_WAVES_F32_LEPTON_FIELD;
   if (GEO == 1)
     return sizeof(R) == 8 ? (PHOTONS ? EMS_WAVES_BOX_F64_PHOTON : EMS_WAVES_BOX_F64_LEPTON)
                           : (PHOTONS ? EMS_WAVES_BOX_F32_PHOTON : EMS_WAVES_BOX_F32_LEPTON);
@@ -421,7 +430,7 @@ constexpr int visit_waves() {
                         : (PHOTONS ? EMS_WAVES_F32_PHOTON : EMS_WAVES_F32_LEPTON);
 }
 template <bool PHOTONS, class R, int GEO, int F>
-__global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO>())) void k_visit(KArgs a) {
+__global__ __launch_bounds__(kBlock, (visit_waves<PHOTONS, R, GEO, F>())) void k_visit(KArgs a) {
   extern __shared__ double lds_words[];
   char* lds = reinterpret_cast<char*>(lds_words);
   Ctl* ctl = a.ctl;
