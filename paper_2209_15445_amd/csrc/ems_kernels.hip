@@ -398,8 +398,9 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 // the world volume's boundary distances computed for many lanes at once,
 // the photon kernels gain more from running without register spills (FP64
 // at 2 waves: 168 VGPRs and 132 spilled at 3; towers photon launch 2.85 ms
-// instead of 3.44 ms; FP32 at 3: 2.58 ms instead of 2.90 ms at 4).  The
-// e-/e+ kernels keep the slab settings (more waves made them slower).
+// instead of 3.44 ms; FP32 at 3: 2.58 ms instead of 2.90 ms at 4).  More
+// waves made the e-/e+ kernels slower; the FP32 one runs at 2 rather than 3
+// (towers e-/e+ launch 1.98 ms instead of 2.11 ms; photons at 2: slower).
 #ifndef EMS_WAVES_BOX_F64_PHOTON
 #define EMS_WAVES_BOX_F64_PHOTON 2
 #endif
@@ -410,7 +411,7 @@ __device__ StepEnv<R> stage(const KArgs& a, char* lds_bytes, bool photons) {
 #define EMS_WAVES_BOX_F32_PHOTON 3
 #endif
 #ifndef EMS_WAVES_BOX_F32_LEPTON
-#define EMS_WAVES_BOX_F32_LEPTON EMS_WAVES_F32_LEPTON
+#define EMS_WAVES_BOX_F32_LEPTON 2
 #endif
 // The FP32 e-/e+ slab kernels with optional parts (every such variant has
 // the field part) need more registers: at 3 waves they spill 100-176 bytes
