@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--serve-capacity", type=int, default=1 << 24)
     ap.add_argument("--serve-admit-gib", type=int, default=8)
     ap.add_argument("--serve-steps-per-launch", type=int, default=1, help="iterations between host polls")
-    ap.add_argument("--serve-steps-per-visit", type=int, default=16)
+    ap.add_argument("--serve-steps-per-visit", type=int, default=12)
     ap.add_argument("--serve-photon-steps-per-visit", type=int, default=32)
     ap.add_argument("--serve-photon-refill-below", type=int, default=24)
     ap.add_argument("--no-fp64-serve", action="store_true")
